@@ -52,6 +52,15 @@ DEFAULT_L = 3
 CONVS = ((0, 0, 0, +1), (1, 1, 0, -1), (1, 0, 1, +1), (0, 1, 1, +1))
 
 
+def _cplx(re, im):
+    """Complex array with exactly these real and imaginary parts (building it
+    as re + 1j*im would add a zero product and drop the sign of zeros)."""
+    out = np.empty(np.shape(re), dtype=np.complex128)
+    out.real = re
+    out.imag = im
+    return out
+
+
 def conv_length(n: int) -> int:
     """Bluestein cyclic-convolution length: smallest power of two >= 2n-1
     (Sec. 3.2, N >= 2n - 1)."""
@@ -200,7 +209,7 @@ def forward_trace(x, K: int | None = DEFAULT_K, L: int = DEFAULT_L, plan: Kernel
     tr["status"] = status
     if status != oz.STATUS_OK:
         nan = np.full(n, np.nan)
-        tr["y"] = nan + 1j * nan
+        tr["y"] = _cplx(nan, nan)
         tr["slices"] = [[], []]
         tr["groups"] = [[] for _ in CONVS]
         return tr
@@ -244,7 +253,7 @@ def forward_trace(x, K: int | None = DEFAULT_K, L: int = DEFAULT_L, plan: Kernel
         yp.append(out)
     tr["ypr"], tr["ypi"] = yp
     yr, yi = postmultiply(yp[0], yp[1], plan.c, plan.s)
-    tr["y"] = yr + 1j * yi
+    tr["y"] = _cplx(yr, yi)
     return tr
 
 
@@ -255,7 +264,7 @@ def fft(x, K: int | None = DEFAULT_K, L: int = DEFAULT_L, plan: KernelPlan | Non
 
 def _conj(v):
     v = np.asarray(v, dtype=np.complex128)
-    return v.real + 1j * (-v.imag)
+    return _cplx(v.real, -v.imag)
 
 
 def adjoint(g, K: int | None = DEFAULT_K, L: int = DEFAULT_L, plan: KernelPlan | None = None):

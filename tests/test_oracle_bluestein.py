@@ -267,3 +267,17 @@ def test_nonfinite_and_range_status():
     z = np.zeros(16, complex)
     y = bl.fft(z)
     assert np.all(y == 0)
+
+
+def test_signed_zeros_follow_ieee_products():
+    """A zero input gives y' = +0; y = y' (.) w is formed by IEEE products and
+    sums, so the output's zeros carry the signs those operations give."""
+    n = 100
+    kp = bl.KernelPlan(n, 3, 3)
+    y = bl.fft(np.zeros(n, complex), plan=kp)
+    zr, zi = np.zeros(n), np.zeros(n)
+    want_r = zr * kp.c + zi * kp.s
+    want_i = zi * kp.c - zr * kp.s
+    assert np.array_equal(np.signbit(y.real), np.signbit(want_r))
+    assert np.array_equal(np.signbit(y.imag), np.signbit(want_i))
+    assert np.any(np.signbit(y.imag))
