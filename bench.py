@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput of the FP64-accurate DFT (Bluestein + Ozaki slices + two-prime
+32-bit NTT convolution) on one MI355X.
+
+One step = one forward execution of the whole path (premultiply, split,
+forward NTTs, NTT-domain multiply-accumulate, inverse NTTs, CRT,
+recombination, postmultiply) over a batch of 8 transforms of length n = 2^18
+whose magnitudes are log-uniform in [2^-30, 2^30] with uniform phase
+(workload `wide_256k`, seed 0), inputs resident in HBM.  The metric is
+GFLOP/s in the 5 n log2 n convention.
+
+Prints one JSON line.  Besides the headline (batched form, HIP graph replay)
+it reports the plain form on the same input, the relative l2 error against
+a long-double DFT, per-stage device times, the roofline of the dominant
+kernel and the CPU oracle timed on a bounded sample.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FP64-accurate FFT GFLOP/s (5n·log2n) at n=2^18, batched vs plain; rel. error"
+HBM_PEAK_GBS = 8000.0
+
+# stage id -> kernel launched by that stage (uniform batch: one launch per stage)
+STAGE_KERNELS = {4: "k_fwd_cols", 5: "k_fwd_rows", 6: "k_inv_rows", 7: "k_inv_cols", 8: "k_recombine"}
+
+
+def algorithmic_bytes(infos, K):
+    """Algorithmic HBM bytes per launch of each pass kernel, from the actual
+    slice and group counts (each value read once and written once)."""
+    out = {4: 0, 5: 0, 6: 0, 7: 0, 8: 0}
+    kernels_seen = set()
+    for d in infos:
+        n, N = d["n"], d["N"]
+        vecs = 2 * (d["kx"][0] + d["kx"][1])          # forward NTT vectors (part, slice, prime)
+        grp = 2 * sum(d["ngroups"])                    # inverse NTT vectors (group, prime)
+        out[4] += vecs * (4 * n + 4 * N)               # read the n non-zero inputs, write N
+        out[5] += vecs * 8 * N                         # read + write N
+        out[6] += vecs * 4 * N + grp * 4 * N           # read the slice spectra, write the group rows
+        key = (n, N)
+        if key not in kernels_seen:                    # kernel spectra + Shoup companions, once per length
+            kernels_seen.add(key)
+            out[6] += 2 * (d["kw"][0] + d["kw"][1]) * 8 * N
+        out[7] += grp * (4 * N + 4 * n)                # read N, write the first n
+        out[8] += grp * 4 * n + 16 * n + 16 * n        # residues + chirp in, y out
+    return out
+
+
+def time_events(torch, fn, reps):
+    s = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(s)
+    fn(reps)
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def cpu_baseline(x0, n, budget_s):
+    """The oracle, as it is, on one transform of the same workload."""
+    from oracle import bluestein as bl
+    plan = bl.KernelPlan(n, 3, 3)            # input independent, not timed (as on the GPU)
+    t0 = time.perf_counter()
+    bl.forward_trace(x0, 3, 3, plan)
+    dt = time.perf_counter() - t0
+    return {"value": round(5.0 * n * math.log2(n) / dt / 1e9, 6), "unit": "GFLOP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"1 transform of the same workload (n={n}), K=3, L=3, kernel plan precomputed; "
+                      f"{dt:.1f} s wall on the host, single-threaded numpy/Python-int oracle",
+            "seconds": round(dt, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1 << 18)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--stage-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(transforms shard by batch with no communication; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2603_29129_amd as oz
+    import workloads as wl
+    from oracle import reference as ref
+
+    n, B = args.n, args.batch
+    print(f"# bench: n={n} batch={B} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    x = wl.wide_256k(seed=0, batch=B, n=n)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xd)
+    flops = B * 5.0 * n * math.log2(n)
+
+    plan = oz.Plan(n, B, mode="batched")
+    for _ in range(args.warmup):
+        plan.forward(xd, out)
+    torch.cuda.synchronize()
+
+    def run(k):
+        for _ in range(k):
+            plan.forward(xd, out)
+
+    ms = time_events(torch, run, args.steps)
+    value = flops / (ms * 1e-3) / 1e9
+    print(f"# batched: {ms:.3f} ms/step, {value:.1f} GFLOP/s", file=sys.stderr, flush=True)
+
+    y = out.cpu().numpy()
+    infos = [plan.transform_info(b) for b in range(B)]
+    rel = ref.rel_l2_error(y[0], ref.dft_longdouble(x[0]))
+    maxrel = ref.max_rel_error(y[0], ref.dft_longdouble(x[0]))
+
+    # per-stage device times (same buffers, one launch of each stage per rep)
+    stage_ms = {}
+    for st in (1, 2, 4, 5, 6, 7, 8):
+        stage_ms[st] = time_events(torch, lambda k, st=st: plan.profile_stage(st, k), args.stage_reps)
+    plan.forward(xd, out)             # restore a consistent state
+    torch.cuda.synchronize()
+    print("# stages (ms): " + ", ".join(f"{k}:{v:.3f}" for k, v in stage_ms.items()), file=sys.stderr, flush=True)
+
+    alg = algorithmic_bytes(infos, 3)
+    dom = max(STAGE_KERNELS, key=lambda s: stage_ms[s])
+    achieved = alg[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": STAGE_KERNELS[dom], "kernel_ms": round(stage_ms[dom], 4),
+                "algorithmic_bytes_per_launch": alg[dom]}
+    per_kernel = {STAGE_KERNELS[s]: {"ms": round(stage_ms[s], 4),
+                                     "alg_GBps": round(alg[s] / (stage_ms[s] * 1e-3) / 1e9, 1)}
+                  for s in STAGE_KERNELS}
+
+    plain = None
+    if not args.no_plain:
+        pplan = oz.Plan(n, B, mode="plain")
+        pout = torch.empty_like(xd)
+        pplan.forward(xd, pout)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            pplan.forward(xd, pout)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t0) * 1e3 / args.plain_steps
+        same = bool(torch.equal(pout.view(torch.float64), out.view(torch.float64)))
+        plain = {"ms_per_step": round(pms, 3), "value": round(flops / (pms * 1e-3) / 1e9, 2),
+                 "batched_over_plain": round(pms / ms, 2), "bit_identical_to_batched": same,
+                 "timing": "host wall clock (the plain form synchronises the host)"}
+        pplan.close()
+        print(f"# plain: {pms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 25, dtype=torch.float64, device="cuda").fill_(1.0)
+        for _ in range(5):
+            a.clone()
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(x[0], n, 30.0)
+        print(f"# cpu oracle: {cpu['seconds']} s", file=sys.stderr, flush=True)
+
+    counts = infos[0]
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "dtype_note": "32-bit modular integer NTT/CRT; binary64 chirp, split and recombination",
+        "data": "synthetic",
+        "config": {"workload": "wide_256k: 8 transforms, n=2^18 (N=2^19), |x| log-uniform in [2^-30,2^30], "
+                               "uniform phase, seed 0; batched form (HIP graph replay)",
+                   "n": n, "batch": B, "K": 3, "L": 3, "parallelism": "single GPU"},
+        "rel_l2_error": rel,
+        "max_rel_error": maxrel,
+        "ntt_counts": {"forward_runtime": counts["forward_runtime"], "inverse": counts["inverse"],
+                       "forward_offline": counts["forward_offline"]},
+        "plain": plain,
+        "stages_ms": {str(k): round(v, 4) for k, v in stage_ms.items()},
+        "per_kernel": per_kernel,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * fft_ozaki.h -- C ABI of an FP64-accurate discrete Fourier transform for
+ * AMD Instinct MI355X (gfx950), computed as in Kawakami & Takahashi,
+ * "Computing FFTs at Target Precision Using Lower-Precision FFTs":
+ *
+ *   y = DFT(x),  y(k) = sum_j x(j) w_n^{jk},  w_n = exp(-2 pi i / n)
+ *   (Sec. 3.2, Eq. dft; the inverse carries 1/n, Eq. idft),
+ *
+ * by Bluestein's algorithm (Sec. 3.2, Alg. 1) whose cyclic convolution is
+ * split into integer slices by the Ozaki scheme (Alg. 3, with the split cap K
+ * of Sec. 4.4), convolved exactly by 32-bit NTTs modulo p0 = 2130706433 and
+ * p1 = 2113929217 with NTT-domain accumulation of at most L products
+ * (Alg. 8), rebuilt by Garner's CRT (Sec. 3.3) and recombined to binary64.
+ * The four real convolutions of the complex convolution share their splits
+ * (Sec. 4.5) and the kernel's splits and NTTs are computed once per plan
+ * (Sec. 4.5, precomputed offline).  Outputs are deterministic: the integer
+ * stages are exact and every binary64 operation has a fixed order; the
+ * recombination is an exact sum rounded once.
+ *
+ * Conventions
+ * -----------
+ *  * Every function returns an int status: FFT_OZAKI_OK (0) or a negative
+ *    FFT_OZAKI_ERR_* code.  fft_ozaki_error_string() describes a code;
+ *    fft_ozaki_last_error_message() gives the detail of the last failure on
+ *    the calling thread.
+ *  * Complex data are arrays of interleaved binary64 pairs (re, im), i.e.
+ *    double2 / complex128, 16-byte aligned, in DEVICE memory of the device
+ *    that was current when the plan was created.  Transform i occupies
+ *    elements [off_i, off_i + n_i) where off_i is the sum of the preceding
+ *    lengths; a uniform batch is therefore a row-major [batch][n] array.
+ *    in == out is allowed.
+ *  * A plan owns all device workspace (chirps, twiddles, kernel NTTs, slice
+ *    and accumulator buffers).  The caller owns in, out and the stream.
+ *  * `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Executions are asynchronous in the batched mode and synchronous (the
+ *    host waits on `stream`) in the plain mode.  One execution may be in
+ *    flight per plan.
+ *  * Data-dependent faults are not returned by the call: a transform whose
+ *    premultiplied input contains NaN/Inf (status bit 1) or whose largest
+ *    value lies outside the supported exponent range, roughly 2^-1000 ..
+ *    2^990 (status bit 2), has its output set to NaN; read the per-transform
+ *    status with fft_ozaki_query_transform() after synchronising.
+ */
+#ifndef FFT_OZAKI_H
+#define FFT_OZAKI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fft_ozaki_plan_s* fft_ozaki_plan_t;
+
+enum {
+  FFT_OZAKI_OK = 0,
+  FFT_OZAKI_ERR_INVALID = -1,      /* bad argument (sizes, K, L, pointers, direction) */
+  FFT_OZAKI_ERR_NOMEM = -2,        /* device or host allocation failed */
+  FFT_OZAKI_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed */
+  FFT_OZAKI_ERR_UNSUPPORTED = -4   /* valid request the library cannot serve */
+};
+
+enum {
+  FFT_OZAKI_FORWARD = 0,           /* y = DFT(x) */
+  FFT_OZAKI_INVERSE = 1,           /* y = conj(DFT(conj x)) / n  (= DFT^{-1}, Eq. idft) */
+  FFT_OZAKI_ADJOINT = 2            /* y = conj(DFT(conj x))      (= DFT^H) */
+};
+
+enum {
+  FFT_OZAKI_MODE_PLAIN = 0,        /* host-driven: one transform at a time, one kernel launch per NTT */
+  FFT_OZAKI_MODE_BATCHED = 1       /* all transforms per launch, device-side schedule, HIP graph replay */
+};
+
+/* Plan options.  K: cap on slices per vector (Sec. 4.4), 1..8, default 3.
+ * L: NTT-domain accumulation bound (Sec. 4.4, Alg. 8), >= 1, default 3.
+ * mode: FFT_OZAKI_MODE_*, default batched.  autotune: 1 = time the NTT tile
+ * shapes at plan time and keep the fastest (results are identical for every
+ * shape); tune_cache: optional file path where tuned shapes are stored and
+ * looked up (NULL = none). */
+typedef struct {
+  int K;
+  int L;
+  int mode;
+  int autotune;
+  const char* tune_cache;
+} fft_ozaki_options;
+
+/* Fills *opt with the defaults (K = 3, L = 3, batched, no autotune). */
+int fft_ozaki_default_options(fft_ozaki_options* opt);
+
+/* Plan `batch` transforms of length n (uniform batch) with default options.
+ * n >= 1 with convolution length N = 2^ceil(log2(2n-1)) <= 2^24; batch >= 1. */
+int fft_ozaki_plan(fft_ozaki_plan_t* plan, int64_t n, int64_t batch);
+
+/* Plan `count` transforms of the given (possibly different) lengths.
+ * lengths: host array of `count` values, each as for fft_ozaki_plan.
+ * opt may be NULL for the defaults.  Fails with FFT_OZAKI_ERR_INVALID when
+ * the split width alpha = floor((log2(p0 p1 / 2) - log2(L n)) / 2) (Sec. 4.4)
+ * would be < 1 or when L n 4^alpha > (p0 p1 - 1) / 2. */
+int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t count,
+                      const fft_ozaki_options* opt);
+
+/* Execute the planned transforms in `direction` on device arrays in -> out. */
+int fft_ozaki_execute(fft_ozaki_plan_t plan, const void* in, void* out, int direction, void* stream);
+/* = fft_ozaki_execute(plan, in, out, FFT_OZAKI_FORWARD, stream) */
+int fft_ozaki_forward(fft_ozaki_plan_t plan, const void* in, void* out, void* stream);
+/* = fft_ozaki_execute(plan, in, out, FFT_OZAKI_INVERSE, stream) */
+int fft_ozaki_inverse(fft_ozaki_plan_t plan, const void* in, void* out, void* stream);
+
+/* Plan-level facts. */
+typedef struct {
+  int64_t count;                   /* number of transforms */
+  int64_t total_length;            /* sum of the lengths */
+  int K, L, mode, num_length_classes;
+  int64_t workspace_bytes;         /* device memory held by the plan */
+} fft_ozaki_info;
+int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info);
+
+/* Per-transform facts.  The data-dependent fields describe the last
+ * execution and are valid once it has completed (the call synchronises the
+ * device).  forward_runtime / inverse count the 32-bit NTTs performed per
+ * execution, forward_offline those done once at plan time (Sec. 4.5). */
+typedef struct {
+  int64_t n, N;
+  int alpha;
+  int status;                      /* bit 1: non-finite input, bit 2: exponent range */
+  int kx[2];                       /* slices of Re x', Im x' */
+  int Ex[2][8];                    /* their exponents E = ceil(log2 max|r|) */
+  int kw[2];                       /* slices of Re w*, Im w* */
+  int Ew[2][8];
+  int ngroups[4];                  /* Alg. 8 groups of ReRe, ImIm, ImRe, ReIm */
+  int forward_runtime, forward_offline, inverse;
+  int ntt_log2N1;                  /* NTT-domain layout: see fft_ozaki_ntt */
+} fft_ozaki_transform_info;
+int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_transform_info* info);
+
+/* Test hook: copy an intermediate buffer of transform `index` of the last
+ * execution to host memory (synchronises the device).  Stages:
+ *   1  x' = x (.) w                          double2[n]
+ *   2  forward NTTs of the x' slices         uint32[2][K][2][N]  (part, slice, prime; NTT-domain order)
+ *   3  inverse NTT outputs per group         uint32[4*K*K][2][n] (slot = conv*K*K + group, prime)
+ *   4  kernel NTTs times N^{-1}              uint32[2][K][2][N]
+ *   5  chirp (cos, sin)                      double2[n]
+ * `bytes` must be at least the stage size (FFT_OZAKI_ERR_INVALID otherwise);
+ * the size is returned through *needed when not NULL. */
+int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* host_dst, size_t bytes,
+                         size_t* needed);
+
+/* Measurement hook: enqueue `reps` repetitions of one stage of the batched
+ * schedule for all transforms of the plan, on `stream`, reusing the buffers
+ * and the in/out pointers of the plan's last execution (they must still be
+ * valid).  Stages: 1 split (premultiply, maxima, extraction passes),
+ * 2 Alg. 8 group tables, 3 forward NTTs (both passes), 4 forward column
+ * pass, 5 forward row pass, 6 inverse row pass with the fused NTT-domain
+ * multiply-accumulate (for N <= 4096: the whole inverse), 7 inverse column
+ * pass, 8 CRT/recombination/postmultiply.  Stages 3-5 transform the slice
+ * buffers again in place, so intermediates read with fft_ozaki_debug_dump
+ * afterwards are not those of the last execution.  Batched plans only. */
+int fft_ozaki_profile_stage(fft_ozaki_plan_t plan, int stage, int reps, void* stream);
+
+/* Release the plan and its device memory. */
+int fft_ozaki_destroy(fft_ozaki_plan_t plan);
+
+/* Static description of a status code; never NULL. */
+const char* fft_ozaki_error_string(int status);
+/* Detail of the last failing call on this thread ("" if none). */
+const char* fft_ozaki_last_error_message(void);
+
+/* The library's 32-bit NTT (Sec. 3.3, Eq. ntt / intt) on `count` contiguous
+ * device vectors of length N = 2^log2N (1 <= N <= 2^24) modulo p0 (prime 0)
+ * or p1 (prime 1), in place.  The forward transform reads natural order and
+ * writes the NTT-domain order: position i1 * N2 + i2 holds X(br(i1) + N1 br(i2))
+ * with N1 = 2^ntt_log2N1 (from fft_ozaki_ntt_layout), N2 = N / N1 and br the
+ * bit reversal on log2 N1 resp. log2 N2 bits.  The inverse reads that order
+ * and writes natural order including the factor N^{-1}.  Inputs must be
+ * residues in [0, p). */
+int fft_ozaki_ntt(int prime, int log2N, int64_t count, void* data, int inverse, void* stream);
+int fft_ozaki_ntt_layout(int log2N, int* log2N1);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFT_OZAKI_H */

@@ -1,0 +1,46 @@
+"""Builds the HIP library libfft_ozaki.so for gfx950 in the package folder.
+
+    python -m paper_2603_29129_amd.build_lib
+"""
+
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB = os.path.join(PKG, "libfft_ozaki.so")
+SOURCES = ["ntt_kernels.hip", "split_kernels.hip", "recombine_kernels.hip", "plan.hip"]
+
+FLAGS = [
+    "-O3",
+    "--offload-arch=gfx950",
+    "-fPIC",
+    "-shared",
+    "-std=c++17",
+    # every binary64 operation rounds on its own; fused forms are written explicitly
+    "-ffp-contract=off",
+    # never emit packed fp32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    srcs = [os.path.join(PKG, "csrc", s) for s in SOURCES]
+    tmp = LIB + ".tmp"
+    cmd = [hipcc, *FLAGS, "-I" + os.path.join(ROOT, "include"), "-o", tmp, *srcs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building libfft_ozaki.so")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,87 @@
+// Internal interfaces between the plan/execution layer and the kernel files.
+#pragma once
+
+#include "common.h"
+
+namespace fo {
+
+constexpr int NTT_THREADS = 256;
+
+// Geometry of the NTT of length N = 2^logN: one workgroup block NTT when
+// logN <= LOG2_BLOCK_MAX, else two passes N = N1 * N2 (columns of length N1
+// strided by N2, then contiguous rows of length N2).  The NTT-domain order is
+// position i1 * N2 + i2 holding X[br(i1) + N1 * br(i2)] (br = bit reversal
+// over log2 N1 resp. log2 N2 bits); for the block case N1 = N, N2 = 1.
+struct NttGeom {
+  int logN, m1, m2;      // N1 = 2^m1, N2 = 2^m2
+  int lc;                // log2 of the columns per workgroup (column pass)
+  int lrows;             // log2 of the rows per workgroup (row pass)
+  bool two_pass() const { return m2 > 0; }
+};
+NttGeom ntt_geom(int logN, int lc_override = -1, int lrows_override = -1);
+
+struct TwTables {
+  TwBlock blk;
+  // step tables per logN (index logN), nullptr when unused
+  TwStep step[MAX_LOG2_N + 1];
+};
+
+// Host-side table creation (plan time).
+int build_block_twiddles(TwBlock* out, void** allocs);
+int build_step_twiddles(int logN, TwStep* out, void** allocs);
+
+// --- NTT launches -----------------------------------------------------------
+// Standalone transforms of `count` contiguous vectors (natural order in for the
+// forward transform, NTT-domain order out; the inverse takes NTT-domain order
+// and returns natural order multiplied by N^{-1}).
+hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool inverse,
+                                 const NttGeom& g, const TwBlock& tb, const TwStep& ts, hipStream_t s);
+
+// Pipeline: forward NTTs of the slice residues of the listed transforms
+// (vector index vi = (part*K + k)*2 + prime; only k < kx[part] are done).
+// valid_full: the vectors are fully populated (kernel slices) instead of
+// holding zeros beyond n.  vi_lo/vi_hi restrict the vectors (plain form).
+hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count,
+                               int K, bool valid_full, int vi_lo, int vi_hi, const NttGeom& g,
+                               const TwBlock& tb, const TwStep& st, hipStream_t s);
+
+// Pipeline: NTT-domain multiply-accumulate of every Alg. 8 group followed by
+// the inverse NTT; writes the first n outputs of each group and prime to the
+// compact buffer.  slot_lo/slot_hi restrict the groups (plain form).
+hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts,
+                               const KernelDesc* kd, const int* tlist, int count, int K,
+                               int slot_lo, int slot_hi, const NttGeom& g, const TwBlock& tb,
+                               const TwStep& st, hipStream_t s);
+
+// Single passes of the above (measurement hook): which = 0 both passes,
+// 1 column pass, 2 row pass (forward); 1 row pass with the fused
+// multiply-accumulate, 2 column pass (inverse).
+hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, int vi_lo,
+                            int vi_hi, const NttGeom& g, const TwBlock& tb, const TwStep& st, int which, hipStream_t s);
+hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                            const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
+                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s);
+
+// Kernel slices: multiply by N^{-1} and build Shoup companions.
+hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s);
+
+// --- split / chirp / groups / recombination --------------------------------
+hipError_t launch_chirp(double2* chirp, int n, int* flag, hipStream_t s);
+hipError_t launch_reset(TState* ts, const int* tlist, int count, hipStream_t s);
+hipError_t launch_premul(const double2* in, double2* xp, const TDesc* td, const KernelDesc* kd,
+                         TState* ts, const int* tlist, int count, int nmax, int dir, bool kernel_mode,
+                         hipStream_t s);
+hipError_t launch_split_plan(const TDesc* td, TState* ts, const int* tlist, int count, int K,
+                             hipStream_t s);
+hipError_t launch_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts,
+                                const int* tlist, int count, int nmax, int K, bool kernel_mode,
+                                hipStream_t s);
+hipError_t launch_split_check(const TDesc* td, TState* ts, const int* tlist, int count, int K,
+                              hipStream_t s);
+hipError_t launch_groups(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist,
+                         int count, int K, int L, hipStream_t s);
+hipError_t launch_recombine(const u32* Z, double2* out, const TDesc* td, const TState* ts,
+                            const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
+                            int dir, hipStream_t s);
+
+}  // namespace fo

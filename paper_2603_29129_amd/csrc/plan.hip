@@ -1,0 +1,829 @@
+// Plans, execution schedules and the C ABI of the library.
+//
+// A plan groups its transforms by convolution length N (one "length class"
+// per distinct N); every stage is launched once per class for all of its
+// transforms, and each kernel reads its transform's descriptor.  The
+// input-independent part of the method -- chirp, splits of Re w* and Im w*
+// and their forward NTTs (Sec. 4.5) -- is computed once per distinct n at
+// plan time with the same kernels as the runtime path.
+//
+// Two execution modes:
+//  * batched: a fixed launch sequence whose data-dependent parts (slice
+//    counts, exponents, Alg. 8 groups) live in device tables; it is captured
+//    once into a HIP graph per (in, out, direction) and replayed.
+//  * plain: transform by transform, the host reads the slice counts and
+//    groups back and issues one launch per NTT (per group and pass for the
+//    inverse), like a library-call-per-NTT implementation.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "fft_ozaki.h"
+
+namespace fo {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(FFT_OZAKI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Split width of Sec. 4.4: the largest alpha with 2 L n 4^alpha <= p0 p1,
+// i.e. alpha = floor((log2(p0 p1 / 2) - log2(L n)) / 2) evaluated exactly.
+static int alpha_for(i64 n, int L) {
+  const unsigned __int128 P = (unsigned __int128)PP;
+  int a = -1;
+  for (int c = 0; c < 40; ++c) {
+    const unsigned __int128 v = ((unsigned __int128)2 * (unsigned)L * (u64)n) << (2 * c);
+    if (v > P) break;
+    a = c;
+  }
+  return a;
+}
+
+// Bluestein convolution length: N = 2^ceil(log2(2n - 1)) (Sec. 3.2).
+static int conv_log2(i64 n) {
+  if (n <= 1) return 0;
+  int l = 0;
+  while (((i64)1 << l) < 2 * n - 1) ++l;
+  return l;
+}
+
+struct KernelHost {
+  i64 n;
+  int logN, alpha;
+  double2* chirp = nullptr;
+  u32* W = nullptr;
+  u32* Wq = nullptr;
+  int kw[2] = {0, 0};
+  int Ew[2][KMAX] = {};
+};
+
+struct LengthClass {
+  int logN;
+  NttGeom geom;
+  std::vector<int> tids;
+  int* d_tlist = nullptr;
+  int nmax = 0;
+};
+
+struct GraphEntry {
+  const void* in;
+  void* out;
+  int dir;
+  hipGraphExec_t exec;
+};
+
+}  // namespace fo
+
+struct fft_ozaki_plan_s {
+  int device = 0;
+  int K = 3, L = 3, mode = FFT_OZAKI_MODE_BATCHED;
+  int autotune = 0;
+  std::string tune_cache;
+  std::vector<fo::i64> lengths;
+  fo::i64 total = 0;
+  std::vector<fo::TDesc> td;
+  std::vector<fo::KernelHost> kernels;
+  std::vector<fo::LengthClass> classes;
+  fo::TwBlock tb{};
+  std::map<int, fo::TwStep> steps;
+  fo::TDesc* d_td = nullptr;
+  fo::KernelDesc* d_kd = nullptr;
+  fo::TState* d_ts = nullptr;
+  int* d_tall = nullptr;
+  double2* xp = nullptr;
+  fo::u32* X = nullptr;
+  fo::u32* G = nullptr;
+  fo::u32* Z = nullptr;
+  std::vector<void*> allocs;
+  fo::i64 bytes = 0;
+  hipStream_t cap = nullptr;
+  std::vector<fo::GraphEntry> graphs;
+  const void* last_in = nullptr;
+  void* last_out = nullptr;
+  int last_dir = -1;
+};
+
+namespace fo {
+
+static int dmalloc(fft_ozaki_plan_s* p, void** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) return fail(FFT_OZAKI_ERR_NOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+  p->allocs.push_back(*ptr);
+  p->bytes += (i64)bytes;
+  return FFT_OZAKI_OK;
+}
+
+static void destroy_plan(fft_ozaki_plan_s* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  for (void* a : p->allocs) (void)hipFree(a);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+static const TwStep& step_for(fft_ozaki_plan_s* p, int logN) {
+  static const TwStep none{};
+  auto it = p->steps.find(logN);
+  return it == p->steps.end() ? none : it->second;
+}
+
+// --- autotuning of the NTT tile shapes -------------------------------------
+// Candidate (log2 columns per workgroup, log2 rows per workgroup) pairs are
+// timed on a scratch vector; every candidate computes the same transform.
+
+static std::string tune_key(int logN) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t pr;
+  (void)hipGetDeviceProperties(&pr, dev);
+  return std::string(pr.gcnArchName) + ":" + std::to_string(logN);
+}
+
+static bool tune_lookup(const std::string& path, const std::string& key, int* lc, int* lr) {
+  if (path.empty()) return false;
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char k[400];
+    int a, b;
+    if (sscanf(line, "%399s %d %d", k, &a, &b) == 3 && key == k) {
+      *lc = a;
+      *lr = b;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+static void tune_store(const std::string& path, const std::string& key, int lc, int lr) {
+  if (path.empty()) return;
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d\n", key.c_str(), lc, lr);
+  fclose(f);
+}
+
+static int autotune_geom(fft_ozaki_plan_s* p, int logN, NttGeom* out) {
+  NttGeom def = ntt_geom(logN);
+  *out = def;
+  if (!def.two_pass()) return FFT_OZAKI_OK;
+  const std::string key = tune_key(logN);
+  int lc = -1, lr = -1;
+  if (tune_lookup(p->tune_cache, key, &lc, &lr)) {
+    *out = ntt_geom(logN, lc, lr);
+    return FFT_OZAKI_OK;
+  }
+  const int vecs = 8;
+  u32* buf = nullptr;
+  const size_t words = (size_t)vecs << logN;
+  HIPCHK(hipMalloc(&buf, words * 4));
+  HIPCHK(hipMemset(buf, 0, words * 4));
+  const TwStep& st = step_for(p, logN);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  for (int c = 2; c <= 6; ++c) {
+    if (def.m1 + c > 15 || c > def.m2) continue;
+    for (int r = 0; r <= 4; ++r) {
+      if (def.m2 + r > 14 || r > def.m1) continue;
+      NttGeom g = ntt_geom(logN, c, r);
+      for (int w = 0; w < 2; ++w) {
+        (void)launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr);
+        (void)launch_ntt_standalone(buf, logN, 0, vecs, true, g, p->tb, st, nullptr);
+      }
+      HIPCHK(hipEventRecord(e0, nullptr));
+      for (int w = 0; w < 5; ++w) {
+        (void)launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr);
+        (void)launch_ntt_standalone(buf, logN, 0, vecs, true, g, p->tb, st, nullptr);
+      }
+      HIPCHK(hipEventRecord(e1, nullptr));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (hipGetLastError() == hipSuccess && ms < best) {
+        best = ms;
+        *out = g;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  tune_store(p->tune_cache, key, out->lc, out->lrows);
+  return FFT_OZAKI_OK;
+}
+
+// --- kernel (chirp) preparation ---------------------------------------------
+
+static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
+  const i64 n = kh.n;
+  const size_t N = (size_t)1 << kh.logN;
+  const int K = p->K;
+  int rc;
+  if ((rc = dmalloc(p, (void**)&kh.chirp, sizeof(double2) * n))) return rc;
+  if ((rc = dmalloc(p, (void**)&kh.W, 4 * (size_t)(4 * K) * N))) return rc;
+  if ((rc = dmalloc(p, (void**)&kh.Wq, 4 * (size_t)(4 * K) * N))) return rc;
+  HIPCHK(hipMemset(kh.W, 0, 4 * (size_t)(4 * K) * N));
+  int* flag = nullptr;
+  double2* xp = nullptr;
+  TState* ts = nullptr;
+  TDesc* td = nullptr;
+  KernelDesc* kd = nullptr;
+  int* tl = nullptr;
+  HIPCHK(hipMalloc(&flag, sizeof(int)));
+  HIPCHK(hipMemset(flag, 0, sizeof(int)));
+  HIPCHK(hipMalloc(&xp, sizeof(double2) * n));
+  HIPCHK(hipMalloc(&ts, sizeof(TState)));
+  HIPCHK(hipMalloc(&td, sizeof(TDesc)));
+  HIPCHK(hipMalloc(&kd, sizeof(KernelDesc)));
+  HIPCHK(hipMalloc(&tl, sizeof(int)));
+  TDesc h{};
+  h.n = (int)n;
+  h.N = (int)N;
+  h.logN = kh.logN;
+  h.alpha = kh.alpha;
+  h.kd = 0;
+  KernelDesc hk{};
+  hk.n = (int)n;
+  hk.N = (int)N;
+  hk.logN = kh.logN;
+  hk.alpha = kh.alpha;
+  hk.chirp = kh.chirp;
+  const int zero = 0;
+  HIPCHK(hipMemcpy(td, &h, sizeof h, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(kd, &hk, sizeof hk, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(tl, &zero, sizeof zero, hipMemcpyHostToDevice));
+  HIPCHK(launch_chirp(kh.chirp, (int)n, flag, nullptr));
+  HIPCHK(launch_reset(ts, tl, 1, nullptr));
+  HIPCHK(launch_premul(nullptr, xp, td, kd, ts, tl, 1, (int)n, 0, true, nullptr));
+  HIPCHK(launch_split_plan(td, ts, tl, 1, K, nullptr));
+  for (int r = 0; r < K; ++r) {
+    HIPCHK(launch_split_extract(xp, kh.W, td, ts, tl, 1, (int)n, K, true, nullptr));
+    HIPCHK(launch_split_check(td, ts, tl, 1, K, nullptr));
+  }
+  TState hs;
+  HIPCHK(hipMemcpy(&hs, ts, sizeof hs, hipMemcpyDeviceToHost));
+  int hflag = 0;
+  HIPCHK(hipMemcpy(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost));
+  if (hs.status || hs.active[0] || hs.active[1]) return fail(FFT_OZAKI_ERR_UNSUPPORTED, "kernel split failed");
+  if (hflag) return fail(FFT_OZAKI_ERR_UNSUPPORTED, "chirp value too close to a rounding boundary for n=" + std::to_string(n));
+  for (int part = 0; part < 2; ++part) {
+    kh.kw[part] = hs.kx[part];
+    for (int k = 0; k < KMAX; ++k) kh.Ew[part][k] = k < hs.kx[part] ? hs.E[part][k] : 0;
+  }
+  // forward NTTs of the kernel slices (all N positions populated)
+  NttGeom g = ntt_geom(kh.logN);
+  HIPCHK(launch_fwd_pipeline(kh.W, td, ts, tl, 1, K, true, 0, 4 * K, g, p->tb, step_for(p, kh.logN), nullptr));
+  HIPCHK(launch_kernel_finish(kh.W, kh.Wq, K, kh.logN, nullptr));
+  HIPCHK(hipDeviceSynchronize());
+  (void)idx;
+  (void)hipFree(flag);
+  (void)hipFree(xp);
+  (void)hipFree(ts);
+  (void)hipFree(td);
+  (void)hipFree(kd);
+  (void)hipFree(tl);
+  return FFT_OZAKI_OK;
+}
+
+static int build_plan(fft_ozaki_plan_s* p) {
+  const int K = p->K;
+  const int count = (int)p->lengths.size();
+  HIPCHK(hipGetDevice(&p->device));
+  void* tw_allocs[4];
+  if (build_block_twiddles(&p->tb, tw_allocs)) return fail(FFT_OZAKI_ERR_NOMEM, "twiddle tables");
+  for (void* a : tw_allocs) p->allocs.push_back(a);
+  // distinct lengths and N classes
+  std::map<i64, int> kidx;
+  std::map<int, int> cidx;
+  for (i64 n : p->lengths) {
+    if (!kidx.count(n)) {
+      KernelHost kh;
+      kh.n = n;
+      kh.logN = conv_log2(n);
+      kh.alpha = alpha_for(n, p->L);
+      kidx[n] = (int)p->kernels.size();
+      p->kernels.push_back(kh);
+    }
+    const int lg = conv_log2(n);
+    if (!cidx.count(lg)) {
+      LengthClass lc;
+      lc.logN = lg;
+      cidx[lg] = (int)p->classes.size();
+      p->classes.push_back(lc);
+    }
+  }
+  for (auto& lc : p->classes) {
+    if (ntt_geom(lc.logN).two_pass() && !p->steps.count(lc.logN)) {
+      void* sa[8];
+      TwStep st{};
+      if (build_step_twiddles(lc.logN, &st, sa)) return fail(FFT_OZAKI_ERR_NOMEM, "step twiddles");
+      for (void* a : sa) p->allocs.push_back(a);
+      p->steps[lc.logN] = st;
+    }
+    lc.geom = ntt_geom(lc.logN);
+    if (p->autotune) {
+      int rc = autotune_geom(p, lc.logN, &lc.geom);
+      if (rc) return rc;
+    }
+  }
+  for (size_t i = 0; i < p->kernels.size(); ++i) {
+    int rc = prepare_kernel(p, p->kernels[i], (int)i);
+    if (rc) return rc;
+  }
+  // descriptors and workspace
+  i64 io = 0, xo = 0, go = 0, zo = 0;
+  const i64 SL = (i64)K * K;
+  for (int t = 0; t < count; ++t) {
+    const i64 n = p->lengths[t];
+    TDesc d{};
+    d.n = (int)n;
+    d.logN = conv_log2(n);
+    d.N = 1 << d.logN;
+    d.alpha = alpha_for(n, p->L);
+    d.kd = kidx[n];
+    d.io_off = io;
+    d.xp_off = io;
+    d.X_off = xo;
+    d.G_off = go;
+    d.Z_off = zo;
+    io += n;
+    xo += (i64)(4 * K) << d.logN;
+    if (ntt_geom(d.logN).two_pass()) go += (8 * SL) << d.logN;
+    zo += 8 * SL * n;
+    p->td.push_back(d);
+    LengthClass& lc = p->classes[cidx[d.logN]];
+    lc.tids.push_back(t);
+    lc.nmax = std::max<int>(lc.nmax, (int)n);
+  }
+  p->total = io;
+  for (auto& lc : p->classes)
+    if (lc.tids.size() > 65535) return fail(FFT_OZAKI_ERR_INVALID, "more than 65535 transforms share one convolution length");
+  int rc;
+  if ((rc = dmalloc(p, (void**)&p->xp, sizeof(double2) * (size_t)io))) return rc;
+  if ((rc = dmalloc(p, (void**)&p->X, 4 * (size_t)xo))) return rc;
+  if ((rc = dmalloc(p, (void**)&p->G, 4 * (size_t)go))) return rc;
+  if ((rc = dmalloc(p, (void**)&p->Z, 4 * (size_t)zo))) return rc;
+  if ((rc = dmalloc(p, (void**)&p->d_td, sizeof(TDesc) * count))) return rc;
+  if ((rc = dmalloc(p, (void**)&p->d_ts, sizeof(TState) * count))) return rc;
+  if ((rc = dmalloc(p, (void**)&p->d_tall, sizeof(int) * count))) return rc;
+  if ((rc = dmalloc(p, (void**)&p->d_kd, sizeof(KernelDesc) * p->kernels.size()))) return rc;
+  HIPCHK(hipMemcpy(p->d_td, p->td.data(), sizeof(TDesc) * count, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(p->d_ts, 0, sizeof(TState) * count));
+  std::vector<int> all(count);
+  for (int t = 0; t < count; ++t) all[t] = t;
+  HIPCHK(hipMemcpy(p->d_tall, all.data(), sizeof(int) * count, hipMemcpyHostToDevice));
+  std::vector<KernelDesc> kds;
+  for (auto& kh : p->kernels) {
+    KernelDesc k{};
+    k.n = (int)kh.n;
+    k.logN = kh.logN;
+    k.N = 1 << kh.logN;
+    k.alpha = kh.alpha;
+    k.chirp = kh.chirp;
+    k.W = kh.W;
+    k.Wq = kh.Wq;
+    for (int part = 0; part < 2; ++part) {
+      k.kw[part] = kh.kw[part];
+      for (int j = 0; j < KMAX; ++j) k.Ew[part][j] = kh.Ew[part][j];
+    }
+    kds.push_back(k);
+  }
+  HIPCHK(hipMemcpy(p->d_kd, kds.data(), sizeof(KernelDesc) * kds.size(), hipMemcpyHostToDevice));
+  for (auto& lc : p->classes) {
+    if ((rc = dmalloc(p, (void**)&lc.d_tlist, sizeof(int) * lc.tids.size()))) return rc;
+    HIPCHK(hipMemcpy(lc.d_tlist, lc.tids.data(), sizeof(int) * lc.tids.size(), hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+  HIPCHK(hipDeviceSynchronize());
+  return FFT_OZAKI_OK;
+}
+
+// The batched launch sequence (also what gets captured into the graph).
+static int enqueue_batched(fft_ozaki_plan_s* p, const double2* in, double2* out, int dir, hipStream_t s) {
+  const int K = p->K, count = (int)p->td.size();
+  HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
+  for (auto& lc : p->classes)
+    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false, s));
+  HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_tall, count, K, s));
+  for (int r = 0; r < K; ++r) {
+    for (auto& lc : p->classes)
+      HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s));
+    HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
+  }
+  HIPCHK(launch_groups(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, p->L, s));
+  for (auto& lc : p->classes)
+    HIPCHK(launch_fwd_pipeline(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K, lc.geom,
+                               p->tb, step_for(p, lc.logN), s));
+  for (auto& lc : p->classes)
+    HIPCHK(launch_inv_pipeline(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), K, 0,
+                               4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), s));
+  for (auto& lc : p->classes)
+    HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, dir, s));
+  return FFT_OZAKI_OK;
+}
+
+static int run_batched(fft_ozaki_plan_s* p, const double2* in, double2* out, int dir, hipStream_t s) {
+  for (auto& g : p->graphs) {
+    if (g.in == in && g.out == out && g.dir == dir) {
+      HIPCHK(hipGraphLaunch(g.exec, s));
+      return FFT_OZAKI_OK;
+    }
+  }
+  // capture on the plan's private stream, after the caller's prior work
+  hipEvent_t ev;
+  HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ev, s));
+  HIPCHK(hipStreamWaitEvent(p->cap, ev, 0));
+  HIPCHK(hipStreamSynchronize(p->cap));
+  (void)hipEventDestroy(ev);
+  hipGraph_t graph;
+  HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_batched(p, in, out, dir, p->cap);
+  hipError_t ce = hipStreamEndCapture(p->cap, &graph);
+  if (rc) return rc;
+  if (ce != hipSuccess) return fail(FFT_OZAKI_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+  hipGraphExec_t exec;
+  HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  (void)hipGraphDestroy(graph);
+  if (p->graphs.size() >= 4) {
+    (void)hipStreamSynchronize(s);
+    (void)hipGraphExecDestroy(p->graphs.front().exec);
+    p->graphs.erase(p->graphs.begin());
+  }
+  p->graphs.push_back({in, out, dir, exec});
+  HIPCHK(hipGraphLaunch(exec, s));
+  return FFT_OZAKI_OK;
+}
+
+static int run_plain(fft_ozaki_plan_s* p, const double2* in, double2* out, int dir, hipStream_t s) {
+  const int K = p->K, SL = K * K;
+  for (int t = 0; t < (int)p->td.size(); ++t) {
+    const TDesc& d = p->td[t];
+    const int* tl = p->d_tall + t;
+    const NttGeom g = p->classes.empty() ? ntt_geom(d.logN) : [&] {
+      for (auto& lc : p->classes)
+        if (lc.logN == d.logN) return lc.geom;
+      return ntt_geom(d.logN);
+    }();
+    const TwStep& st = step_for(p, d.logN);
+    HIPCHK(launch_reset(p->d_ts, tl, 1, s));
+    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, s));
+    HIPCHK(launch_split_plan(p->d_td, p->d_ts, tl, 1, K, s));
+    for (int r = 0; r < K; ++r) {
+      HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, tl, 1, d.n, K, false, s));
+      HIPCHK(launch_split_check(p->d_td, p->d_ts, tl, 1, K, s));
+      int act[2];
+      HIPCHK(hipMemcpyAsync(act, &p->d_ts[t].active, sizeof act, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (!act[0] && !act[1]) break;
+    }
+    HIPCHK(launch_groups(p->d_td, p->d_ts, p->d_kd, tl, 1, K, p->L, s));
+    TState hs;
+    HIPCHK(hipMemcpyAsync(&hs, &p->d_ts[t], sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!hs.status) {
+      for (int part = 0; part < 2; ++part)
+        for (int k = 0; k < hs.kx[part]; ++k)
+          for (int prime = 0; prime < 2; ++prime) {
+            const int vi = (part * K + k) * 2 + prime;
+            HIPCHK(launch_fwd_pipeline(p->X, p->d_td, p->d_ts, tl, 1, K, false, vi, vi + 1, g, p->tb, st, s));
+          }
+      for (int c = 0; c < 4; ++c)
+        for (int gi = 0; gi < hs.ngroups[c]; ++gi) {
+          const int slot = c * SL + gi;
+          HIPCHK(launch_inv_pipeline(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, tl, 1, K, slot, slot + 1, g, p->tb,
+                                     st, s));
+        }
+    }
+    HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, tl, 1, d.n, K, dir, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return FFT_OZAKI_OK;
+}
+
+// One stage of the batched sequence for all transforms (measurement hook).
+static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
+  const int K = p->K, count = (int)p->td.size();
+  const double2* in = (const double2*)p->last_in;
+  double2* out = (double2*)p->last_out;
+  const int dir = p->last_dir;
+  switch (stage) {
+    case 1:   // split: premultiply, maxima and the K extraction/check passes
+      HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
+      for (auto& lc : p->classes)
+        HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false, s));
+      HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_tall, count, K, s));
+      for (int r = 0; r < K; ++r) {
+        for (auto& lc : p->classes)
+          HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s));
+        HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
+      }
+      return FFT_OZAKI_OK;
+    case 2:
+      HIPCHK(launch_groups(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, p->L, s));
+      return FFT_OZAKI_OK;
+    case 3:
+    case 4:
+    case 5:
+      for (auto& lc : p->classes) {
+        NttGeom g = lc.geom;
+        if (stage != 3 && !g.two_pass()) continue;
+        HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, 0, 4 * K, g, p->tb,
+                                step_for(p, lc.logN), stage == 3 ? 0 : stage - 3, s));
+      }
+      return FFT_OZAKI_OK;
+    case 6:
+    case 7:
+      for (auto& lc : p->classes)
+        HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), K, 0,
+                                4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), stage - 5, s));
+      return FFT_OZAKI_OK;
+    case 8:
+      for (auto& lc : p->classes)
+        HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, dir, s));
+      return FFT_OZAKI_OK;
+    default:
+      return fail(FFT_OZAKI_ERR_INVALID, "unknown stage");
+  }
+}
+
+// Global tables for the standalone NTT entry point, per device.
+struct StdTables {
+  TwBlock tb{};
+  std::map<int, TwStep> steps;
+};
+static std::mutex g_std_mu;
+static std::map<int, StdTables> g_std;
+
+}  // namespace fo
+
+using namespace fo;
+
+extern "C" {
+
+int fft_ozaki_default_options(fft_ozaki_options* opt) {
+  if (!opt) return fail(FFT_OZAKI_ERR_INVALID, "opt is NULL");
+  opt->K = 3;
+  opt->L = 3;
+  opt->mode = FFT_OZAKI_MODE_BATCHED;
+  opt->autotune = 0;
+  opt->tune_cache = nullptr;
+  return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t count, const fft_ozaki_options* opt) {
+  g_err.clear();
+  if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
+  *plan = nullptr;
+  if (!lengths || count < 1) return fail(FFT_OZAKI_ERR_INVALID, "need count >= 1 and a lengths array");
+  if (count > (1 << 24)) return fail(FFT_OZAKI_ERR_INVALID, "too many transforms");
+  fft_ozaki_options o;
+  fft_ozaki_default_options(&o);
+  if (opt) o = *opt;
+  if (o.K < 1 || o.K > KMAX) return fail(FFT_OZAKI_ERR_INVALID, "K must be in [1, 8]");
+  if (o.L < 1 || o.L > (1 << 20)) return fail(FFT_OZAKI_ERR_INVALID, "L must be in [1, 2^20]");
+  if (o.mode != FFT_OZAKI_MODE_PLAIN && o.mode != FFT_OZAKI_MODE_BATCHED)
+    return fail(FFT_OZAKI_ERR_INVALID, "mode must be 0 (plain) or 1 (batched)");
+  i64 total = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const i64 n = lengths[i];
+    if (n < 1) return fail(FFT_OZAKI_ERR_INVALID, "lengths must be >= 1");
+    if (conv_log2(n) > MAX_LOG2_N) return fail(FFT_OZAKI_ERR_INVALID, "convolution length 2^ceil(log2(2n-1)) exceeds 2^24");
+    const int a = alpha_for(n, o.L);
+    if (a < 1 || a > 30) return fail(FFT_OZAKI_ERR_INVALID, "split width alpha < 1 for this n and L");
+    total += n;
+  }
+  if (total > ((i64)1 << 31)) return fail(FFT_OZAKI_ERR_INVALID, "total length too large");
+  fft_ozaki_plan_s* p = new (std::nothrow) fft_ozaki_plan_s();
+  if (!p) return fail(FFT_OZAKI_ERR_NOMEM, "host allocation");
+  p->K = o.K;
+  p->L = o.L;
+  p->mode = o.mode;
+  p->autotune = o.autotune;
+  p->tune_cache = o.tune_cache ? o.tune_cache : "";
+  p->lengths.assign(lengths, lengths + count);
+  int rc = build_plan(p);
+  if (rc) {
+    std::string keep = g_err;
+    destroy_plan(p);
+    g_err = keep;
+    return rc;
+  }
+  *plan = p;
+  return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_plan(fft_ozaki_plan_t* plan, int64_t n, int64_t batch) {
+  if (batch < 1) return fail(FFT_OZAKI_ERR_INVALID, "batch must be >= 1");
+  if (batch > (1 << 24)) return fail(FFT_OZAKI_ERR_INVALID, "batch too large");
+  std::vector<int64_t> l((size_t)batch, n);
+  return fft_ozaki_plan_ex(plan, l.data(), batch, nullptr);
+}
+
+int fft_ozaki_execute(fft_ozaki_plan_t plan, const void* in, void* out, int direction, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
+  if (!in || !out) return fail(FFT_OZAKI_ERR_INVALID, "in/out is NULL");
+  if (direction < 0 || direction > 2) return fail(FFT_OZAKI_ERR_INVALID, "direction must be 0, 1 or 2");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(FFT_OZAKI_ERR_INVALID, "in/out must be 16-byte aligned");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != plan->device) HIPCHK(hipSetDevice(plan->device));
+  hipStream_t s = (hipStream_t)stream;
+  plan->last_in = in;
+  plan->last_out = out;
+  plan->last_dir = direction;
+  int rc = plan->mode == FFT_OZAKI_MODE_PLAIN
+               ? run_plain(plan, (const double2*)in, (double2*)out, direction, s)
+               : run_batched(plan, (const double2*)in, (double2*)out, direction, s);
+  if (cur != plan->device) (void)hipSetDevice(cur);
+  return rc;
+}
+
+int fft_ozaki_forward(fft_ozaki_plan_t plan, const void* in, void* out, void* stream) {
+  return fft_ozaki_execute(plan, in, out, FFT_OZAKI_FORWARD, stream);
+}
+
+int fft_ozaki_inverse(fft_ozaki_plan_t plan, const void* in, void* out, void* stream) {
+  return fft_ozaki_execute(plan, in, out, FFT_OZAKI_INVERSE, stream);
+}
+
+int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info) {
+  if (!plan || !info) return fail(FFT_OZAKI_ERR_INVALID, "plan/info is NULL");
+  info->count = (int64_t)plan->td.size();
+  info->total_length = plan->total;
+  info->K = plan->K;
+  info->L = plan->L;
+  info->mode = plan->mode;
+  info->num_length_classes = (int)plan->classes.size();
+  info->workspace_bytes = plan->bytes;
+  return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_transform_info* info) {
+  if (!plan || !info) return fail(FFT_OZAKI_ERR_INVALID, "plan/info is NULL");
+  if (index < 0 || index >= (int64_t)plan->td.size()) return fail(FFT_OZAKI_ERR_INVALID, "index out of range");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  HIPCHK(hipSetDevice(plan->device));
+  HIPCHK(hipDeviceSynchronize());
+  TState hs;
+  HIPCHK(hipMemcpy(&hs, &plan->d_ts[index], sizeof hs, hipMemcpyDeviceToHost));
+  (void)hipSetDevice(cur);
+  const TDesc& d = plan->td[index];
+  const KernelHost& kh = plan->kernels[d.kd];
+  memset(info, 0, sizeof *info);
+  info->n = d.n;
+  info->N = d.N;
+  info->alpha = d.alpha;
+  info->status = hs.status;
+  int fr = 0, fo_ = 0, iv = 0;
+  for (int part = 0; part < 2; ++part) {
+    info->kx[part] = hs.kx[part];
+    info->kw[part] = kh.kw[part];
+    for (int k = 0; k < 8; ++k) {
+      info->Ex[part][k] = k < hs.kx[part] ? hs.E[part][k] : 0;
+      info->Ew[part][k] = kh.Ew[part][k];
+    }
+    fr += 2 * hs.kx[part];
+    fo_ += 2 * kh.kw[part];
+  }
+  for (int c = 0; c < 4; ++c) {
+    info->ngroups[c] = hs.ngroups[c];
+    iv += 2 * hs.ngroups[c];
+  }
+  info->forward_runtime = fr;
+  info->forward_offline = fo_;
+  info->inverse = iv;
+  info->ntt_log2N1 = ntt_geom(d.logN).m1;
+  return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* host_dst, size_t bytes,
+                         size_t* needed) {
+  if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
+  if (index < 0 || index >= (int64_t)plan->td.size()) return fail(FFT_OZAKI_ERR_INVALID, "index out of range");
+  const TDesc& d = plan->td[index];
+  const KernelHost& kh = plan->kernels[d.kd];
+  const int K = plan->K;
+  const void* src = nullptr;
+  size_t sz = 0;
+  switch (stage) {
+    case 1: src = plan->xp + d.xp_off; sz = sizeof(double2) * (size_t)d.n; break;
+    case 2: src = plan->X + d.X_off; sz = 4 * ((size_t)(4 * K) << d.logN); break;
+    case 3: src = plan->Z + d.Z_off; sz = 4 * (size_t)(8 * K * K) * (size_t)d.n; break;
+    case 4: src = kh.W; sz = 4 * ((size_t)(4 * K) << d.logN); break;
+    case 5: src = kh.chirp; sz = sizeof(double2) * (size_t)d.n; break;
+    default: return fail(FFT_OZAKI_ERR_INVALID, "unknown stage");
+  }
+  if (needed) *needed = sz;
+  if (!host_dst) return FFT_OZAKI_OK;
+  if (bytes < sz) return fail(FFT_OZAKI_ERR_INVALID, "buffer too small");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  HIPCHK(hipSetDevice(plan->device));
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(host_dst, src, sz, hipMemcpyDeviceToHost));
+  (void)hipSetDevice(cur);
+  return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_profile_stage(fft_ozaki_plan_t plan, int stage, int reps, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
+  if (plan->mode != FFT_OZAKI_MODE_BATCHED) return fail(FFT_OZAKI_ERR_INVALID, "stage profiling needs the batched mode");
+  if (!plan->last_in) return fail(FFT_OZAKI_ERR_INVALID, "execute the plan once before profiling");
+  if (reps < 1) return fail(FFT_OZAKI_ERR_INVALID, "reps must be >= 1");
+  for (int r = 0; r < reps; ++r) {
+    int rc = enqueue_stage(plan, stage, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_destroy(fft_ozaki_plan_t plan) {
+  if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
+  destroy_plan(plan);
+  return FFT_OZAKI_OK;
+}
+
+const char* fft_ozaki_error_string(int status) {
+  switch (status) {
+    case FFT_OZAKI_OK: return "success";
+    case FFT_OZAKI_ERR_INVALID: return "invalid argument";
+    case FFT_OZAKI_ERR_NOMEM: return "out of memory";
+    case FFT_OZAKI_ERR_HIP: return "HIP runtime error";
+    case FFT_OZAKI_ERR_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+const char* fft_ozaki_last_error_message(void) { return g_err.c_str(); }
+
+int fft_ozaki_ntt_layout(int log2N, int* log2N1) {
+  if (log2N < 0 || log2N > MAX_LOG2_N || !log2N1) return fail(FFT_OZAKI_ERR_INVALID, "log2N out of range");
+  *log2N1 = ntt_geom(log2N).m1;
+  return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_ntt(int prime, int log2N, int64_t count, void* data, int inverse, void* stream) {
+  g_err.clear();
+  if (prime < 0 || prime > 1) return fail(FFT_OZAKI_ERR_INVALID, "prime must be 0 or 1");
+  if (log2N < 0 || log2N > MAX_LOG2_N) return fail(FFT_OZAKI_ERR_INVALID, "log2N out of range");
+  if (count < 0 || count > 65535) return fail(FFT_OZAKI_ERR_INVALID, "count must be in [0, 65535]");
+  if (!data && count) return fail(FFT_OZAKI_ERR_INVALID, "data is NULL");
+  if (count == 0) return FFT_OZAKI_OK;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  TwBlock tb;
+  TwStep st{};
+  {
+    std::lock_guard<std::mutex> lk(g_std_mu);
+    StdTables& T = g_std[dev];
+    if (!T.tb.fwd[0]) {
+      void* a[4];
+      if (build_block_twiddles(&T.tb, a)) return fail(FFT_OZAKI_ERR_NOMEM, "twiddle tables");
+    }
+    NttGeom g = ntt_geom(log2N);
+    if (g.two_pass() && !T.steps.count(log2N)) {
+      void* a[8];
+      TwStep s{};
+      if (build_step_twiddles(log2N, &s, a)) return fail(FFT_OZAKI_ERR_NOMEM, "step twiddles");
+      T.steps[log2N] = s;
+    }
+    tb = T.tb;
+    if (g.two_pass()) st = T.steps[log2N];
+  }
+  HIPCHK(launch_ntt_standalone((u32*)data, log2N, prime, (int)count, inverse != 0, ntt_geom(log2N), tb, st,
+                               (hipStream_t)stream));
+  return FFT_OZAKI_OK;
+}
+
+}  // extern "C"

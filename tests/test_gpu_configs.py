@@ -1,0 +1,144 @@
+"""GPU parity at the benchmark workloads' full sizes.
+
+n = 2^18 (wide dynamic range), the 256 mixed lengths in one batched launch,
+and the differentiable transform on 32 x 2^16.  Where the oracle cannot
+recompute everything in seconds, sampled transforms are compared exactly and
+the rest is checked through properties that hold at any size (a transform
+computed inside the batch equals the same transform planned alone; the plain
+and batched forms agree bit for bit)."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import bluestein as bl
+from oracle import reference as ref
+from tests.gpu_helpers import max_ulp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _gpu(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda()
+
+
+@pytest.fixture(scope="module")
+def wide_plan():
+    return bl.KernelPlan(1 << 18, 3, 3)
+
+
+def test_wide_256k_batch8(torch_mod, wide_plan):
+    """8 x n = 2^18, |x| log-uniform in [2^-30, 2^30]: transforms 0 and 7
+    against the oracle, all 8 batched vs plain bit for bit."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n, B = 1 << 18, 8
+    x = wl.wide_256k(seed=0, batch=B, n=n)
+    xd = _gpu(torch, x)
+    yb = oz.Plan(n, B, mode="batched").forward(xd).cpu().numpy()
+    yp = oz.Plan(n, B, mode="plain").forward(xd).cpu().numpy()
+    assert np.array_equal(yb.view(np.uint64), yp.view(np.uint64))
+    for b in (0, 7):
+        want = bl.fft(x[b], 3, 3, wide_plan)
+        assert max_ulp(yb[b], want) == 0
+    assert ref.rel_l2_error(yb[0], ref.dft_longdouble(x[0])) < 1e-15
+
+
+def test_wide_256k_single_K6_L1(torch_mod):
+    """Single transform at n = 2^18 with K = 6, L = 1 (uncapped for this
+    distribution's dynamic range)."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 1 << 18
+    x = wl.wide_256k(seed=0, batch=1, n=n)
+    plan = oz.Plan(n, 1, K=6, L=1)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    want = bl.fft(x[0], 6, 1, bl.KernelPlan(n, 6, 1))
+    assert max_ulp(y[0], want) == 0
+    info = plan.transform_info(0)
+    assert info["alpha"] == 21
+
+
+def test_mixed_256_one_launch(torch_mod):
+    """256 transforms of lengths log-uniform in [2^10, 2^16] (a third prime)
+    in one batched execution: sampled transforms against the oracle, every
+    transform equal to the same transform computed by a plan of its own
+    (for a subset), and the graph replay stable."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    ns, xs = wl.mixed_256(0)
+    flat = _gpu(torch, np.concatenate(xs))
+    plan = oz.Plan(lengths=ns)
+    y1 = plan.forward(flat).cpu().numpy()
+    y2 = plan.forward(flat).cpu().numpy()
+    assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    # one sample per convolution-length class, smallest n first
+    by_N = {}
+    for i, n in enumerate(ns):
+        by_N.setdefault(bl.conv_length(n), i)
+    for i in sorted(by_N.values()):
+        n = ns[i]
+        want = bl.fft(xs[i], 3, 3, bl.KernelPlan(n, 3, 3))
+        assert max_ulp(y1[offs[i]:offs[i + 1]], want) == 0, (i, n)
+    for i in range(0, 256, 37):
+        single = oz.Plan(ns[i], 1).forward(_gpu(torch, xs[i][None, :])).cpu().numpy()[0]
+        assert np.array_equal(single.view(np.uint64), y1[offs[i]:offs[i + 1]].view(np.uint64)), i
+
+
+def test_autograd_backward_is_oracle_adjoint(torch_mod):
+    """loss = sum(w |X|^2) on 32 x 2^16: the gradient equals the oracle's
+    adjoint DFT of 2 w X (sampled rows, bit for bit) and central finite
+    differences (h = 1e-6) along the gradient and random directions."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x, w = wl.grad_64k(0)
+    n = x.shape[1]
+    xd = _gpu(torch, x).requires_grad_(True)
+    wd = torch.from_numpy(w).cuda()
+    X = oz.OzakiDFT.apply(xd)
+    seen = []
+    X.register_hook(lambda gX: seen.append(gX.detach().clone()))
+    loss = (wd * X.abs() ** 2).sum()
+    loss.backward()
+    g = xd.grad.detach().cpu().numpy()
+    gX = seen[0].cpu().numpy()
+    Xh = X.detach().cpu().numpy()
+    # the incoming gradient is 2 w X (torch's convention for real losses)
+    assert np.allclose(gX, 2.0 * w * Xh, rtol=1e-14, atol=0)
+    kp = bl.KernelPlan(n, 3, 3)
+    for b in (0, 31):
+        want = bl.adjoint(gX[b], plan=kp)          # backward = DFT^H of the incoming gradient
+        assert max_ulp(g[b], want) == 0
+    # finite differences of the loss along directions v: (L(x+hv)-L(x-hv))/(2h) = Re<grad, v>
+    def L(xx):
+        with torch.no_grad():
+            Y = oz.fft(xx)
+            return float((wd * Y.abs() ** 2).sum())
+    h = 1e-6
+    gn = np.linalg.norm(g)
+    rng = np.random.default_rng(4)
+    dirs = [g / gn]
+    for _ in range(2):
+        v = rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)
+        dirs.append(v / np.linalg.norm(v))
+    for k, v in enumerate(dirs):
+        vd = _gpu(torch, v)
+        fd = (L(xd.detach() + h * vd) - L(xd.detach() - h * vd)) / (2 * h)
+        an = float(np.real(np.vdot(g, v)))   # torch grads are conjugate Wirtinger: dL = Re<g, dx>
+        tol = 1e-6 if k == 0 else 1e-3
+        assert abs(fd - an) <= tol * max(abs(an), gn), (k, fd, an)
+
+
+def test_autograd_gradcheck_small(torch_mod):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = _gpu(torch, wl.uniform(12, batch=2, seed=1)).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: oz.OzakiDFT.apply(t), (x,), eps=1e-6, atol=1e-7, rtol=1e-5)

@@ -1,0 +1,226 @@
+"""GPU parity of the full transform against the oracle.
+
+Every intermediate the library exposes is compared bit for bit with the
+oracle's (chirp, x', slice counts and exponents, forward NTTs of the slices,
+kernel NTTs, inverse-NTT residues of every Alg. 8 group); the binary64
+outputs must agree within 2 ulp per component (the method is deterministic
+and the expected distance is 0)."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import bluestein as bl
+from oracle import ntt as nt
+from oracle import ozaki as oz_or
+from oracle import reference as ref
+from tests.gpu_helpers import max_ulp, ntt_domain_index
+
+pytestmark = pytest.mark.gpu
+ULP_TOL = 2
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _gpu(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda()
+
+
+_KPLANS = {}
+
+
+def kplan(n, K, L):
+    key = (n, K, L)
+    if key not in _KPLANS:
+        _KPLANS[key] = bl.KernelPlan(n, K, L)
+    return _KPLANS[key]
+
+
+def check_stages(plan, idx, tr, kp, K):
+    """Bit-exact comparison of the exposed intermediates of one transform."""
+    n, N = tr["n"], tr["N"]
+    info = plan.transform_info(idx)
+    assert info["status"] == tr["status"]
+    assert info["N"] == N and info["alpha"] == tr["alpha"]
+    # chirp
+    ch = plan.debug_dump(5, idx)
+    assert np.array_equal(ch.real, kp.c) and np.array_equal(ch.imag, kp.s)
+    if tr["status"]:
+        return
+    # x'
+    xp = plan.debug_dump(1, idx)
+    assert np.array_equal(xp.real, tr["xpr"]) and np.array_equal(xp.imag, tr["xpi"])
+    # slice counts and exponents
+    for part in range(2):
+        assert info["kx"][part] == len(tr["slices"][part])
+        assert info["Ex"][part] == [E for _, E in tr["slices"][part]]
+        assert info["kw"][part] == len(kp.slices[part])
+        assert info["Ew"][part] == [E for _, E in kp.slices[part]]
+    assert info["ngroups"] == [len(g) for g in tr["groups"]]
+    logN = N.bit_length() - 1
+    perm = ntt_domain_index(logN, info["ntt_log2N1"])
+    # forward NTTs of the slices
+    X = plan.debug_dump(2, idx).reshape(2, K, 2, N)
+    for part in range(2):
+        for k in range(len(tr["slices"][part])):
+            for ip in range(2):
+                assert np.array_equal(X[part, k, ip].astype(np.uint64), tr["X"][part][k][ip][perm]), (part, k, ip)
+    # kernel NTTs (times N^-1)
+    W = plan.debug_dump(4, idx).reshape(2, K, 2, N)
+    for part in range(2):
+        for t in range(len(kp.slices[part])):
+            for ip, p in enumerate(nt.PRIMES):
+                want = (kp.ntts[part][t][ip] * np.uint64(pow(N, -1, p))) % np.uint64(p)
+                assert np.array_equal(W[part, t, ip].astype(np.uint64), want[perm]), (part, t, ip)
+    # inverse NTT residues of every group
+    Z = plan.debug_dump(3, idx).reshape(4 * K * K, 2, n)
+    for c in range(4):
+        for g, (z, _e) in enumerate(tr["group_z"][c]):
+            for ip, p in enumerate(nt.PRIMES):
+                want = np.mod(z, p).astype(np.uint64)
+                assert np.array_equal(Z[c * K * K + g, ip].astype(np.uint64), want), (c, g, ip)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 16, 17, 31, 64, 100, 127, 1000, 1024, 2047, 2048, 2049, 4097])
+def test_forward_small(torch_mod, n):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    K, L = 3, 3
+    x = wl.paper_phi(n, 1.0, seed=n, batch=2)
+    plan = oz.Plan(n, 2, K=K, L=L)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan(n, K, L)
+    for b in range(2):
+        tr = bl.forward_trace(x[b], K, L, kp)
+        check_stages(plan, b, tr, kp, K)
+        assert max_ulp(y[b], tr["y"]) <= ULP_TOL
+
+
+def test_plain_1k_config(torch_mod):
+    """One transform, n = 2^10 (N = 2048), uniform[-1, 1], seed 0."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = wl.plain_1k(0)
+    for mode in ("plain", "batched"):
+        plan = oz.Plan(1024, 1, mode=mode)
+        y = plan.forward(_gpu(torch, x)).cpu().numpy()
+        kp = kplan(1024, 3, 3)
+        tr = bl.forward_trace(x[0], 3, 3, kp)
+        check_stages(plan, 0, tr, kp, 3)
+        assert max_ulp(y[0], tr["y"]) == 0
+        assert ref.rel_l2_error(y[0], ref.dft_longdouble(x[0])) < 1e-15
+
+
+@pytest.mark.parametrize("K,L", [(1, 1), (2, 1), (3, 1), (2, 2), (4, 3), (6, 1), (8, 8)])
+def test_K_L_variants(torch_mod, K, L):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 777
+    x = wl.paper_phi(n, 4.0, seed=K * 10 + L, batch=1)
+    plan = oz.Plan(n, 1, K=K, L=L)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan(n, K, L)
+    tr = bl.forward_trace(x[0], K, L, kp)
+    check_stages(plan, 0, tr, kp, K)
+    assert max_ulp(y[0], tr["y"]) == 0
+
+
+@pytest.mark.parametrize("direction", [1, 2])
+def test_inverse_and_adjoint(torch_mod, direction):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    for n in (64, 1000, 10007):
+        x = wl.uniform(n, batch=1, seed=n)
+        plan = oz.Plan(n, 1)
+        y = plan.execute(_gpu(torch, x), direction).cpu().numpy()
+        kp = kplan(n, 3, 3)
+        want = bl.ifft(x[0], plan=kp) if direction == 1 else bl.adjoint(x[0], plan=kp)
+        assert max_ulp(y[0], want) == 0
+
+
+def test_modes_identical_and_uneven_lengths(torch_mod):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    lengths = [1, 3, 1024, 1031, 5000, 4096, 4099, 257, 10007, 2]
+    rng = np.random.default_rng(5)
+    xs = [rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n) for n in lengths]
+    flat = np.concatenate(xs)
+    outs = {}
+    for mode in ("plain", "batched"):
+        plan = oz.Plan(lengths=lengths, mode=mode)
+        outs[mode] = plan.forward(_gpu(torch, flat)).cpu().numpy()
+        # run twice: the graph replay must give the same bits
+        again = plan.forward(_gpu(torch, flat)).cpu().numpy()
+        assert np.array_equal(again.view(np.uint64), outs[mode].view(np.uint64))
+    assert np.array_equal(outs["plain"].view(np.uint64), outs["batched"].view(np.uint64))
+    off = 0
+    for n, x in zip(lengths, xs):
+        want = bl.fft(x, 3, 3, kplan(n, 3, 3))
+        assert max_ulp(outs["batched"][off:off + n], want) == 0, n
+        off += n
+
+
+def test_special_inputs(torch_mod):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 100
+    x = wl.uniform(n, batch=4, seed=3)
+    x[0] = 0
+    x[1, 7] = np.nan
+    x[2] *= 2.0 ** 1000
+    x[3, 5] = 1e-300          # tiny element next to O(1) values: split stops early
+    plan = oz.Plan(n, 4)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    # a zero input gives y' = +0; the postmultiply's IEEE products then carry
+    # the chirp's signs into signed zeros, exactly as in the oracle
+    assert np.all(y[0] == 0)
+    assert np.array_equal(y[0].view(np.uint64), bl.fft(x[0], 3, 3, kplan(n, 3, 3)).view(np.uint64))
+    assert plan.transform_info(1)["status"] == oz_or.STATUS_NONFINITE and np.all(np.isnan(y[1].real))
+    assert plan.transform_info(2)["status"] == oz_or.STATUS_RANGE and np.all(np.isnan(y[2].imag))
+    kp = kplan(n, 3, 3)
+    for b in range(4):
+        tr = bl.forward_trace(x[b], 3, 3, kp)
+        assert plan.transform_info(b)["status"] == tr["status"]
+        assert max_ulp(y[b], tr["y"]) == 0
+
+
+def test_batch_16k_roundtrip(torch_mod):
+    """64 transforms at n = 2^14 (N = 2^15): two sampled transforms compared
+    with the oracle, all 64 round-tripped through the inverse."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = wl.batch_16k(0)
+    plan = oz.Plan(16384, 64)
+    xd = _gpu(torch, x)
+    yd = plan.forward(xd)
+    y = yd.cpu().numpy()
+    kp = kplan(16384, 3, 3)
+    for b in (0, 63):
+        tr = bl.forward_trace(x[b], 3, 3, kp)
+        check_stages(plan, b, tr, kp, 3)       # intermediates of the last execution
+        assert max_ulp(y[b], tr["y"]) == 0
+    z = plan.inverse(yd).cpu().numpy()
+    assert np.max(np.abs(z - x)) < 1e-14
+    assert ref.rel_l2_error(y[5], ref.dft_longdouble(x[5])) < 1e-15
+
+
+def test_batch_prime_10007(torch_mod):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = wl.batch_prime(0)
+    plan = oz.Plan(10007, 64)
+    xd = _gpu(torch, x)
+    yd = plan.forward(xd)
+    y = yd.cpu().numpy()
+    kp = kplan(10007, 3, 3)
+    for b in (0, 31):
+        tr = bl.forward_trace(x[b], 3, 3, kp)
+        check_stages(plan, b, tr, kp, 3)
+        assert max_ulp(y[b], tr["y"]) == 0
+    z = plan.inverse(yd).cpu().numpy()
+    assert np.max(np.abs(z - x)) < 1e-14
