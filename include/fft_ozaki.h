@@ -139,7 +139,8 @@ int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_tr
  * execution to host memory (synchronises the device).  Stages:
  *   1  x' = x (.) w                          double2[n]
  *   2  forward NTTs of the x' slices         uint32[2][K][2][N]  (part, slice, prime; NTT-domain order)
- *   3  inverse NTT outputs per group         uint32[4*K*K][2][n] (slot = conv*K*K + group, prime)
+ *   3  inverse NTT outputs per group         uint32[4*K*K][2][n4] (slot = conv*K*K + group, prime;
+ *                                            n4 = n rounded up to a multiple of 4, first n valid)
  *   4  kernel NTTs times N^{-1}              uint32[2][K][2][N]
  *   5  chirp (cos, sin)                      double2[n]
  * `bytes` must be at least the stage size (FFT_OZAKI_ERR_INVALID otherwise);

@@ -124,6 +124,7 @@ struct TState {
   unsigned char ps[4][MAX_PAIRS], pt[4][MAX_PAIRS];   // walk order pairs (s, t)
   int ngroups[4];
   Group groups[4][MAX_PAIRS];
+  u64 gend[4];             // bit w set: walk pair w closes its group
   int emin[2];             // per output component: smallest group exponent
   int span[2];             // per output component: largest shift above emin
 };
@@ -132,12 +133,12 @@ struct TState {
 struct TDesc {
   int n, N, logN, alpha;
   int kd;                  // index into the KernelDesc array
-  int pad_;
+  int zs;                  // row stride of the compact outputs: n rounded up to a multiple of 4
   i64 io_off;              // element offset of this transform in in/out
   i64 xp_off;              // element offset in the x' buffer (double2)
   i64 X_off;               // u32 offset of the slice/NTT buffer [part][k][prime][N]
   i64 G_off;               // u32 offset of the group buffer [slot][prime][N]
-  i64 Z_off;               // u32 offset of the compact outputs [slot][prime][n]
+  i64 Z_off;               // u32 offset of the compact outputs [slot][prime][zs]
 };
 
 }  // namespace fo

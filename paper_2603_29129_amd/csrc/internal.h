@@ -6,6 +6,7 @@
 namespace fo {
 
 constexpr int NTT_THREADS = 256;
+constexpr int COL_THREADS = 512;     // column passes: 2 x 64 KiB tiles per CU, 16 waves
 
 // Geometry of the NTT of length N = 2^logN: one workgroup block NTT when
 // logN <= LOG2_BLOCK_MAX, else two passes N = N1 * N2 (columns of length N1
@@ -15,7 +16,8 @@ constexpr int NTT_THREADS = 256;
 struct NttGeom {
   int logN, m1, m2;      // N1 = 2^m1, N2 = 2^m2
   int lc;                // log2 of the columns per workgroup (column pass)
-  int lrows;             // log2 of the rows per workgroup (row pass)
+  int lrows;             // log2 of the rows per workgroup (forward row pass)
+  int lrows_inv;         // log2 of the rows per workgroup (inverse row pass, all groups in LDS)
   bool two_pass() const { return m2 > 0; }
 };
 NttGeom ntt_geom(int logN, int lc_override = -1, int lrows_override = -1);
@@ -56,8 +58,9 @@ hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, co
 // Single passes of the above (measurement hook): which = 0 both passes,
 // 1 column pass, 2 row pass (forward); 1 row pass with the fused
 // multiply-accumulate, 2 column pass (inverse).
-hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, int vi_lo,
-                            int vi_hi, const NttGeom& g, const TwBlock& tb, const TwStep& st, int which, hipStream_t s);
+hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K,
+                            bool valid_full, int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb,
+                            const TwStep& st, int which, hipStream_t s);
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
                             const TwBlock& tb, const TwStep& st, int which, hipStream_t s);

@@ -7,19 +7,26 @@
 //    bit-reversed order out); the inverse is its exact mirror, decimation in
 //    time (bit-reversed in, natural out), so no permutation pass is needed:
 //    the pointwise products of the convolution work on bit-reversed data.
-//  * Each thread holds 2^r elements (r <= 4) in registers and performs r
-//    radix-2 stages between LDS exchanges, so a 4096-point transform takes
-//    three LDS round trips.
+//  * Each thread holds 2^r elements (r <= 3) in registers and performs r
+//    radix-2 stages between LDS exchanges (a 512-point transform takes three
+//    LDS round trips); eight registers per group keep the register file
+//    small enough for four to five waves per SIMD.
 //  * Lengths N > 4096 use two passes N = N1 * N2: column transforms of length
 //    N1 (stride N2, a tile of C adjacent columns per workgroup so that global
 //    accesses are C*4 bytes contiguous), the twiddle w_N^{j2 k1}, then
 //    contiguous row transforms of length N2.
+//  * Global traffic uses 16-byte accesses, several in flight per thread
+//    before their LDS writes, so each wave keeps the memory pipe busy.
 //  * Modular products are Shoup multiplications by precomputed constants
 //    (value and floor(w 2^32 / p)); gfx950 issues v_mul_lo_u32 / v_mul_hi_u32
 //    at full rate, so a butterfly is ~11 VALU instructions.
 //  * The convolution's pointwise products and their NTT-domain accumulation
-//    (Alg. 8) are fused into the first inverse pass; N^{-1} is folded into the
-//    precomputed kernel transforms.
+//    (Alg. 8) are fused into the first inverse pass: for four adjacent
+//    positions a thread loads the NTT-domain slices of one input part and of
+//    one kernel part once and forms every group sum of that convolution from
+//    registers.  N^{-1} is folded into the precomputed kernel transforms.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace fo {
@@ -27,50 +34,65 @@ namespace fo {
 __device__ __forceinline__ u32 prime_of(int i) { return i ? P1 : P0; }
 __device__ __forceinline__ u32 bitrev(u32 v, int bits) { return bits ? (__brev(v) >> (32 - bits)) : 0u; }
 
-// LDS addressing of element i of vector v inside a tile.  COLS: vectors are
-// interleaved (element i of all vectors adjacent), used by the column pass.
-// Rows: one vector after another with one pad word every 32 elements.
-__host__ __device__ inline int row_ld(int M) { return M + (M >> 5) + 1; }
+// Row layout of a tile: vector v at v * ldr (ldr = M + 8), element i at
+// swz(i): the 16-byte chunk index inside each 64-word block is XORed with
+// the block index, which keeps 16-byte chunks contiguous (vector LDS access)
+// and spreads the strided accesses of the radix rounds over the LDS banks.
+// Column layout (COLS): element i of all 2^lnvec vectors adjacent.
+__host__ __device__ inline int swz(int i) { return i ^ (((i >> 6) & 15) << 2); }
+__host__ __device__ inline int row_ld(int M) { return M + 8; }
 template <bool COLS>
 __device__ __forceinline__ int laddr(int v, int i, int lnvec, int ldr) {
-  return COLS ? ((i << lnvec) + v) : (v * ldr + i + (i >> 5));
+  return COLS ? ((i << lnvec) + v) : (v * ldr + swz(i));
 }
 
+constexpr int UNR = 4;           // 16-byte global loads in flight per thread
+constexpr int INV_TILE_ROWS = 20;        // group rows per inverse chunk: the 20 groups of K = L = 3 fit, 3 workgroups per CU
+constexpr int KT = 3;            // slices per operand handled from registers in the fused MAC
+
 // r = RL radix-2 stages on the 2^RL registers of one group.  The group holds
-// tile elements base + j*st (j < 2^RL) of a length-2^m vector and the round
-// covers stages s0 .. s0+RL-1 (stage s pairs elements h = 2^(m-s-1) apart).
-// tw[e] = (w_M^e, companion) for e < M/2 (forward or inverse roots).
+// tile elements base + j*st (j < 2^RL, base = blk * 2^RL * st + off, off < st)
+// of a length-2^m vector and the round covers stages s0 .. s0+RL-1.  At stage
+// s the partners are hd = 2^RL >> (s - s0 + 1) registers apart and the pair
+// (j, j + hd) uses w_M^e with e = (off + (j mod hd) * st) << s, so a stage
+// needs only hd distinct roots.  tw[e] = (w_M^e, companion), e < M/2.
 template <int RL, bool INV>
-__device__ __forceinline__ void radix_group(u32 (&a)[1 << RL], int base, int st, int m, int s0,
+__device__ __forceinline__ void radix_group(u32 (&a)[1 << RL], int off, int st, int s0,
                                             const uint2* __restrict__ tw, u32 p) {
   constexpr int R = 1 << RL;
   if (!INV) {
 #pragma unroll
     for (int ss = 0; ss < RL; ++ss) {
-      const int s = s0 + ss;
       const int hd = R >> (ss + 1);
-      const int hmask = (1 << (m - s - 1)) - 1;
+      const int s = s0 + ss;
+      const int eb = off << s, es = st << s;
+      uint2 w[R / 2];
+#pragma unroll
+      for (int jj = 0; jj < hd; ++jj) w[jj] = tw[eb + jj * es];
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         if (j & hd) continue;
-        const uint2 w = tw[((base + j * st) & hmask) << s];
+        const uint2 ww = w[j & (hd - 1)];
         const u32 x = a[j], y = a[j + hd];
         a[j] = add_mod(x, y, p);
-        a[j + hd] = shoup_mul(x + p - y, w.x, w.y, p);   // x - y + p < 2p < 2^32
+        a[j + hd] = shoup_mul(x + p - y, ww.x, ww.y, p);   // x - y + p < 2p < 2^32
       }
     }
   } else {
 #pragma unroll
     for (int ss = RL - 1; ss >= 0; --ss) {
-      const int s = s0 + ss;
       const int hd = R >> (ss + 1);
-      const int hmask = (1 << (m - s - 1)) - 1;
+      const int s = s0 + ss;
+      const int eb = off << s, es = st << s;
+      uint2 w[R / 2];
+#pragma unroll
+      for (int jj = 0; jj < hd; ++jj) w[jj] = tw[eb + jj * es];
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         if (j & hd) continue;
-        const uint2 w = tw[((base + j * st) & hmask) << s];
+        const uint2 ww = w[j & (hd - 1)];
         const u32 x = a[j];
-        const u32 t = shoup_mul(a[j + hd], w.x, w.y, p);
+        const u32 t = shoup_mul(a[j + hd], ww.x, ww.y, p);
         a[j] = add_mod(x, t, p);
         a[j + hd] = sub_mod(x, t, p);
       }
@@ -78,47 +100,69 @@ __device__ __forceinline__ void radix_group(u32 (&a)[1 << RL], int base, int st,
   }
 }
 
+// nv: number of vectors (row layout) or log2 of it (column layout).  In the
+// last round of the row layout a group's registers are contiguous and move
+// as 16-byte LDS accesses.
 template <int RL, bool INV, bool COLS>
-__device__ void ntt_round(u32* lds, int m, int s0, int lnvec, int ldr, const uint2* tw, u32 p) {
+__device__ void ntt_round(u32* lds, int m, int s0, int nv, int ldr, const uint2* tw, u32 p) {
   constexpr int R = 1 << RL;
   const int lbk = m - s0;              // log2 of the block size
   const int lst = lbk - RL;            // log2 of the register stride
   const int st = 1 << lst;
   const int lgpv = m - RL;             // log2 groups per vector
-  const int total = 1 << (lnvec + lgpv);
+  const int total = COLS ? (1 << (nv + lgpv)) : (nv << lgpv);
   for (int g = threadIdx.x; g < total; g += blockDim.x) {
     int v, q;
     if (COLS) {
-      v = g & ((1 << lnvec) - 1);
-      q = g >> lnvec;
+      v = g & ((1 << nv) - 1);
+      q = g >> nv;
     } else {
       v = g >> lgpv;
       q = g & ((1 << lgpv) - 1);
     }
-    const int base = ((q >> lst) << lbk) + (q & (st - 1));
+    const int off = q & (st - 1);
+    const int base = ((q >> lst) << lbk) + off;
     u32 a[R];
+    if (!COLS && R >= 4 && lst == 0) {
+      u32* row = lds + v * ldr;
 #pragma unroll
-    for (int j = 0; j < R; ++j) a[j] = lds[laddr<COLS>(v, base + j * st, lnvec, ldr)];
-    radix_group<RL, INV>(a, base, st, m, s0, tw, p);
+      for (int j = 0; j < R; j += 4) {
+        const uint4 t = *reinterpret_cast<const uint4*>(row + swz(base + j));
+        a[j] = t.x;
+        a[j + 1] = t.y;
+        a[j + 2] = t.z;
+        a[j + 3] = t.w;
+      }
+      radix_group<RL, INV>(a, off, st, s0, tw, p);
 #pragma unroll
-    for (int j = 0; j < R; ++j) lds[laddr<COLS>(v, base + j * st, lnvec, ldr)] = a[j];
+      for (int j = 0; j < R; j += 4) *reinterpret_cast<uint4*>(row + swz(base + j)) = make_uint4(a[j], a[j + 1], a[j + 2], a[j + 3]);
+      continue;
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) a[j] = lds[laddr<COLS>(v, base + j * st, nv, ldr)];
+    radix_group<RL, INV>(a, off, st, s0, tw, p);
+#pragma unroll
+    for (int j = 0; j < R; ++j) lds[laddr<COLS>(v, base + j * st, nv, ldr)] = a[j];
   }
 }
 
-// In-place block NTT of 2^lnvec vectors of length 2^m held in LDS.  The caller
-// synchronises after filling the tile; this routine ends synchronised.
+// In-place block NTT of the vectors of a tile (length 2^m each).  The m
+// radix-2 stages are spread evenly over ceil(m/3) rounds of at most three
+// stages (eight registers per group).  The caller synchronises after
+// filling the tile; this routine ends synchronised.
 template <bool INV, bool COLS>
-__device__ void block_ntt(u32* lds, int m, int lnvec, int ldr, const uint2* tw, u32 p) {
-  const int nr = (m + 3) >> 2;
+__device__ void block_ntt(u32* lds, int m, int nv, int ldr, const uint2* tw, u32 p) {
+  if (m == 0) return;
+  const int nr = (m + 2) / 3;
+  const int rb = m / nr, rx = m % nr;          // the first rx rounds take rb + 1 stages
   for (int rr = 0; rr < nr; ++rr) {
     const int round = INV ? (nr - 1 - rr) : rr;
-    const int s0 = round << 2;
-    const int r = min(4, m - s0);
+    const int s0 = round * rb + min(round, rx);
+    const int r = rb + (round < rx ? 1 : 0);
     switch (r) {
-      case 4: ntt_round<4, INV, COLS>(lds, m, s0, lnvec, ldr, tw, p); break;
-      case 3: ntt_round<3, INV, COLS>(lds, m, s0, lnvec, ldr, tw, p); break;
-      case 2: ntt_round<2, INV, COLS>(lds, m, s0, lnvec, ldr, tw, p); break;
-      default: ntt_round<1, INV, COLS>(lds, m, s0, lnvec, ldr, tw, p); break;
+      case 3: ntt_round<3, INV, COLS>(lds, m, s0, nv, ldr, tw, p); break;
+      case 2: ntt_round<2, INV, COLS>(lds, m, s0, nv, ldr, tw, p); break;
+      default: ntt_round<1, INV, COLS>(lds, m, s0, nv, ldr, tw, p); break;
     }
     __syncthreads();
   }
@@ -131,74 +175,202 @@ __device__ __forceinline__ void load_block_tw(uint2* tw, const uint2* __restrict
   for (int e = threadIdx.x; e < half; e += blockDim.x) tw[e] = src[e << (LOG2_BLOCK_MAX - m)];
 }
 
-// w_N^e (forward or inverse) applied to x, e < N.
-__device__ __forceinline__ u32 step_twiddle(u32 x, u32 e, const uint2* __restrict__ lo,
-                                            const uint2* __restrict__ hi, u32 p) {
-  const uint2 a = lo[e & 4095u];
-  x = shoup_mul(x, a.x, a.y, p);
-  const uint2 b = hi[e >> 12];
-  return shoup_mul(x, b.x, b.y, p);
+// floor(v 2^32 / p) for v < p, exactly: a binary64 estimate (off by at most
+// one) corrected with an exact 64-bit remainder.
+__device__ __forceinline__ u32 companion_dev(u32 v, u32 p) {
+  u32 c = (u32)((double)v * (4294967296.0 / (double)p));
+  long long r = (long long)(((u64)v << 32) - (u64)c * p);
+  while (r < 0) { --c; r += p; }
+  while (r >= (long long)p) { ++c; r -= p; }
+  return c;
+}
+
+// (w_N^e, companion) from the two-level step tables.
+__device__ __forceinline__ uint2 step_root(u32 e, const uint2* __restrict__ lo, const uint2* __restrict__ hi, u32 p) {
+  const uint2 a = lo[e & 4095u], b = hi[e >> 12];
+  const u32 v = shoup_mul(a.x, b.x, b.y, p);
+  return make_uint2(v, companion_dev(v, p));
+}
+
+// Twiddles of a row pass: rows r < nr of the tile are rows i1_0 + r of the
+// N1 x N2 matrix, with k1 = br(i1_0 + r); element j2 of row r is multiplied
+// by w_N^{j2 k1} (forward) or its inverse.  With j2 = jh 2^lb + jl the root
+// factors as A_r[jl] * B_r[jh]; both small tables live in LDS with their
+// Shoup companions (A: nr << lb entries, B: nr << (m2 - lb) entries).
+struct RowTw {
+  uint2* A;
+  uint2* B;
+  int lb;
+};
+__host__ __device__ inline int rowtw_lb(int m2) { return m2 < 6 ? m2 : 6; }
+__host__ __device__ inline int rowtw_words(int m2, int nr) {
+  const int lb = rowtw_lb(m2);
+  return 2 * ((nr << lb) + (nr << (m2 - lb)));
+}
+__device__ void build_rowtw(RowTw& t, u32* mem, int nr, int i1_0, int m1, int m2, u32 Nmask,
+                            const uint2* __restrict__ lo, const uint2* __restrict__ hi, u32 p) {
+  t.lb = rowtw_lb(m2);
+  t.A = reinterpret_cast<uint2*>(mem);
+  t.B = t.A + (nr << t.lb);
+  const int na = nr << t.lb, nb = nr << (m2 - t.lb);
+  for (int i = threadIdx.x; i < na + nb; i += blockDim.x) {
+    if (i < na) {
+      const int r = i >> t.lb, jl = i & ((1 << t.lb) - 1);
+      t.A[i] = step_root(((u32)jl * bitrev(i1_0 + r, m1)) & Nmask, lo, hi, p);
+    } else {
+      const int k = i - na, r = k >> (m2 - t.lb), jh = k & ((1 << (m2 - t.lb)) - 1);
+      t.B[k] = step_root(((u32)(jh << t.lb) * bitrev(i1_0 + r, m1)) & Nmask, lo, hi, p);
+    }
+  }
+}
+__device__ __forceinline__ u32 apply_rowtw(const RowTw& t, u32 x, int r, int j2, int m2, u32 p) {
+  const uint2 a = t.A[(r << t.lb) + (j2 & ((1 << t.lb) - 1))];
+  const uint2 b = t.B[(r << (m2 - t.lb)) + (j2 >> t.lb)];
+  return shoup_mul(shoup_mul(x, a.x, a.y, p), b.x, b.y, p);
+}
+
+__device__ __forceinline__ uint4 zero_from(uint4 w, int e, int valid) {
+  if (e + 3 >= valid) {
+    if (e >= valid) w.x = 0;
+    if (e + 1 >= valid) w.y = 0;
+    if (e + 2 >= valid) w.z = 0;
+    w.w = 0;
+  }
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// Tile movers.
+
+// `nrows` rows of M = 2^m words (row r at src + r*M) into tile rows 0..nrows-1;
+// flattened positions >= valid read as zero.
+__device__ void load_rows(u32* tile, const u32* __restrict__ src, int nrows, int m, int ldr, int valid) {
+  const int M = 1 << m;
+  if (m < 2) {
+    for (int e = threadIdx.x; e < (nrows << m); e += blockDim.x)
+      tile[(e >> m) * ldr + swz(e & (M - 1))] = e < valid ? src[e] : 0u;
+    return;
+  }
+  const int tot4 = (nrows << m) >> 2;
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  for (int q0 = threadIdx.x; q0 < tot4; q0 += blockDim.x * UNR) {
+    uint4 v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * blockDim.x;
+      if (q < tot4) v[u] = (q << 2) < valid ? s4[q] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * blockDim.x;
+      if (q < tot4) {
+        const int e = q << 2;
+        *reinterpret_cast<uint4*>(tile + (e >> m) * ldr + swz(e & (M - 1))) = zero_from(v[u], e, valid);
+      }
+    }
+  }
+}
+
+__device__ void store_rows(u32* __restrict__ dst, const u32* tile, int nrows, int m, int ldr) {
+  const int M = 1 << m;
+  if (m < 2) {
+    for (int e = threadIdx.x; e < (nrows << m); e += blockDim.x) dst[e] = tile[(e >> m) * ldr + swz(e & (M - 1))];
+    return;
+  }
+  const int tot4 = (nrows << m) >> 2;
+  uint4* d4 = reinterpret_cast<uint4*>(dst);
+  for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
+    const int e = q << 2;
+    d4[q] = *reinterpret_cast<const uint4*>(tile + (e >> m) * ldr + swz(e & (M - 1)));
+  }
+}
+
+// Columns [j2_0, j2_0 + 2^lc) of a 2^m1 x 2^m2 row-major vector into the
+// column-layout tile; positions >= valid read as zero.  Needs lc >= 2.
+__device__ void load_cols(u32* tile, const u32* __restrict__ vec, int m1, int m2, int lc, int j2_0, int valid) {
+  const int lq = lc - 2;
+  const int tot4 = 1 << (m1 + lq);
+  for (int q0 = threadIdx.x; q0 < tot4; q0 += blockDim.x * UNR) {
+    uint4 v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * blockDim.x;
+      if (q < tot4) {
+        const int i = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+        const int gi = (i << m2) + j2_0 + c4;
+        v[u] = gi < valid ? *reinterpret_cast<const uint4*>(vec + gi) : make_uint4(0, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * blockDim.x;
+      if (q < tot4) {
+        const int i = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+        const int gi = (i << m2) + j2_0 + c4;
+        *reinterpret_cast<uint4*>(tile + (i << lc) + c4) = zero_from(v[u], gi, valid);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Transform bodies shared by the pipeline and the standalone kernels.
 
-// Forward column pass on vector `vec` (elements >= valid read as zero).
-__device__ void fwd_cols_body(u32* vec, int valid, int prime, const NttGeom g, int j2_0,
-                              const uint2* twb, const uint2* lo, const uint2* hi, u32* smem) {
+// Forward column pass on vector `vec` (elements >= valid read as zero),
+// written back in place; the twiddle w_N^{j2 k1} is applied by the row pass.
+__device__ void fwd_cols_body(u32* vec, int valid, int prime, const NttGeom g, int j2_0, const uint2* twb, u32* smem) {
   const u32 p = prime_of(prime);
-  const int m1 = g.m1, N2 = 1 << g.m2, lc = g.lc, C = 1 << lc;
-  const u32 Nmask = (1u << g.logN) - 1;
+  const int m1 = g.m1, m2 = g.m2, lc = g.lc, lq = lc - 2;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + (1 << m1);
   load_block_tw(tw, twb, m1);
-  const int tot = C << m1;
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int c = idx & (C - 1), i1 = idx >> lc;
-    const int gi = i1 * N2 + j2_0 + c;
-    tile[idx] = gi < valid ? vec[gi] : 0u;
-  }
+  load_cols(tile, vec, m1, m2, lc, j2_0, valid);
   __syncthreads();
   block_ntt<false, true>(tile, m1, lc, 0, tw, p);
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int c = idx & (C - 1), i1 = idx >> lc;
-    const u32 e = ((u32)(j2_0 + c) * bitrev(i1, m1)) & Nmask;
-    vec[i1 * N2 + j2_0 + c] = step_twiddle(tile[idx], e, lo, hi, p);
+  const int tot4 = 1 << (m1 + lq);
+  for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
+    const int i = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+    *reinterpret_cast<uint4*>(vec + (i << m2) + j2_0 + c4) = *reinterpret_cast<const uint4*>(tile + (i << lc) + c4);
   }
 }
 
-// Forward row pass: rows [i1_0, i1_0 + 2^lrows) of vector vec.
-__device__ void fwd_rows_body(u32* vec, int prime, const NttGeom g, int i1_0, const uint2* twb, u32* smem) {
+// Forward row pass: rows [i1_0, i1_0 + 2^lrows) of vector vec, each element
+// first multiplied by w_N^{j2 k1}.
+__device__ void fwd_rows_body(u32* vec, int prime, const NttGeom g, int i1_0, const uint2* twb,
+                              const uint2* lo, const uint2* hi, u32* smem) {
   const u32 p = prime_of(prime);
-  const int m2 = g.m2, N2 = 1 << m2, lr = g.lrows, ldr = row_ld(N2);
+  const int m2 = g.m2, N2 = 1 << m2, ldr = row_ld(N2), nr = 1 << g.lrows;
+  const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + N2;
+  u32* twmem = tile + nr * ldr;
   load_block_tw(tw, twb, m2);
-  const int tot = N2 << lr;
-  u32* src = vec + (size_t)i1_0 * N2;
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int r = idx >> m2, i = idx & (N2 - 1);
-    tile[r * ldr + i + (i >> 5)] = src[idx];
+  RowTw rt;
+  build_rowtw(rt, twmem, nr, i1_0, g.m1, m2, Nmask, lo, hi, p);
+  u32* src = vec + ((size_t)i1_0 << m2);
+  load_rows(tile, src, nr, m2, ldr, 1 << 30);
+  __syncthreads();
+  for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x) {
+    const int r = e >> m2, j2 = e & (N2 - 1);
+    u32* q = tile + r * ldr + swz(j2);
+    *q = apply_rowtw(rt, *q, r, j2, m2, p);
   }
   __syncthreads();
-  block_ntt<false, false>(tile, m2, lr, ldr, tw, p);
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int r = idx >> m2, i = idx & (N2 - 1);
-    src[idx] = tile[r * ldr + i + (i >> 5)];
-  }
+  block_ntt<false, false>(tile, m2, nr, ldr, tw, p);
+  store_rows(src, tile, nr, m2, ldr);
 }
 
 // Forward single-workgroup transform of a vector of length 2^logN <= 4096.
 __device__ void fwd_single_body(u32* vec, int valid, int prime, int logN, const uint2* twb, u32* smem) {
   const u32 p = prime_of(prime);
-  const int N = 1 << logN, ldr = row_ld(N);
+  const int ldr = row_ld(1 << logN);
   uint2* tw = reinterpret_cast<uint2*>(smem);
-  u32* tile = smem + N;
+  u32* tile = smem + (1 << logN);
   load_block_tw(tw, twb, logN);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) tile[i + (i >> 5)] = i < valid ? vec[i] : 0u;
+  load_rows(tile, vec, 1, logN, ldr, valid);
   __syncthreads();
-  block_ntt<false, false>(tile, logN, 0, ldr, tw, p);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) vec[i] = tile[i + (i >> 5)];
+  block_ntt<false, false>(tile, logN, 1, ldr, tw, p);
+  store_rows(vec, tile, 1, logN, ldr);
 }
 
 // ---------------------------------------------------------------------------
@@ -218,24 +390,24 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int logN,
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + N;
   load_block_tw(tw, tb.inv[prime], logN);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) tile[i + (i >> 5)] = vec[i];
+  load_rows(tile, vec, 1, logN, ldr, N);
   __syncthreads();
-  block_ntt<true, false>(tile, logN, 0, ldr, tw, p);
+  block_ntt<true, false>(tile, logN, 1, ldr, tw, p);
   // N^{-1} = p - (p-1)/N
   const u32 ninv = p - ((p - 1) >> logN), ninvq = shoup_companion(ninv, p);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) vec[i] = shoup_mul(tile[i + (i >> 5)], ninv, ninvq, p);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) vec[i] = shoup_mul(tile[swz(i)], ninv, ninvq, p);
 }
 
-__global__ void __launch_bounds__(NTT_THREADS) k_std_fwd_cols(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
+__global__ void __launch_bounds__(COL_THREADS) k_std_fwd_cols(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
   extern __shared__ u32 smem[];
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
-  fwd_cols_body(vec, 1 << g.logN, prime, g, blockIdx.x << g.lc, tb.fwd[prime], ts.lo[0][prime], ts.hi[0][prime], smem);
+  fwd_cols_body(vec, 1 << g.logN, prime, g, blockIdx.x << g.lc, tb.fwd[prime], smem);
 }
 
-__global__ void __launch_bounds__(NTT_THREADS) k_std_fwd_rows(u32* data, int prime, NttGeom g, TwBlock tb) {
+__global__ void __launch_bounds__(NTT_THREADS) k_std_fwd_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
   extern __shared__ u32 smem[];
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
-  fwd_rows_body(vec, prime, g, blockIdx.x << g.lrows, tb.fwd[prime], smem);
+  fwd_rows_body(vec, prime, g, blockIdx.x << g.lrows, tb.fwd[prime], ts.lo[0][prime], ts.hi[0][prime], smem);
 }
 
 // Inverse row pass (standalone): DIT rows then w_N^{-j2 k1}.
@@ -243,48 +415,48 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int pri
   extern __shared__ u32 smem[];
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   const u32 p = prime_of(prime);
-  const int m2 = g.m2, N2 = 1 << m2, lr = g.lrows, ldr = row_ld(N2);
+  const int m2 = g.m2, N2 = 1 << m2, nr = 1 << g.lrows, ldr = row_ld(N2);
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + N2;
+  u32* twmem = tile + nr * ldr;
   load_block_tw(tw, tb.inv[prime], m2);
-  const int i1_0 = blockIdx.x << lr;
-  const int tot = N2 << lr;
-  u32* src = vec + (size_t)i1_0 * N2;
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int r = idx >> m2, i = idx & (N2 - 1);
-    tile[r * ldr + i + (i >> 5)] = src[idx];
-  }
+  const int i1_0 = blockIdx.x << g.lrows;
+  RowTw rt;
+  build_rowtw(rt, twmem, nr, i1_0, g.m1, m2, Nmask, ts.lo[1][prime], ts.hi[1][prime], p);
+  u32* src = vec + ((size_t)i1_0 << m2);
+  load_rows(tile, src, nr, m2, ldr, 1 << 30);
   __syncthreads();
-  block_ntt<true, false>(tile, m2, lr, ldr, tw, p);
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+  block_ntt<true, false>(tile, m2, nr, ldr, tw, p);
+  for (int idx = threadIdx.x; idx < (nr << m2); idx += blockDim.x) {
     const int r = idx >> m2, j2 = idx & (N2 - 1);
-    const u32 e = ((u32)j2 * bitrev(i1_0 + r, g.m1)) & Nmask;
-    src[idx] = step_twiddle(tile[r * ldr + j2 + (j2 >> 5)], e, ts.lo[1][prime], ts.hi[1][prime], p);
+    src[idx] = apply_rowtw(rt, tile[r * ldr + swz(j2)], r, j2, m2, p);
   }
 }
 
 // Inverse column pass (standalone): DIT columns, times N^{-1}, natural order.
-__global__ void __launch_bounds__(NTT_THREADS) k_std_inv_cols(u32* data, int prime, NttGeom g, TwBlock tb) {
+__global__ void __launch_bounds__(COL_THREADS) k_std_inv_cols(u32* data, int prime, NttGeom g, TwBlock tb) {
   extern __shared__ u32 smem[];
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   const u32 p = prime_of(prime);
-  const int m1 = g.m1, N2 = 1 << g.m2, lc = g.lc, C = 1 << lc;
+  const int m1 = g.m1, m2 = g.m2, lc = g.lc, lq = lc - 2;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + (1 << m1);
   load_block_tw(tw, tb.inv[prime], m1);
   const int j2_0 = blockIdx.x << lc;
-  const int tot = C << m1;
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int c = idx & (C - 1), i1 = idx >> lc;
-    tile[idx] = vec[i1 * N2 + j2_0 + c];
-  }
+  load_cols(tile, vec, m1, m2, lc, j2_0, 1 << 30);
   __syncthreads();
   block_ntt<true, true>(tile, m1, lc, 0, tw, p);
   const u32 ninv = p - ((p - 1) >> g.logN), ninvq = shoup_companion(ninv, p);
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int c = idx & (C - 1), i1 = idx >> lc;
-    vec[i1 * N2 + j2_0 + c] = shoup_mul(tile[idx], ninv, ninvq, p);
+  const int tot4 = 1 << (m1 + lq);
+  for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
+    const int i = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+    uint4 w = *reinterpret_cast<const uint4*>(tile + (i << lc) + c4);
+    w.x = shoup_mul(w.x, ninv, ninvq, p);
+    w.y = shoup_mul(w.y, ninv, ninvq, p);
+    w.z = shoup_mul(w.z, ninv, ninvq, p);
+    w.w = shoup_mul(w.w, ninv, ninvq, p);
+    *reinterpret_cast<uint4*>(vec + (i << m2) + j2_0 + c4) = w;
   }
 }
 
@@ -318,123 +490,300 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_single(u32* X, const TDesc*
   fwd_single_body(o.vec, o.valid, o.prime, logN, tb.fwd[o.prime], smem);
 }
 
-__global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(u32* X, const TDesc* td, const TState* ts,
+__global__ void __launch_bounds__(COL_THREADS) k_fwd_cols(u32* X, const TDesc* td, const TState* ts,
                                                           const int* tlist, int K, bool valid_full, int vi_lo,
                                                           NttGeom g, TwBlock tb, TwStep st) {
   extern __shared__ u32 smem[];
   FwdSel o;
   if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
-  fwd_cols_body(o.vec, o.valid, o.prime, g, blockIdx.x << g.lc, tb.fwd[o.prime], st.lo[0][o.prime],
-                st.hi[0][o.prime], smem);
+  fwd_cols_body(o.vec, o.valid, o.prime, g, blockIdx.x << g.lc, tb.fwd[o.prime], smem);
 }
 
 __global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(u32* X, const TDesc* td, const TState* ts,
                                                           const int* tlist, int K, bool valid_full, int vi_lo,
-                                                          NttGeom g, TwBlock tb) {
+                                                          NttGeom g, TwBlock tb, TwStep st) {
   extern __shared__ u32 smem[];
   FwdSel o;
   if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
-  fwd_rows_body(o.vec, o.prime, g, blockIdx.x << g.lrows, tb.fwd[o.prime], smem);
+  fwd_rows_body(o.vec, o.prime, g, blockIdx.x << g.lrows, tb.fwd[o.prime], st.lo[0][o.prime], st.hi[0][o.prime], smem);
 }
 
 // The four real convolutions (Sec. 4.5): input part pa with kernel part pb.
 __device__ __constant__ int c_conv_pa[4] = {0, 1, 1, 0};
 __device__ __constant__ int c_conv_pb[4] = {0, 1, 0, 1};
 
-// Accumulates sum over the pairs of group (c, g) of X_pa^s (.) W_pb^t at
-// NTT-domain position idx (Alg. 8, NTT-domain accumulation).
-__device__ __forceinline__ u32 group_mac(const u32* __restrict__ Xb, const u32* __restrict__ Wb,
-                                         const u32* __restrict__ Wqb, const TState& s, int c, const Group& gr,
-                                         int K, int prime, int logN, size_t idx, u32 p) {
-  const int pa = c_conv_pa[c], pb = c_conv_pb[c];
-  u32 acc = 0;
-  for (int w = gr.start; w < gr.start + gr.count; ++w) {
-    const int ss = s.ps[c][w], tt = s.pt[c][w];
-    const size_t xo = ((size_t)((pa * K + ss) * 2 + prime) << logN) + idx;
-    const size_t wo = ((size_t)((pb * K + tt) * 2 + prime) << logN) + idx;
-    acc = add_mod(acc, shoup_mul(Xb[xo], Wb[wo], Wqb[wo], p), p);
-  }
-  return acc;
+// NTT-domain multiply-accumulate (Alg. 8) at the two positions e, e+1 of
+// the NTT domain: every group sum
+//     Z_g = sum over the pairs (s, t) of g of X_pa^s (.) W_pb^t   (mod p).
+// Groups are numbered across the convolutions (group g of convolution c has
+// number gofs[c] + g); those in [g0, g1) are written to LDS at
+// lds0 + (number - g0) * rstride.  Pairs are visited in Alg. 8's walk order
+// (anti-diagonals s + t from the last down to 0, s ascending) and `gend`
+// marks the pair closing each group.  With at most KT slices per operand
+// the slices of the two positions are loaded once into registers and every
+// convolution is formed from them.
+struct MacArgs {
+  const u32* X;      // this transform's slice spectra, [part][k][prime][N]
+  const u32* W;      // kernel spectra of its length, same layout
+  const u32* Wq;
+  int K, logN, prime;
+  u32 p;
+  int kw0, kw1;      // kernel slice counts of Re w*, Im w*
+};
+
+__device__ __forceinline__ uint2 ld2(const u32* ptr) { return *reinterpret_cast<const uint2*>(ptr); }
+
+__device__ __forceinline__ void mac_acc(uint2& acc, const uint2& x, const uint2& w, const uint2& q, u32 p) {
+  acc.x = add_mod(acc.x, shoup_mul(x.x, w.x, q.x, p), p);
+  acc.y = add_mod(acc.y, shoup_mul(x.y, w.y, q.y, p), p);
 }
 
-// Single-workgroup inverse (N <= 4096): blockIdx.y = conv*2 + prime.
+// one convolution from register-held slices (kA, kB <= KT)
+__device__ __forceinline__ void walk_regs(const uint2 (&xv)[KT], const uint2 (&wv)[KT], const uint2 (&qv)[KT], int kA,
+                                          int kB, u64 gend, int gbase, int g0, int g1, u32* lds0, int rstride, u32 p) {
+  int w = 0, g = gbase;
+  uint2 acc = make_uint2(0, 0);
+#pragma unroll
+  for (int d = 2 * KT - 2; d >= 0; --d) {
+#pragma unroll
+    for (int ss = (d - KT + 1 > 0 ? d - KT + 1 : 0); ss <= (KT - 1 < d ? KT - 1 : d); ++ss) {
+      const int tt = d - ss;
+      if (ss < kA && tt < kB) {
+        mac_acc(acc, xv[ss], wv[tt], qv[tt], p);
+        if ((gend >> w) & 1) {
+          if (g >= g0 && g < g1) *reinterpret_cast<uint2*>(lds0 + (g - g0) * rstride) = acc;
+          acc = make_uint2(0, 0);
+          ++g;
+        }
+        ++w;
+      }
+    }
+  }
+}
+
+// one convolution with operands read per pair (any slice counts)
+__device__ void walk_mem(const MacArgs& a, const TState& s, int c, int gbase, int g0, int g1, size_t e, u32* lds0,
+                         int rstride) {
+  const int pa = c_conv_pa[c], pb = c_conv_pb[c];
+  const size_t N = (size_t)1 << a.logN, sstride = 2 * N;
+  const u32* xb = a.X + (size_t)((pa * a.K) * 2 + a.prime) * N + e;
+  const u32* wb = a.W + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
+  const u32* qb = a.Wq + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
+  const u64 gend = s.gend[c];
+  int g = gbase;
+  uint2 acc = make_uint2(0, 0);
+  for (int w = 0; w < s.npairs[c]; ++w) {
+    const int ss = s.ps[c][w], tt = s.pt[c][w];
+    mac_acc(acc, ld2(xb + ss * sstride), ld2(wb + tt * sstride), ld2(qb + tt * sstride), a.p);
+    if ((gend >> w) & 1) {
+      if (g >= g0 && g < g1) *reinterpret_cast<uint2*>(lds0 + (g - g0) * rstride) = acc;
+      acc = make_uint2(0, 0);
+      ++g;
+    }
+  }
+}
+
+// Convolutions [c_lo, c_hi] at positions e, e+1 (e even).
+__device__ void mac_pair(const MacArgs& a, const TState& s, int c_lo, int c_hi, const int (&gofs)[4], int g0, int g1,
+                         size_t e, u32* lds0, int rstride) {
+  const size_t N = (size_t)1 << a.logN, sstride = 2 * N;
+  const int kx0 = s.kx[0], kx1 = s.kx[1];
+  if (kx0 <= KT && kx1 <= KT && a.kw0 <= KT && a.kw1 <= KT) {
+    uint2 w0[KT], q0[KT], w1[KT], q1[KT], xv[KT];
+    const u32* wb = a.W + (size_t)a.prime * N + e;
+    const u32* qb = a.Wq + (size_t)a.prime * N + e;
+    const size_t part = (size_t)a.K * sstride;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (k < a.kw0) {
+        w0[k] = ld2(wb + k * sstride);
+        q0[k] = ld2(qb + k * sstride);
+      }
+      if (k < a.kw1) {
+        w1[k] = ld2(wb + part + k * sstride);
+        q1[k] = ld2(qb + part + k * sstride);
+      }
+    }
+    const u32* xb = a.X + (size_t)a.prime * N + e;
+    // Re x' feeds ReRe (0) and ReIm (3); Im x' feeds ImIm (1) and ImRe (2)
+    if (c_lo <= 0 || c_hi >= 3) {
+#pragma unroll
+      for (int k = 0; k < KT; ++k)
+        if (k < kx0) xv[k] = ld2(xb + k * sstride);
+      if (c_lo <= 0 && 0 <= c_hi) walk_regs(xv, w0, q0, kx0, a.kw0, s.gend[0], gofs[0], g0, g1, lds0, rstride, a.p);
+      if (c_lo <= 3 && 3 <= c_hi) walk_regs(xv, w1, q1, kx0, a.kw1, s.gend[3], gofs[3], g0, g1, lds0, rstride, a.p);
+    }
+    if (c_lo <= 2 && c_hi >= 1) {
+#pragma unroll
+      for (int k = 0; k < KT; ++k)
+        if (k < kx1) xv[k] = ld2(xb + part + k * sstride);
+      if (c_lo <= 1 && 1 <= c_hi) walk_regs(xv, w1, q1, kx1, a.kw1, s.gend[1], gofs[1], g0, g1, lds0, rstride, a.p);
+      if (c_lo <= 2 && 2 <= c_hi) walk_regs(xv, w0, q0, kx1, a.kw0, s.gend[2], gofs[2], g0, g1, lds0, rstride, a.p);
+    }
+    return;
+  }
+  for (int c = c_lo; c <= c_hi; ++c) walk_mem(a, s, c, gofs[c], g0, g1, e, lds0, rstride);
+}
+
+// Scalar variant for vectors of length 1.
+__device__ void mac_single(const MacArgs& a, const TState& s, int c_lo, int c_hi, const int (&gofs)[4], int g0, int g1,
+                           size_t e, u32* lds0, int rstride) {
+  const size_t N = (size_t)1 << a.logN;
+  for (int c = c_lo; c <= c_hi; ++c) {
+    const int pa = c_conv_pa[c], pb = c_conv_pb[c];
+    const u32* xb = a.X + (size_t)((pa * a.K) * 2 + a.prime) * N + e;
+    const u32* wb = a.W + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
+    const u32* qb = a.Wq + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
+    const u64 gend = s.gend[c];
+    u32 acc = 0;
+    int g = gofs[c];
+    for (int w = 0; w < s.npairs[c]; ++w) {
+      const int ss = s.ps[c][w], tt = s.pt[c][w];
+      acc = add_mod(acc, shoup_mul(xb[ss * 2 * N], wb[tt * 2 * N], qb[tt * 2 * N], a.p), a.p);
+      if ((gend >> w) & 1) {
+        if (g >= g0 && g < g1) lds0[(g - g0) * rstride] = acc;
+        acc = 0;
+        ++g;
+      }
+    }
+  }
+}
+
+// Rows of the group tile that fit the inverse's LDS budget.
+// (about 512 words each; longer rows get proportionally fewer)
+__host__ __device__ inline int inv_vmax(int m) {
+  const int v = m <= 9 ? INV_TILE_ROWS : (INV_TILE_ROWS >> (m - 9));
+  return v < 1 ? 1 : v;
+}
+
+// Workgroup index -> (tile, prime, transform).  When the tile-prime pairs
+// divide evenly over the eight XCDs (workgroups are dispatched to XCDs
+// round-robin), consecutive workgroups of one XCD take the same tile of
+// consecutive transforms, so the kernel spectra they share stay in that
+// XCD's L2.
+__device__ __forceinline__ void decode_tile(int L, int pairs, int count, int& pair, int& b) {
+  if ((pairs & 7) == 0) {
+    const int xcd = L & 7, r = L >> 3;
+    b = r % count;
+    pair = (r / count) * 8 + xcd;
+  } else {
+    b = L / pairs;
+    pair = L % pairs;
+  }
+}
+
+// Single-workgroup inverse (N <= 4096): one workgroup per (transform, prime,
+// convolution).  For each chunk of groups: multiply-accumulate into LDS
+// rows, inverse block NTTs, first n outputs to the compact buffer.
 __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z, const TDesc* td, const TState* ts,
-                                                            const KernelDesc* kd, const int* tlist, int K,
+                                                            const KernelDesc* kd, const int* tlist, int count, int K,
                                                             int slot_lo, int slot_hi, int logN, TwBlock tb) {
   extern __shared__ u32 smem[];
-  const int t = tlist[blockIdx.z];
+  int pair, b;
+  decode_tile(blockIdx.x, 8, count, pair, b);
+  const int t = tlist[b];
   const TDesc& d = td[t];
   const TState& s = ts[t];
   if (s.status) return;
-  const int c = blockIdx.y >> 1, prime = blockIdx.y & 1;
+  const int c = pair >> 1, prime = pair & 1;
+  const int ng = s.ngroups[c];
+  if (ng == 0) return;
   const u32 p = prime_of(prime);
   const KernelDesc& kk = kd[d.kd];
-  const int N = 1 << logN, ldr = row_ld(N), SL = K * K;
+  const int N = 1 << logN, ldr = row_ld(N), SL = K * K, vmax = inv_vmax(logN);
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + N;
   load_block_tw(tw, tb.inv[prime], logN);
-  const u32* Xb = X + d.X_off;
-  for (int gidx = 0; gidx < s.ngroups[c]; ++gidx) {
-    const int slot = c * SL + gidx;
-    if (slot < slot_lo || slot >= slot_hi) continue;
-    const Group gr = s.groups[c][gidx];
-    for (int i = threadIdx.x; i < N; i += blockDim.x)
-      tile[i + (i >> 5)] = group_mac(Xb, kk.W, kk.Wq, s, c, gr, K, prime, logN, i, p);
+  const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, logN, prime, p, kk.kw[0], kk.kw[1]};
+  const int gofs[4] = {0, 0, 0, 0};
+  for (int g0 = 0; g0 < ng; g0 += vmax) {
+    const int g1 = min(ng, g0 + vmax);
+    if (c * SL + g1 <= slot_lo || c * SL + g0 >= slot_hi) continue;
+    if (logN >= 1) {
+      for (int q = threadIdx.x; q < (N >> 1); q += blockDim.x)
+        mac_pair(ma, s, c, c, gofs, g0, g1, (size_t)q << 1, tile + swz(q << 1), ldr);
+    } else {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) mac_single(ma, s, c, c, gofs, g0, g1, i, tile + swz(i), ldr);
+    }
     __syncthreads();
-    block_ntt<true, false>(tile, logN, 0, ldr, tw, p);
-    u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.n;
-    for (int i = threadIdx.x; i < d.n; i += blockDim.x) zo[i] = tile[i + (i >> 5)];
+    block_ntt<true, false>(tile, logN, g1 - g0, ldr, tw, p);
+    for (int gi = g0; gi < g1; ++gi) {
+      const int slot = c * SL + gi;
+      if (slot < slot_lo || slot >= slot_hi) continue;
+      u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.zs;
+      const u32* row = tile + (gi - g0) * ldr;
+      for (int i = threadIdx.x; i < d.n; i += blockDim.x) zo[i] = row[swz(i)];
+    }
     __syncthreads();
   }
 }
 
-// Two-pass inverse, first pass (rows): blockIdx.x = row tile, blockIdx.y = prime.
+// Two-pass inverse, first pass (rows): one workgroup per (row tile, prime,
+// transform).  For each chunk of groups (normally all groups of the four
+// convolutions at once): multiply-accumulate into LDS, inverse row NTTs,
+// twiddle w_N^{-j2 k1}, store the group rows.
 __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, const TDesc* td, const TState* ts,
-                                                          const KernelDesc* kd, const int* tlist, int K,
+                                                          const KernelDesc* kd, const int* tlist, int count, int K,
                                                           int slot_lo, int slot_hi, NttGeom g, TwBlock tb,
                                                           TwStep st) {
   extern __shared__ u32 smem[];
-  const int t = tlist[blockIdx.z];
+  int pair, b;
+  decode_tile(blockIdx.x, 2 << (g.m1 - g.lrows_inv), count, pair, b);
+  const int t = tlist[b];
   const TDesc& d = td[t];
   const TState& s = ts[t];
   if (s.status) return;
-  const int prime = blockIdx.y;
+  const int prime = pair & 1;
   const u32 p = prime_of(prime);
   const KernelDesc& kk = kd[d.kd];
-  const int m2 = g.m2, N2 = 1 << m2, lr = g.lrows, ldr = row_ld(N2), SL = K * K;
+  const int m2 = g.m2, N2 = 1 << m2, nr = 1 << g.lrows_inv, ldr = row_ld(N2), SL = K * K;
+  const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);
-  u32* tile = smem + N2;
+  uint2* rtw = tw + (N2 >> 1);                                // w_N^{-j2 k1} per tile element
+  u32* tile = smem + N2 + 2 * (nr << m2);
   load_block_tw(tw, tb.inv[prime], m2);
-  const int i1_0 = blockIdx.x << lr;
-  const int tot = N2 << lr;
-  const size_t base = (size_t)i1_0 * N2;
-  const u32* Xb = X + d.X_off;
-  for (int c = 0; c < 4; ++c) {
-    for (int gidx = 0; gidx < s.ngroups[c]; ++gidx) {
-      const int slot = c * SL + gidx;
-      if (slot < slot_lo || slot >= slot_hi) continue;
-      const Group gr = s.groups[c][gidx];
-      for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int r = idx >> m2, i = idx & (N2 - 1);
-        tile[r * ldr + i + (i >> 5)] = group_mac(Xb, kk.W, kk.Wq, s, c, gr, K, prime, g.logN, base + idx, p);
-      }
-      __syncthreads();
-      block_ntt<true, false>(tile, m2, lr, ldr, tw, p);
-      u32* go = G + d.G_off + ((size_t)(slot * 2 + prime) << g.logN) + base;
-      for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int r = idx >> m2, j2 = idx & (N2 - 1);
-        const u32 e = ((u32)j2 * bitrev(i1_0 + r, g.m1)) & Nmask;
-        go[idx] = step_twiddle(tile[r * ldr + j2 + (j2 >> 5)], e, st.lo[1][prime], st.hi[1][prime], p);
-      }
-      __syncthreads();
+  const int i1_0 = (pair >> 1) << g.lrows_inv;
+  for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x)
+    rtw[e] = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime], st.hi[1][prime], p);
+  const size_t base = (size_t)i1_0 << m2;
+  const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, g.logN, prime, p, kk.kw[0], kk.kw[1]};
+  const int gofs[4] = {0, s.ngroups[0], s.ngroups[0] + s.ngroups[1], s.ngroups[0] + s.ngroups[1] + s.ngroups[2]};
+  const int gtot = gofs[3] + s.ngroups[3];
+  const int quads = (nr << m2) >> 2;
+  for (int g0 = 0; g0 < gtot; g0 += gch) {
+    const int g1 = min(gtot, g0 + gch);
+    // tile vector (number - g0) * nr + r holds row r of that group
+    for (int q = threadIdx.x; q < 2 * quads; q += blockDim.x) {
+      const int e = q << 1, r = e >> m2, i = e & (N2 - 1);
+      mac_pair(ma, s, 0, 3, gofs, g0, g1, base + e, tile + r * ldr + swz(i), nr * ldr);
     }
+    __syncthreads();
+    block_ntt<true, false>(tile, m2, (g1 - g0) * nr, ldr, tw, p);
+    for (int gi = g0; gi < g1; ++gi) {
+      const int c = gi >= gofs[3] ? 3 : gi >= gofs[2] ? 2 : gi >= gofs[1] ? 1 : 0;
+      const int slot = c * SL + gi - gofs[c];
+      if (slot < slot_lo || slot >= slot_hi) continue;
+      uint4* go = reinterpret_cast<uint4*>(G + d.G_off + ((size_t)(slot * 2 + prime) << g.logN) + base);
+      const u32* tv = tile + (gi - g0) * nr * ldr;
+      for (int q = threadIdx.x; q < quads; q += blockDim.x) {
+        const int e = q << 2, r = e >> m2, j2 = e & (N2 - 1);
+        uint4 v = *reinterpret_cast<const uint4*>(tv + r * ldr + swz(j2));
+        const uint2 t0 = rtw[e], t1 = rtw[e + 1], t2 = rtw[e + 2], t3 = rtw[e + 3];
+        v.x = shoup_mul(v.x, t0.x, t0.y, p);
+        v.y = shoup_mul(v.y, t1.x, t1.y, p);
+        v.z = shoup_mul(v.z, t2.x, t2.y, p);
+        v.w = shoup_mul(v.w, t3.x, t3.y, p);
+        go[q] = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
 // Two-pass inverse, second pass (columns): blockIdx.y = slot*2 + prime.
 // Writes the first n natural-order outputs to the compact buffer.
-__global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(const u32* G, u32* Z, const TDesc* td, const TState* ts,
+__global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, const TDesc* td, const TState* ts,
                                                           const int* tlist, int K, int slot_lo, NttGeom g,
                                                           TwBlock tb) {
   extern __shared__ u32 smem[];
@@ -445,24 +794,22 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(const u32* G, u32* Z, 
   const int SL = K * K, c = slot / SL, gidx = slot % SL;
   if (s.status || gidx >= s.ngroups[c]) return;
   const u32 p = prime_of(prime);
-  const int m1 = g.m1, N2 = 1 << g.m2, lc = g.lc, C = 1 << lc;
+  const int m1 = g.m1, m2 = g.m2, lc = g.lc, lq = lc - 2;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + (1 << m1);
   load_block_tw(tw, tb.inv[prime], m1);
   const int j2_0 = blockIdx.x << lc;
-  const int tot = C << m1;
   const u32* gv = G + d.G_off + ((size_t)(slot * 2 + prime) << g.logN);
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int c2 = idx & (C - 1), i1 = idx >> lc;
-    tile[idx] = gv[i1 * N2 + j2_0 + c2];
-  }
+  load_cols(tile, gv, m1, m2, lc, j2_0, 1 << 30);
   __syncthreads();
   block_ntt<true, true>(tile, m1, lc, 0, tw, p);
-  u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.n;
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int c2 = idx & (C - 1), j1 = idx >> lc;
-    const int gi = j1 * N2 + j2_0 + c2;
-    if (gi < d.n) zo[gi] = tile[idx];
+  u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.zs;   // rows padded to a multiple of 4
+  const int n = d.n;
+  const int tot4 = 1 << (m1 + lq);
+  for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
+    const int j1 = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+    const int gi = (j1 << m2) + j2_0 + c4;
+    if (gi < n) *reinterpret_cast<uint4*>(zo + gi) = *reinterpret_cast<const uint4*>(tile + (j1 << lc) + c4);
   }
 }
 
@@ -491,11 +838,11 @@ NttGeom ntt_geom(int logN, int lc_override, int lrows_override) {
     g.lrows = 0;
     return g;
   }
-  g.m1 = logN / 2;
-  g.m2 = logN - g.m1;
-  // column tile: C * N1 words <= 32K words (128 KiB), at most 32 columns
+  g.m2 = logN / 2;
+  g.m1 = logN - g.m2;
+  // column tile: C * N1 words <= 16K words (64 KiB), 4 <= C <= 32 columns
   int lc = 5;
-  while (lc > 0 && (g.m1 + lc) > 15) --lc;
+  while (lc > 2 && (g.m1 + lc) > 14) --lc;
   if (lc > g.m2) lc = g.m2;
   // row tile: 4096 words per workgroup
   int lr = LOG2_BLOCK_MAX - g.m2;
@@ -503,14 +850,28 @@ NttGeom ntt_geom(int logN, int lc_override, int lrows_override) {
   if (lr > g.m1) lr = g.m1;
   g.lc = lc_override >= 0 ? lc_override : lc;
   g.lrows = lrows_override >= 0 ? lrows_override : lr;
+  // inverse rows: about 512 words per group row so that the groups of all
+  // four convolutions fit the LDS tile together
+  int li = 9 - g.m2;
+  if (li < 0) li = 0;
+  if (li > g.m1) li = g.m1;
+  g.lrows_inv = li;
   return g;
 }
 
 static size_t smem_cols(const NttGeom& g) { return ((size_t)(1 << g.m1) + ((size_t)1 << (g.m1 + g.lc))) * 4; }
 static size_t smem_rows(const NttGeom& g) {
-  return ((size_t)(1 << g.m2) + ((size_t)row_ld(1 << g.m2) << g.lrows)) * 4;
+  return ((size_t)(1 << g.m2) + ((size_t)row_ld(1 << g.m2) << g.lrows) + rowtw_words(g.m2, 1 << g.lrows)) * 4;
 }
 static size_t smem_single(int logN) { return ((size_t)(1 << logN) + row_ld(1 << logN)) * 4; }
+static size_t smem_inv_rows(const NttGeom& g) {
+  const int gch = std::max(1, inv_vmax(g.m2) >> g.lrows_inv);
+  return ((size_t)(1 << g.m2) + ((size_t)2 << (g.m2 + g.lrows_inv)) +
+          (size_t)row_ld(1 << g.m2) * (size_t)(gch << g.lrows_inv)) * 4;
+}
+static size_t smem_inv_single(int logN) {
+  return ((size_t)(1 << logN) + (size_t)row_ld(1 << logN) * (size_t)inv_vmax(logN)) * 4;
+}
 
 static hipError_t allow_big_lds() {
   static bool done = false;
@@ -540,65 +901,41 @@ hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool
   }
   const dim3 gc(1u << (g.m2 - g.lc), 1, count), gr(1u << (g.m1 - g.lrows), 1, count);
   if (!inverse) {
-    hipLaunchKernelGGL(k_std_fwd_cols, gc, dim3(NTT_THREADS), smem_cols(g), s, data, prime, g, tb, ts);
-    hipLaunchKernelGGL(k_std_fwd_rows, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb);
+    hipLaunchKernelGGL(k_std_fwd_cols, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, ts);
+    hipLaunchKernelGGL(k_std_fwd_rows, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
   } else {
     hipLaunchKernelGGL(k_std_inv_rows, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
-    hipLaunchKernelGGL(k_std_inv_cols, gc, dim3(NTT_THREADS), smem_cols(g), s, data, prime, g, tb);
+    hipLaunchKernelGGL(k_std_inv_cols, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, bool valid_full,
+                            int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb, const TwStep& st, int which,
+                            hipStream_t s) {
+  hipError_t e = allow_big_lds();
+  if (e != hipSuccess) return e;
+  const int nv = vi_hi - vi_lo;
+  if (count <= 0 || nv <= 0) return hipSuccess;
+  if (!g.two_pass()) {
+    if (which == 2) return hipSuccess;
+    hipLaunchKernelGGL(k_fwd_single, dim3(1, nv, count), dim3(NTT_THREADS), smem_single(g.logN), s, X, td, ts, tlist,
+                       K, valid_full, vi_lo, g.logN, tb);
+    return hipGetLastError();
+  }
+  if (which != 2)
+    hipLaunchKernelGGL(k_fwd_cols, dim3(1u << (g.m2 - g.lc), nv, count), dim3(COL_THREADS), smem_cols(g), s, X, td,
+                       ts, tlist, K, valid_full, vi_lo, g, tb, st);
+  if (which != 1)
+    hipLaunchKernelGGL(k_fwd_rows, dim3(1u << (g.m1 - g.lrows), nv, count), dim3(NTT_THREADS), smem_rows(g), s, X,
+                       td, ts, tlist, K, valid_full, vi_lo, g, tb, st);
   return hipGetLastError();
 }
 
 hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K,
                                bool valid_full, int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb,
                                const TwStep& st, hipStream_t s) {
-  hipError_t e = allow_big_lds();
-  if (e != hipSuccess) return e;
-  const int nv = vi_hi - vi_lo;
-  if (count <= 0 || nv <= 0) return hipSuccess;
-  if (!g.two_pass()) {
-    hipLaunchKernelGGL(k_fwd_single, dim3(1, nv, count), dim3(NTT_THREADS), smem_single(g.logN), s, X, td, ts, tlist,
-                       K, valid_full, vi_lo, g.logN, tb);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_fwd_cols, dim3(1u << (g.m2 - g.lc), nv, count), dim3(NTT_THREADS), smem_cols(g), s, X, td, ts,
-                     tlist, K, valid_full, vi_lo, g, tb, st);
-  hipLaunchKernelGGL(k_fwd_rows, dim3(1u << (g.m1 - g.lrows), nv, count), dim3(NTT_THREADS), smem_rows(g), s, X, td,
-                     ts, tlist, K, valid_full, vi_lo, g, tb);
-  return hipGetLastError();
-}
-
-hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts,
-                               const KernelDesc* kd, const int* tlist, int count, int K, int slot_lo, int slot_hi,
-                               const NttGeom& g, const TwBlock& tb, const TwStep& st, hipStream_t s) {
-  hipError_t e = allow_big_lds();
-  if (e != hipSuccess) return e;
-  if (count <= 0 || slot_hi <= slot_lo) return hipSuccess;
-  if (!g.two_pass()) {
-    hipLaunchKernelGGL(k_inv_single, dim3(1, 8, count), dim3(NTT_THREADS), smem_single(g.logN), s, X, Z, td, ts, kd,
-                       tlist, K, slot_lo, slot_hi, g.logN, tb);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_inv_rows, dim3(1u << (g.m1 - g.lrows), 2, count), dim3(NTT_THREADS), smem_rows(g), s, X, G,
-                     td, ts, kd, tlist, K, slot_lo, slot_hi, g, tb, st);
-  hipLaunchKernelGGL(k_inv_cols, dim3(1u << (g.m2 - g.lc), 2 * (slot_hi - slot_lo), count), dim3(NTT_THREADS),
-                     smem_cols(g), s, G, Z, td, ts, tlist, K, slot_lo, g, tb);
-  return hipGetLastError();
-}
-
-hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, int vi_lo,
-                            int vi_hi, const NttGeom& g, const TwBlock& tb, const TwStep& st, int which, hipStream_t s) {
-  if (which == 0) return launch_fwd_pipeline(X, td, ts, tlist, count, K, false, vi_lo, vi_hi, g, tb, st, s);
-  hipError_t e = allow_big_lds();
-  if (e != hipSuccess) return e;
-  const int nv = vi_hi - vi_lo;
-  if (which == 1)
-    hipLaunchKernelGGL(k_fwd_cols, dim3(1u << (g.m2 - g.lc), nv, count), dim3(NTT_THREADS), smem_cols(g), s, X, td,
-                       ts, tlist, K, false, vi_lo, g, tb, st);
-  else
-    hipLaunchKernelGGL(k_fwd_rows, dim3(1u << (g.m1 - g.lrows), nv, count), dim3(NTT_THREADS), smem_rows(g), s, X, td,
-                       ts, tlist, K, false, vi_lo, g, tb);
-  return hipGetLastError();
+  return launch_fwd_stage(X, td, ts, tlist, count, K, valid_full, vi_lo, vi_hi, g, tb, st, 0, s);
 }
 
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
@@ -606,17 +943,26 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
                             const TwBlock& tb, const TwStep& st, int which, hipStream_t s) {
   hipError_t e = allow_big_lds();
   if (e != hipSuccess) return e;
+  if (count <= 0 || slot_hi <= slot_lo) return hipSuccess;
   if (!g.two_pass()) {
-    if (which == 1) return launch_inv_pipeline(X, G, Z, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, s);
-    return hipSuccess;
+    if (which == 2) return hipSuccess;
+    hipLaunchKernelGGL(k_inv_single, dim3(8 * count), dim3(NTT_THREADS), smem_inv_single(g.logN), s, X, Z, td, ts,
+                       kd, tlist, count, K, slot_lo, slot_hi, g.logN, tb);
+    return hipGetLastError();
   }
-  if (which == 1)
-    hipLaunchKernelGGL(k_inv_rows, dim3(1u << (g.m1 - g.lrows), 2, count), dim3(NTT_THREADS), smem_rows(g), s, X, G,
-                       td, ts, kd, tlist, K, slot_lo, slot_hi, g, tb, st);
-  else
-    hipLaunchKernelGGL(k_inv_cols, dim3(1u << (g.m2 - g.lc), 2 * (slot_hi - slot_lo), count), dim3(NTT_THREADS),
+  if (which != 2)
+    hipLaunchKernelGGL(k_inv_rows, dim3((2u << (g.m1 - g.lrows_inv)) * count), dim3(NTT_THREADS), smem_inv_rows(g), s,
+                       X, G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st);
+  if (which != 1)
+    hipLaunchKernelGGL(k_inv_cols, dim3(1u << (g.m2 - g.lc), 2 * (slot_hi - slot_lo), count), dim3(COL_THREADS),
                        smem_cols(g), s, G, Z, td, ts, tlist, K, slot_lo, g, tb);
   return hipGetLastError();
+}
+
+hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts,
+                               const KernelDesc* kd, const int* tlist, int count, int K, int slot_lo, int slot_hi,
+                               const NttGeom& g, const TwBlock& tb, const TwStep& st, hipStream_t s) {
+  return launch_inv_stage(X, G, Z, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, 0, s);
 }
 
 hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s) {

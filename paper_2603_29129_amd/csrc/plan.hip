@@ -368,6 +368,7 @@ static int build_plan(fft_ozaki_plan_s* p) {
     d.N = 1 << d.logN;
     d.alpha = alpha_for(n, p->L);
     d.kd = kidx[n];
+    d.zs = (int)((n + 3) & ~(i64)3);
     d.io_off = io;
     d.xp_off = io;
     d.X_off = xo;
@@ -376,7 +377,7 @@ static int build_plan(fft_ozaki_plan_s* p) {
     io += n;
     xo += (i64)(4 * K) << d.logN;
     if (ntt_geom(d.logN).two_pass()) go += (8 * SL) << d.logN;
-    zo += 8 * SL * n;
+    zo += 8 * SL * (i64)d.zs;
     p->td.push_back(d);
     LengthClass& lc = p->classes[cidx[d.logN]];
     lc.tids.push_back(t);
@@ -555,7 +556,7 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
       for (auto& lc : p->classes) {
         NttGeom g = lc.geom;
         if (stage != 3 && !g.two_pass()) continue;
-        HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, 0, 4 * K, g, p->tb,
+        HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K, g, p->tb,
                                 step_for(p, lc.logN), stage == 3 ? 0 : stage - 3, s));
       }
       return FFT_OZAKI_OK;
@@ -738,7 +739,7 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
   switch (stage) {
     case 1: src = plan->xp + d.xp_off; sz = sizeof(double2) * (size_t)d.n; break;
     case 2: src = plan->X + d.X_off; sz = 4 * ((size_t)(4 * K) << d.logN); break;
-    case 3: src = plan->Z + d.Z_off; sz = 4 * (size_t)(8 * K * K) * (size_t)d.n; break;
+    case 3: src = plan->Z + d.Z_off; sz = 4 * (size_t)(8 * K * K) * (size_t)d.zs; break;
     case 4: src = kh.W; sz = 4 * ((size_t)(4 * K) << d.logN); break;
     case 5: src = kh.chirp; sz = sizeof(double2) * (size_t)d.n; break;
     default: return fail(FFT_OZAKI_ERR_INVALID, "unknown stage");

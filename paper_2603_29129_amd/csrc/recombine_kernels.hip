@@ -94,7 +94,7 @@ __device__ __constant__ int c_tconv[2][2] = {{0, 1}, {2, 3}};
 __device__ __constant__ int c_tsign[2][2] = {{1, -1}, {1, 1}};
 
 template <int W>
-__device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, int n, int j) {
+__device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, int zs, int j) {
   u64 acc[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -104,8 +104,8 @@ __device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, 
     const int sg = c_tsign[tg][ci];
     for (int g = 0; g < s.ngroups[c]; ++g) {
       const int slot = c * SL + g;
-      const u32 z0 = Zb[(size_t)(slot * 2) * n + j];
-      const u32 z1 = Zb[(size_t)(slot * 2 + 1) * n + j];
+      const u32 z0 = Zb[(size_t)(slot * 2) * zs + j];
+      const u32 z1 = Zb[(size_t)(slot * 2 + 1) * zs + j];
       i64 z = garner(z0, z1);
       if (sg < 0) z = -z;
       acc_add<W>(acc, z, s.groups[c][g].e - emin);
@@ -128,8 +128,8 @@ __global__ void k_recombine(const u32* Z, double2* out, const TDesc* td, const T
     if (s.status) {
       yr = yi = __builtin_nan("");
     } else {
-      const double pr = wide0 ? recombine_one<W_WIDE>(Zb, s, 0, SL, d.n, j) : recombine_one<W_FAST>(Zb, s, 0, SL, d.n, j);
-      const double pi = wide1 ? recombine_one<W_WIDE>(Zb, s, 1, SL, d.n, j) : recombine_one<W_FAST>(Zb, s, 1, SL, d.n, j);
+      const double pr = wide0 ? recombine_one<W_WIDE>(Zb, s, 0, SL, d.zs, j) : recombine_one<W_FAST>(Zb, s, 0, SL, d.zs, j);
+      const double pi = wide1 ? recombine_one<W_WIDE>(Zb, s, 1, SL, d.zs, j) : recombine_one<W_FAST>(Zb, s, 1, SL, d.zs, j);
       const double2 w = ch[j];
       yr = pr * w.x + pi * w.y;     // RN(RN(y'r c) + RN(y'i s))
       yi = pi * w.x - pr * w.y;     // RN(RN(y'i c) - RN(y'r s))

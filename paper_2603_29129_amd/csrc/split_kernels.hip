@@ -438,6 +438,9 @@ __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
     }
     s.npairs[c] = np;
     s.ngroups[c] = ng;
+    u64 gend = 0;
+    for (int g = 0; g < ng; ++g) gend |= 1ull << (s.groups[c][g].start + s.groups[c][g].count - 1);
+    s.gend[c] = gend;
     const int tg = c_tgt[c];
     for (int g = 0; g < ng; ++g) {
       const int e = s.groups[c][g].e;

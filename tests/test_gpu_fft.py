@@ -78,7 +78,7 @@ def check_stages(plan, idx, tr, kp, K):
                 want = (kp.ntts[part][t][ip] * np.uint64(pow(N, -1, p))) % np.uint64(p)
                 assert np.array_equal(W[part, t, ip].astype(np.uint64), want[perm]), (part, t, ip)
     # inverse NTT residues of every group
-    Z = plan.debug_dump(3, idx).reshape(4 * K * K, 2, n)
+    Z = plan.debug_dump(3, idx).reshape(4 * K * K, 2, (n + 3) // 4 * 4)[:, :, :n]
     for c in range(4):
         for g, (z, _e) in enumerate(tr["group_z"][c]):
             for ip, p in enumerate(nt.PRIMES):

@@ -57,7 +57,7 @@ def test_host_only_calls():
     assert L.fft_ozaki_execute(None, None, None, 0, None) == -1
     assert L.fft_ozaki_destroy(None) == -1
     m = ctypes.c_int()
-    assert L.fft_ozaki_ntt_layout(19, ctypes.byref(m)) == 0 and m.value == 9
+    assert L.fft_ozaki_ntt_layout(19, ctypes.byref(m)) == 0 and m.value == 10
     assert L.fft_ozaki_ntt_layout(12, ctypes.byref(m)) == 0 and m.value == 12
     assert L.fft_ozaki_ntt_layout(25, ctypes.byref(m)) == -1
     assert L.fft_ozaki_ntt(2, 10, 1, None, 0, None) == -1
