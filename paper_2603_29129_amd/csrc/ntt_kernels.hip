@@ -10,7 +10,10 @@
 //  * Each thread holds 2^r elements (r <= 3) in registers and performs r
 //    radix-2 stages between LDS exchanges (a 512-point transform takes three
 //    LDS round trips); eight registers per group keep the register file
-//    small enough for four to five waves per SIMD.
+//    small enough for four to five waves per SIMD.  The round structure is
+//    instantiated per transform length, so LDS and twiddle addresses are
+//    compile-time offsets and the butterflies whose root is 1 skip the
+//    product.
 //  * Lengths N > 4096 use two passes N = N1 * N2: column transforms of length
 //    N1 (stride N2, a tile of C adjacent columns per workgroup so that global
 //    accesses are C*4 bytes contiguous), the twiddle w_N^{j2 k1}, then
@@ -34,65 +37,49 @@ namespace fo {
 __device__ __forceinline__ u32 prime_of(int i) { return i ? P1 : P0; }
 __device__ __forceinline__ u32 bitrev(u32 v, int bits) { return bits ? (__brev(v) >> (32 - bits)) : 0u; }
 
-// Row layout of a tile: vector v at v * ldr (ldr = M + 8), element i at
-// swz(i): the 16-byte chunk index inside each 64-word block is XORed with
-// the block index, which keeps 16-byte chunks contiguous (vector LDS access)
-// and spreads the strided accesses of the radix rounds over the LDS banks.
+// Row layout of a tile: vector v at v * ldr, element i at pad8(i) = i + 8 (i / 64)
+// (eight pad words per 64 keep 16-byte chunks contiguous, make the addresses
+// of a radix group an affine function of its index -- compile-time offsets --
+// and spread the strided accesses of the radix rounds over the LDS banks).
 // Column layout (COLS): element i of all 2^lnvec vectors adjacent.
-__host__ __device__ inline int swz(int i) { return i ^ (((i >> 6) & 15) << 2); }
-__host__ __device__ inline int row_ld(int M) { return M + 8; }
-template <bool COLS>
-__device__ __forceinline__ int laddr(int v, int i, int lnvec, int ldr) {
-  return COLS ? ((i << lnvec) + v) : (v * ldr + swz(i));
-}
+__host__ __device__ constexpr int pad8(int i) { return i + ((i >> 6) << 3); }
+__host__ __device__ constexpr int row_ld(int M) { return pad8(M) + 4; }
 
 constexpr int UNR = 4;           // 16-byte global loads in flight per thread
 constexpr int INV_TILE_ROWS = 20;        // group rows per inverse chunk: the 20 groups of K = L = 3 fit, 3 workgroups per CU
 constexpr int KT = 3;            // slices per operand handled from registers in the fused MAC
 
-// r = RL radix-2 stages on the 2^RL registers of one group.  The group holds
-// tile elements base + j*st (j < 2^RL, base = blk * 2^RL * st + off, off < st)
-// of a length-2^m vector and the round covers stages s0 .. s0+RL-1.  At stage
-// s the partners are hd = 2^RL >> (s - s0 + 1) registers apart and the pair
-// (j, j + hd) uses w_M^e with e = (off + (j mod hd) * st) << s, so a stage
-// needs only hd distinct roots.  tw[e] = (w_M^e, companion), e < M/2.
-template <int RL, bool INV>
-__device__ __forceinline__ void radix_group(u32 (&a)[1 << RL], int off, int st, int s0,
-                                            const uint2* __restrict__ tw, u32 p) {
+// RL radix-2 stages (s = S0 .. S0+RL-1) on the 2^RL registers of one group of
+// a length-2^M transform.  The group holds elements base + j*ST, base =
+// blk * 2^RL * ST + off with off < ST.  At stage s the partners are hd =
+// 2^RL >> (s - S0 + 1) registers apart and pair (j, j + hd) uses w_M^e with
+// e = (off + (j mod hd) * ST) << s: hd distinct roots per stage, at
+// compile-time offsets from tw + (off << s).  When ST = 1 (off = 0) the roots
+// of the round are the same for every group (`twr`, preloaded) and those with
+// j mod hd = 0 are 1, so those butterflies skip the product.
+template <int RL, int S0, int ST, bool INV>
+__device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const uint2* __restrict__ tw,
+                                              const uint2 (&twr)[1 << RL], u32 p) {
   constexpr int R = 1 << RL;
-  if (!INV) {
 #pragma unroll
-    for (int ss = 0; ss < RL; ++ss) {
-      const int hd = R >> (ss + 1);
-      const int s = s0 + ss;
-      const int eb = off << s, es = st << s;
-      uint2 w[R / 2];
+  for (int k = 0; k < RL; ++k) {
+    const int ss = INV ? RL - 1 - k : k;
+    const int hd = R >> (ss + 1);
+    const int s = S0 + ss;
+    const uint2* tws = tw + (off << s);
 #pragma unroll
-      for (int jj = 0; jj < hd; ++jj) w[jj] = tw[eb + jj * es];
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        if (j & hd) continue;
-        const uint2 ww = w[j & (hd - 1)];
-        const u32 x = a[j], y = a[j + hd];
+    for (int j = 0; j < R; ++j) {
+      if (j & hd) continue;
+      const int jj = j & (hd - 1);
+      const bool trivial = (ST == 1) && jj == 0;
+      uint2 w = make_uint2(1u, 0u);
+      if (!trivial) w = (ST == 1) ? twr[hd + jj] : tws[(jj * ST) << s];
+      const u32 x = a[j], y = a[j + hd];
+      if (!INV) {
         a[j] = add_mod(x, y, p);
-        a[j + hd] = shoup_mul(x + p - y, ww.x, ww.y, p);   // x - y + p < 2p < 2^32
-      }
-    }
-  } else {
-#pragma unroll
-    for (int ss = RL - 1; ss >= 0; --ss) {
-      const int hd = R >> (ss + 1);
-      const int s = s0 + ss;
-      const int eb = off << s, es = st << s;
-      uint2 w[R / 2];
-#pragma unroll
-      for (int jj = 0; jj < hd; ++jj) w[jj] = tw[eb + jj * es];
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        if (j & hd) continue;
-        const uint2 ww = w[j & (hd - 1)];
-        const u32 x = a[j];
-        const u32 t = shoup_mul(a[j + hd], ww.x, ww.y, p);
+        a[j + hd] = trivial ? sub_mod(x, y, p) : shoup_mul(x + p - y, w.x, w.y, p);   // x - y + p < 2p
+      } else {
+        const u32 t = trivial ? y : shoup_mul(y, w.x, w.y, p);
         a[j] = add_mod(x, t, p);
         a[j + hd] = sub_mod(x, t, p);
       }
@@ -100,71 +87,96 @@ __device__ __forceinline__ void radix_group(u32 (&a)[1 << RL], int off, int st, 
   }
 }
 
-// nv: number of vectors (row layout) or log2 of it (column layout).  In the
-// last round of the row layout a group's registers are contiguous and move
-// as 16-byte LDS accesses.
-template <int RL, bool INV, bool COLS>
-__device__ void ntt_round(u32* lds, int m, int s0, int nv, int ldr, const uint2* tw, u32 p) {
-  constexpr int R = 1 << RL;
-  const int lbk = m - s0;              // log2 of the block size
-  const int lst = lbk - RL;            // log2 of the register stride
-  const int st = 1 << lst;
-  const int lgpv = m - RL;             // log2 groups per vector
-  const int total = COLS ? (1 << (nv + lgpv)) : (nv << lgpv);
+// One round of a length-2^M block NTT over the vectors of a tile.
+// nv: number of vectors (row layout) or log2 of it (column layout).
+template <int M, int S0, int RL, bool INV, bool COLS>
+__device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* __restrict__ tw, u32 p) {
+  constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
+  uint2 twr[R];
+  if (ST == 1) {
+    // roots of this round, shared by all groups: stage S0+ss uses twr[hd + jj] = w^(jj << s)
+#pragma unroll
+    for (int ss = 0; ss < RL; ++ss) {
+      const int hd = R >> (ss + 1);
+#pragma unroll
+      for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = tw[jj << (S0 + ss)];
+    }
+  }
+  const int total = COLS ? (1 << (nv + LGPV)) : (nv << LGPV);
+  const int sst = COLS ? (ST << nv) : 0;     // element stride of a group, column layout
   for (int g = threadIdx.x; g < total; g += blockDim.x) {
     int v, q;
     if (COLS) {
       v = g & ((1 << nv) - 1);
       q = g >> nv;
     } else {
-      v = g >> lgpv;
-      q = g & ((1 << lgpv) - 1);
+      v = g >> LGPV;
+      q = g & ((1 << LGPV) - 1);
     }
-    const int off = q & (st - 1);
-    const int base = ((q >> lst) << lbk) + off;
+    const int off = q & (ST - 1);
+    const int base = ((q >> LST) << LBK) + off;
     u32 a[R];
-    if (!COLS && R >= 4 && lst == 0) {
-      u32* row = lds + v * ldr;
+    u32* p0 = COLS ? lds + (base << nv) + v : lds + v * ldr + pad8(base);
+    if (!COLS && ST == 1 && R >= 4) {
 #pragma unroll
       for (int j = 0; j < R; j += 4) {
-        const uint4 t = *reinterpret_cast<const uint4*>(row + swz(base + j));
+        const uint4 t = *reinterpret_cast<const uint4*>(p0 + j);
         a[j] = t.x;
         a[j + 1] = t.y;
         a[j + 2] = t.z;
         a[j + 3] = t.w;
       }
-      radix_group<RL, INV>(a, off, st, s0, tw, p);
+      radix_group_t<RL, S0, ST, INV>(a, off, tw, twr, p);
 #pragma unroll
-      for (int j = 0; j < R; j += 4) *reinterpret_cast<uint4*>(row + swz(base + j)) = make_uint4(a[j], a[j + 1], a[j + 2], a[j + 3]);
+      for (int j = 0; j < R; j += 4) *reinterpret_cast<uint4*>(p0 + j) = make_uint4(a[j], a[j + 1], a[j + 2], a[j + 3]);
       continue;
     }
 #pragma unroll
-    for (int j = 0; j < R; ++j) a[j] = lds[laddr<COLS>(v, base + j * st, nv, ldr)];
-    radix_group<RL, INV>(a, off, st, s0, tw, p);
+    for (int j = 0; j < R; ++j) a[j] = COLS ? p0[j * sst] : p0[pad8(j * ST)];
+    radix_group_t<RL, S0, ST, INV>(a, off, tw, twr, p);
 #pragma unroll
-    for (int j = 0; j < R; ++j) lds[laddr<COLS>(v, base + j * st, nv, ldr)] = a[j];
+    for (int j = 0; j < R; ++j) {
+      if (COLS) p0[j * sst] = a[j];
+      else p0[pad8(j * ST)] = a[j];
+    }
   }
 }
 
-// In-place block NTT of the vectors of a tile (length 2^m each).  The m
-// radix-2 stages are spread evenly over ceil(m/3) rounds of at most three
-// stages (eight registers per group).  The caller synchronises after
-// filling the tile; this routine ends synchronised.
+// Rounds I.. of a length-2^M block NTT: ceil(M/3) rounds, the M stages spread
+// evenly (the first M mod nr rounds take one stage more); the inverse runs
+// the mirrored rounds in reverse order.
+template <int M, int I, bool INV, bool COLS>
+__device__ __forceinline__ void rounds_t(u32* lds, int nv, int ldr, const uint2* tw, u32 p) {
+  constexpr int NR = (M + 2) / 3, RB = M / NR, RX = M % NR;
+  if constexpr (I < NR) {
+    constexpr int IDX = INV ? NR - 1 - I : I;
+    constexpr int S0 = IDX * RB + (IDX < RX ? IDX : RX);
+    constexpr int RL = RB + (IDX < RX ? 1 : 0);
+    round_t<M, S0, RL, INV, COLS>(lds, nv, ldr, tw, p);
+    __syncthreads();
+    rounds_t<M, I + 1, INV, COLS>(lds, nv, ldr, tw, p);
+  }
+}
+
+// In-place block NTT of the vectors of a tile (length 2^m each, m <= 12).  The
+// caller synchronises after filling the tile; this routine ends
+// synchronised.
 template <bool INV, bool COLS>
 __device__ void block_ntt(u32* lds, int m, int nv, int ldr, const uint2* tw, u32 p) {
-  if (m == 0) return;
-  const int nr = (m + 2) / 3;
-  const int rb = m / nr, rx = m % nr;          // the first rx rounds take rb + 1 stages
-  for (int rr = 0; rr < nr; ++rr) {
-    const int round = INV ? (nr - 1 - rr) : rr;
-    const int s0 = round * rb + min(round, rx);
-    const int r = rb + (round < rx ? 1 : 0);
-    switch (r) {
-      case 3: ntt_round<3, INV, COLS>(lds, m, s0, nv, ldr, tw, p); break;
-      case 2: ntt_round<2, INV, COLS>(lds, m, s0, nv, ldr, tw, p); break;
-      default: ntt_round<1, INV, COLS>(lds, m, s0, nv, ldr, tw, p); break;
-    }
-    __syncthreads();
+  switch (m) {
+    case 1: rounds_t<1, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 2: rounds_t<2, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 3: rounds_t<3, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 4: rounds_t<4, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 5: rounds_t<5, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 6: rounds_t<6, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 7: rounds_t<7, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 8: rounds_t<8, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 9: rounds_t<9, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 10: rounds_t<10, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 11: rounds_t<11, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    case 12: rounds_t<12, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
+    default: break;
   }
 }
 
@@ -248,7 +260,7 @@ __device__ void load_rows(u32* tile, const u32* __restrict__ src, int nrows, int
   const int M = 1 << m;
   if (m < 2) {
     for (int e = threadIdx.x; e < (nrows << m); e += blockDim.x)
-      tile[(e >> m) * ldr + swz(e & (M - 1))] = e < valid ? src[e] : 0u;
+      tile[(e >> m) * ldr + pad8(e & (M - 1))] = e < valid ? src[e] : 0u;
     return;
   }
   const int tot4 = (nrows << m) >> 2;
@@ -265,7 +277,7 @@ __device__ void load_rows(u32* tile, const u32* __restrict__ src, int nrows, int
       const int q = q0 + u * blockDim.x;
       if (q < tot4) {
         const int e = q << 2;
-        *reinterpret_cast<uint4*>(tile + (e >> m) * ldr + swz(e & (M - 1))) = zero_from(v[u], e, valid);
+        *reinterpret_cast<uint4*>(tile + (e >> m) * ldr + pad8(e & (M - 1))) = zero_from(v[u], e, valid);
       }
     }
   }
@@ -274,14 +286,14 @@ __device__ void load_rows(u32* tile, const u32* __restrict__ src, int nrows, int
 __device__ void store_rows(u32* __restrict__ dst, const u32* tile, int nrows, int m, int ldr) {
   const int M = 1 << m;
   if (m < 2) {
-    for (int e = threadIdx.x; e < (nrows << m); e += blockDim.x) dst[e] = tile[(e >> m) * ldr + swz(e & (M - 1))];
+    for (int e = threadIdx.x; e < (nrows << m); e += blockDim.x) dst[e] = tile[(e >> m) * ldr + pad8(e & (M - 1))];
     return;
   }
   const int tot4 = (nrows << m) >> 2;
   uint4* d4 = reinterpret_cast<uint4*>(dst);
   for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
     const int e = q << 2;
-    d4[q] = *reinterpret_cast<const uint4*>(tile + (e >> m) * ldr + swz(e & (M - 1)));
+    d4[q] = *reinterpret_cast<const uint4*>(tile + (e >> m) * ldr + pad8(e & (M - 1)));
   }
 }
 
@@ -352,7 +364,7 @@ __device__ void fwd_rows_body(u32* vec, int prime, const NttGeom g, int i1_0, co
   __syncthreads();
   for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x) {
     const int r = e >> m2, j2 = e & (N2 - 1);
-    u32* q = tile + r * ldr + swz(j2);
+    u32* q = tile + r * ldr + pad8(j2);
     *q = apply_rowtw(rt, *q, r, j2, m2, p);
   }
   __syncthreads();
@@ -395,7 +407,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int logN,
   block_ntt<true, false>(tile, logN, 1, ldr, tw, p);
   // N^{-1} = p - (p-1)/N
   const u32 ninv = p - ((p - 1) >> logN), ninvq = shoup_companion(ninv, p);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) vec[i] = shoup_mul(tile[swz(i)], ninv, ninvq, p);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) vec[i] = shoup_mul(tile[pad8(i)], ninv, ninvq, p);
 }
 
 __global__ void __launch_bounds__(COL_THREADS) k_std_fwd_cols(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
@@ -430,7 +442,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int pri
   block_ntt<true, false>(tile, m2, nr, ldr, tw, p);
   for (int idx = threadIdx.x; idx < (nr << m2); idx += blockDim.x) {
     const int r = idx >> m2, j2 = idx & (N2 - 1);
-    src[idx] = apply_rowtw(rt, tile[r * ldr + swz(j2)], r, j2, m2, p);
+    src[idx] = apply_rowtw(rt, tile[r * ldr + pad8(j2)], r, j2, m2, p);
   }
 }
 
@@ -701,9 +713,9 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
     if (c * SL + g1 <= slot_lo || c * SL + g0 >= slot_hi) continue;
     if (logN >= 1) {
       for (int q = threadIdx.x; q < (N >> 1); q += blockDim.x)
-        mac_pair(ma, s, c, c, gofs, g0, g1, (size_t)q << 1, tile + swz(q << 1), ldr);
+        mac_pair(ma, s, c, c, gofs, g0, g1, (size_t)q << 1, tile + pad8(q << 1), ldr);
     } else {
-      for (int i = threadIdx.x; i < N; i += blockDim.x) mac_single(ma, s, c, c, gofs, g0, g1, i, tile + swz(i), ldr);
+      for (int i = threadIdx.x; i < N; i += blockDim.x) mac_single(ma, s, c, c, gofs, g0, g1, i, tile + pad8(i), ldr);
     }
     __syncthreads();
     block_ntt<true, false>(tile, logN, g1 - g0, ldr, tw, p);
@@ -712,7 +724,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
       if (slot < slot_lo || slot >= slot_hi) continue;
       u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.zs;
       const u32* row = tile + (gi - g0) * ldr;
-      for (int i = threadIdx.x; i < d.n; i += blockDim.x) zo[i] = row[swz(i)];
+      for (int i = threadIdx.x; i < d.n; i += blockDim.x) zo[i] = row[pad8(i)];
     }
     __syncthreads();
   }
@@ -756,7 +768,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
     // tile vector (number - g0) * nr + r holds row r of that group
     for (int q = threadIdx.x; q < 2 * quads; q += blockDim.x) {
       const int e = q << 1, r = e >> m2, i = e & (N2 - 1);
-      mac_pair(ma, s, 0, 3, gofs, g0, g1, base + e, tile + r * ldr + swz(i), nr * ldr);
+      mac_pair(ma, s, 0, 3, gofs, g0, g1, base + e, tile + r * ldr + pad8(i), nr * ldr);
     }
     __syncthreads();
     block_ntt<true, false>(tile, m2, (g1 - g0) * nr, ldr, tw, p);
@@ -768,7 +780,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
       const u32* tv = tile + (gi - g0) * nr * ldr;
       for (int q = threadIdx.x; q < quads; q += blockDim.x) {
         const int e = q << 2, r = e >> m2, j2 = e & (N2 - 1);
-        uint4 v = *reinterpret_cast<const uint4*>(tv + r * ldr + swz(j2));
+        uint4 v = *reinterpret_cast<const uint4*>(tv + r * ldr + pad8(j2));
         const uint2 t0 = rtw[e], t1 = rtw[e + 1], t2 = rtw[e + 2], t3 = rtw[e + 3];
         v.x = shoup_mul(v.x, t0.x, t0.y, p);
         v.y = shoup_mul(v.y, t1.x, t1.y, p);
