@@ -297,6 +297,13 @@ __device__ void store_rows(u32* __restrict__ dst, const u32* tile, int nrows, in
   }
 }
 
+// Column tile taken by workgroup x of a column pass over the 2^lt tiles of a
+// vector (grid x dimension = 2^lt).  Workgroups go to the eight XCDs
+// round-robin, so x and x + 8 run on one XCD at about the same time; giving
+// them adjacent tiles lets their partial cache lines (a tile row is 16 to
+// 128 bytes) meet in that XCD's L2 instead of being fetched by two XCDs.
+__device__ __forceinline__ int col_tile(int x, int lt) { return lt < 3 ? x : (((x & 7) << (lt - 3)) | (x >> 3)); }
+
 // Columns [j2_0, j2_0 + 2^lc) of a 2^m1 x 2^m2 row-major vector into the
 // column-layout tile; positions >= valid read as zero.  Needs lc >= 2.
 __device__ void load_cols(u32* tile, const u32* __restrict__ vec, int m1, int m2, int lc, int j2_0, int valid) {
@@ -413,7 +420,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int logN,
 __global__ void __launch_bounds__(COL_THREADS) k_std_fwd_cols(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
   extern __shared__ u32 smem[];
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
-  fwd_cols_body(vec, 1 << g.logN, prime, g, blockIdx.x << g.lc, tb.fwd[prime], smem);
+  fwd_cols_body(vec, 1 << g.logN, prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[prime], smem);
 }
 
 __global__ void __launch_bounds__(NTT_THREADS) k_std_fwd_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
@@ -455,7 +462,7 @@ __global__ void __launch_bounds__(COL_THREADS) k_std_inv_cols(u32* data, int pri
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + (1 << m1);
   load_block_tw(tw, tb.inv[prime], m1);
-  const int j2_0 = blockIdx.x << lc;
+  const int j2_0 = col_tile(blockIdx.x, m2 - lc) << lc;
   load_cols(tile, vec, m1, m2, lc, j2_0, 1 << 30);
   __syncthreads();
   block_ntt<true, true>(tile, m1, lc, 0, tw, p);
@@ -508,7 +515,7 @@ __global__ void __launch_bounds__(COL_THREADS) k_fwd_cols(u32* X, const TDesc* t
   extern __shared__ u32 smem[];
   FwdSel o;
   if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
-  fwd_cols_body(o.vec, o.valid, o.prime, g, blockIdx.x << g.lc, tb.fwd[o.prime], smem);
+  fwd_cols_body(o.vec, o.valid, o.prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[o.prime], smem);
 }
 
 __global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(u32* X, const TDesc* td, const TState* ts,
@@ -810,7 +817,7 @@ __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, 
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + (1 << m1);
   load_block_tw(tw, tb.inv[prime], m1);
-  const int j2_0 = blockIdx.x << lc;
+  const int j2_0 = col_tile(blockIdx.x, m2 - lc) << lc;
   const u32* gv = G + d.G_off + ((size_t)(slot * 2 + prime) << g.logN);
   load_cols(tile, gv, m1, m2, lc, j2_0, 1 << 30);
   __syncthreads();
