@@ -32,6 +32,11 @@
 
 #include "internal.h"
 
+#include <mutex>
+#include <type_traits>
+#include <unordered_set>
+#include <utility>
+
 namespace fo {
 
 __device__ __forceinline__ u32 prime_of(int i) { return i ? P1 : P0; }
@@ -43,7 +48,9 @@ __device__ __forceinline__ u32 bitrev(u32 v, int bits) { return bits ? (__brev(v
 // and spread the strided accesses of the radix rounds over the LDS banks).
 // Column layout (COLS): element i of all 2^lnvec vectors adjacent.
 __host__ __device__ constexpr int pad8(int i) { return i + ((i >> 6) << 3); }
-__host__ __device__ constexpr int row_ld(int M) { return pad8(M) + 4; }
+// Row stride: rows shorter than 512 words are offset by four banks (a wave's
+// radix groups then span several rows); longer rows need no offset.
+__host__ __device__ constexpr int row_ld(int M) { return pad8(M) + (M >= 512 ? 0 : 4); }
 
 constexpr int UNR = 4;           // 16-byte global loads in flight per thread
 constexpr int INV_TILE_ROWS = 20;        // group rows per inverse chunk: the 20 groups of K = L = 3 fit, 3 workgroups per CU
@@ -147,7 +154,7 @@ __device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* 
 // the mirrored rounds in reverse order.
 template <int M, int I, bool INV, bool COLS>
 __device__ __forceinline__ void rounds_t(u32* lds, int nv, int ldr, const uint2* tw, u32 p) {
-  constexpr int NR = (M + 2) / 3, RB = M / NR, RX = M % NR;
+  constexpr int NR = (M + 2) / 3, RB = NR ? M / NR : 0, RX = NR ? M % NR : 0;
   if constexpr (I < NR) {
     constexpr int IDX = INV ? NR - 1 - I : I;
     constexpr int S0 = IDX * RB + (IDX < RX ? IDX : RX);
@@ -158,26 +165,13 @@ __device__ __forceinline__ void rounds_t(u32* lds, int nv, int ldr, const uint2*
   }
 }
 
-// In-place block NTT of the vectors of a tile (length 2^m each, m <= 12).  The
+// In-place block NTT of the vectors of a tile (length 2^M each, M <= 12).  The
 // caller synchronises after filling the tile; this routine ends
-// synchronised.
-template <bool INV, bool COLS>
-__device__ void block_ntt(u32* lds, int m, int nv, int ldr, const uint2* tw, u32 p) {
-  switch (m) {
-    case 1: rounds_t<1, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 2: rounds_t<2, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 3: rounds_t<3, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 4: rounds_t<4, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 5: rounds_t<5, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 6: rounds_t<6, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 7: rounds_t<7, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 8: rounds_t<8, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 9: rounds_t<9, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 10: rounds_t<10, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 11: rounds_t<11, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    case 12: rounds_t<12, 0, INV, COLS>(lds, nv, ldr, tw, p); break;
-    default: break;
-  }
+// synchronised.  Every kernel is instantiated per block length, so the
+// rounds inline with compile-time geometry.
+template <int M, bool INV, bool COLS>
+__device__ __forceinline__ void block_ntt(u32* lds, int nv, int ldr, const uint2* tw, u32 p) {
+  rounds_t<M, 0, INV, COLS>(lds, nv, ldr, tw, p);
 }
 
 // Copies the roots w_M^e (e < M/2) of a length-2^m block NTT into LDS from the
@@ -337,15 +331,18 @@ __device__ void load_cols(u32* tile, const u32* __restrict__ vec, int m1, int m2
 
 // Forward column pass on vector `vec` (elements >= valid read as zero),
 // written back in place; the twiddle w_N^{j2 k1} is applied by the row pass.
-__device__ void fwd_cols_body(u32* vec, int valid, int prime, const NttGeom g, int j2_0, const uint2* twb, u32* smem) {
+template <int M1>
+__device__ __forceinline__ void fwd_cols_body(u32* vec, int valid, int prime, const NttGeom g, int j2_0, const uint2* twb,
+                                              u32* smem) {
   const u32 p = prime_of(prime);
-  const int m1 = g.m1, m2 = g.m2, lc = g.lc, lq = lc - 2;
+  constexpr int m1 = M1;
+  const int m2 = g.m2, lc = g.lc, lq = lc - 2;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + (1 << m1);
   load_block_tw(tw, twb, m1);
   load_cols(tile, vec, m1, m2, lc, j2_0, valid);
   __syncthreads();
-  block_ntt<false, true>(tile, m1, lc, 0, tw, p);
+  block_ntt<M1, false, true>(tile, lc, 0, tw, p);
   const int tot4 = 1 << (m1 + lq);
   for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
     const int i = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
@@ -355,10 +352,12 @@ __device__ void fwd_cols_body(u32* vec, int valid, int prime, const NttGeom g, i
 
 // Forward row pass: rows [i1_0, i1_0 + 2^lrows) of vector vec, each element
 // first multiplied by w_N^{j2 k1}.
-__device__ void fwd_rows_body(u32* vec, int prime, const NttGeom g, int i1_0, const uint2* twb,
-                              const uint2* lo, const uint2* hi, u32* smem) {
+template <int M2>
+__device__ __forceinline__ void fwd_rows_body(u32* vec, int prime, const NttGeom g, int i1_0, const uint2* twb,
+                                              const uint2* lo, const uint2* hi, u32* smem) {
   const u32 p = prime_of(prime);
-  const int m2 = g.m2, N2 = 1 << m2, ldr = row_ld(N2), nr = 1 << g.lrows;
+  constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
+  const int nr = 1 << g.lrows;
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + N2;
@@ -375,33 +374,34 @@ __device__ void fwd_rows_body(u32* vec, int prime, const NttGeom g, int i1_0, co
     *q = apply_rowtw(rt, *q, r, j2, m2, p);
   }
   __syncthreads();
-  block_ntt<false, false>(tile, m2, nr, ldr, tw, p);
+  block_ntt<M2, false, false>(tile, nr, ldr, tw, p);
   store_rows(src, tile, nr, m2, ldr);
 }
 
 // Forward single-workgroup transform of a vector of length 2^logN <= 4096.
-__device__ void fwd_single_body(u32* vec, int valid, int prime, int logN, const uint2* twb, u32* smem) {
+template <int M>
+__device__ __forceinline__ void fwd_single_body(u32* vec, int valid, int prime, const uint2* twb, u32* smem) {
   const u32 p = prime_of(prime);
-  const int ldr = row_ld(1 << logN);
+  constexpr int logN = M, ldr = row_ld(1 << logN);
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + (1 << logN);
   load_block_tw(tw, twb, logN);
   load_rows(tile, vec, 1, logN, ldr, valid);
   __syncthreads();
-  block_ntt<false, false>(tile, logN, 1, ldr, tw, p);
+  block_ntt<M, false, false>(tile, 1, ldr, tw, p);
   store_rows(vec, tile, 1, logN, ldr);
 }
 
 // ---------------------------------------------------------------------------
 // Standalone kernels (count contiguous vectors; blockIdx.z = vector).
 
-__global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int logN, int prime, bool inverse,
-                                                            TwBlock tb) {
+template <int M>
+__global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int prime, bool inverse, TwBlock tb) {
   extern __shared__ u32 smem[];
+  constexpr int logN = M, N = 1 << logN;
   u32* vec = data + ((size_t)blockIdx.z << logN);
-  const int N = 1 << logN;
   if (!inverse) {
-    fwd_single_body(vec, N, prime, logN, tb.fwd[prime], smem);
+    fwd_single_body<M>(vec, N, prime, tb.fwd[prime], smem);
     return;
   }
   const u32 p = prime_of(prime);
@@ -411,30 +411,34 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int logN,
   load_block_tw(tw, tb.inv[prime], logN);
   load_rows(tile, vec, 1, logN, ldr, N);
   __syncthreads();
-  block_ntt<true, false>(tile, logN, 1, ldr, tw, p);
+  block_ntt<M, true, false>(tile, 1, ldr, tw, p);
   // N^{-1} = p - (p-1)/N
   const u32 ninv = p - ((p - 1) >> logN), ninvq = shoup_companion(ninv, p);
   for (int i = threadIdx.x; i < N; i += blockDim.x) vec[i] = shoup_mul(tile[pad8(i)], ninv, ninvq, p);
 }
 
+template <int M1>
 __global__ void __launch_bounds__(COL_THREADS) k_std_fwd_cols(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
   extern __shared__ u32 smem[];
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
-  fwd_cols_body(vec, 1 << g.logN, prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[prime], smem);
+  fwd_cols_body<M1>(vec, 1 << g.logN, prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[prime], smem);
 }
 
+template <int M2>
 __global__ void __launch_bounds__(NTT_THREADS) k_std_fwd_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
   extern __shared__ u32 smem[];
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
-  fwd_rows_body(vec, prime, g, blockIdx.x << g.lrows, tb.fwd[prime], ts.lo[0][prime], ts.hi[0][prime], smem);
+  fwd_rows_body<M2>(vec, prime, g, blockIdx.x << g.lrows, tb.fwd[prime], ts.lo[0][prime], ts.hi[0][prime], smem);
 }
 
 // Inverse row pass (standalone): DIT rows then w_N^{-j2 k1}.
+template <int M2>
 __global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
   extern __shared__ u32 smem[];
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   const u32 p = prime_of(prime);
-  const int m2 = g.m2, N2 = 1 << m2, nr = 1 << g.lrows, ldr = row_ld(N2);
+  constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
+  const int nr = 1 << g.lrows;
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + N2;
@@ -446,7 +450,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int pri
   u32* src = vec + ((size_t)i1_0 << m2);
   load_rows(tile, src, nr, m2, ldr, 1 << 30);
   __syncthreads();
-  block_ntt<true, false>(tile, m2, nr, ldr, tw, p);
+  block_ntt<M2, true, false>(tile, nr, ldr, tw, p);
   for (int idx = threadIdx.x; idx < (nr << m2); idx += blockDim.x) {
     const int r = idx >> m2, j2 = idx & (N2 - 1);
     src[idx] = apply_rowtw(rt, tile[r * ldr + pad8(j2)], r, j2, m2, p);
@@ -454,18 +458,20 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int pri
 }
 
 // Inverse column pass (standalone): DIT columns, times N^{-1}, natural order.
+template <int M1>
 __global__ void __launch_bounds__(COL_THREADS) k_std_inv_cols(u32* data, int prime, NttGeom g, TwBlock tb) {
   extern __shared__ u32 smem[];
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   const u32 p = prime_of(prime);
-  const int m1 = g.m1, m2 = g.m2, lc = g.lc, lq = lc - 2;
+  constexpr int m1 = M1;
+  const int m2 = g.m2, lc = g.lc, lq = lc - 2;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + (1 << m1);
   load_block_tw(tw, tb.inv[prime], m1);
   const int j2_0 = col_tile(blockIdx.x, m2 - lc) << lc;
   load_cols(tile, vec, m1, m2, lc, j2_0, 1 << 30);
   __syncthreads();
-  block_ntt<true, true>(tile, m1, lc, 0, tw, p);
+  block_ntt<M1, true, true>(tile, lc, 0, tw, p);
   const u32 ninv = p - ((p - 1) >> g.logN), ninvq = shoup_companion(ninv, p);
   const int tot4 = 1 << (m1 + lq);
   for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
@@ -500,31 +506,34 @@ __device__ __forceinline__ bool fwd_select(u32* X, const TDesc* td, const TState
   return true;
 }
 
+template <int M>
 __global__ void __launch_bounds__(NTT_THREADS) k_fwd_single(u32* X, const TDesc* td, const TState* ts,
                                                             const int* tlist, int K, bool valid_full, int vi_lo,
-                                                            int logN, TwBlock tb) {
+                                                            TwBlock tb) {
   extern __shared__ u32 smem[];
   FwdSel o;
   if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
-  fwd_single_body(o.vec, o.valid, o.prime, logN, tb.fwd[o.prime], smem);
+  fwd_single_body<M>(o.vec, o.valid, o.prime, tb.fwd[o.prime], smem);
 }
 
+template <int M1>
 __global__ void __launch_bounds__(COL_THREADS) k_fwd_cols(u32* X, const TDesc* td, const TState* ts,
                                                           const int* tlist, int K, bool valid_full, int vi_lo,
                                                           NttGeom g, TwBlock tb, TwStep st) {
   extern __shared__ u32 smem[];
   FwdSel o;
   if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
-  fwd_cols_body(o.vec, o.valid, o.prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[o.prime], smem);
+  fwd_cols_body<M1>(o.vec, o.valid, o.prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[o.prime], smem);
 }
 
+template <int M2>
 __global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(u32* X, const TDesc* td, const TState* ts,
                                                           const int* tlist, int K, bool valid_full, int vi_lo,
                                                           NttGeom g, TwBlock tb, TwStep st) {
   extern __shared__ u32 smem[];
   FwdSel o;
   if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
-  fwd_rows_body(o.vec, o.prime, g, blockIdx.x << g.lrows, tb.fwd[o.prime], st.lo[0][o.prime], st.hi[0][o.prime], smem);
+  fwd_rows_body<M2>(o.vec, o.prime, g, blockIdx.x << g.lrows, tb.fwd[o.prime], st.lo[0][o.prime], st.hi[0][o.prime], smem);
 }
 
 // The four real convolutions (Sec. 4.5): input part pa with kernel part pb.
@@ -600,6 +609,51 @@ __device__ void walk_mem(const MacArgs& a, const TState& s, int c, int gbase, in
       ++g;
     }
   }
+}
+
+// Kernel-slice operands of positions e, e+1 held in registers (<= KT slices
+// per part): Re w* slices with companions (w0, q0), Im w* (w1, q1).
+struct WRegs {
+  uint2 w0[KT], q0[KT], w1[KT], q1[KT];
+};
+__device__ __forceinline__ void load_wregs(WRegs& r, const u32* W, const u32* Wq, int K, int logN, int prime,
+                                           int kw0, int kw1, size_t e) {
+  const size_t N = (size_t)1 << logN, sstride = 2 * N, part = (size_t)K * sstride;
+  const u32* wb = W + (size_t)prime * N + e;
+  const u32* qb = Wq + (size_t)prime * N + e;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    if (k < kw0) {
+      r.w0[k] = ld2(wb + k * sstride);
+      r.q0[k] = ld2(qb + k * sstride);
+    }
+    if (k < kw1) {
+      r.w1[k] = ld2(wb + part + k * sstride);
+      r.q1[k] = ld2(qb + part + k * sstride);
+    }
+  }
+}
+// Slice spectra of Re x' (xr) and Im x' (xi) at positions e, e+1.
+__device__ __forceinline__ void load_xregs(uint2 (&xr)[KT], uint2 (&xi)[KT], const u32* X, int K, int logN,
+                                           int prime, int kx0, int kx1, size_t e) {
+  const size_t N = (size_t)1 << logN, sstride = 2 * N, part = (size_t)K * sstride;
+  const u32* xb = X + (size_t)prime * N + e;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    if (k < kx0) xr[k] = ld2(xb + k * sstride);
+    if (k < kx1) xi[k] = ld2(xb + part + k * sstride);
+  }
+}
+// All four convolutions from register operands; groups [g0, g1) go to LDS.
+// Re x' feeds ReRe (0) and ReIm (3); Im x' feeds ImIm (1) and ImRe (2).
+__device__ __forceinline__ void mac_regs(const uint2 (&xr)[KT], const uint2 (&xi)[KT], const WRegs& r,
+                                         const TState& s, int kw0, int kw1, const int (&gofs)[4], int g0, int g1,
+                                         u32* lds0, int rstride, u32 p) {
+  const int kx0 = s.kx[0], kx1 = s.kx[1];
+  walk_regs(xr, r.w0, r.q0, kx0, kw0, s.gend[0], gofs[0], g0, g1, lds0, rstride, p);
+  walk_regs(xr, r.w1, r.q1, kx0, kw1, s.gend[3], gofs[3], g0, g1, lds0, rstride, p);
+  walk_regs(xi, r.w1, r.q1, kx1, kw1, s.gend[1], gofs[1], g0, g1, lds0, rstride, p);
+  walk_regs(xi, r.w0, r.q0, kx1, kw0, s.gend[2], gofs[2], g0, g1, lds0, rstride, p);
 }
 
 // Convolutions [c_lo, c_hi] at positions e, e+1 (e even).
@@ -694,9 +748,11 @@ __device__ __forceinline__ void decode_tile(int L, int pairs, int count, int& pa
 // Single-workgroup inverse (N <= 4096): one workgroup per (transform, prime,
 // convolution).  For each chunk of groups: multiply-accumulate into LDS
 // rows, inverse block NTTs, first n outputs to the compact buffer.
+template <int M>
 __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z, const TDesc* td, const TState* ts,
                                                             const KernelDesc* kd, const int* tlist, int count, int K,
-                                                            int slot_lo, int slot_hi, int logN, TwBlock tb) {
+                                                            int slot_lo, int slot_hi, TwBlock tb) {
+  constexpr int logN = M;
   extern __shared__ u32 smem[];
   int pair, b;
   decode_tile(blockIdx.x, 8, count, pair, b);
@@ -725,7 +781,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
       for (int i = threadIdx.x; i < N; i += blockDim.x) mac_single(ma, s, c, c, gofs, g0, g1, i, tile + pad8(i), ldr);
     }
     __syncthreads();
-    block_ntt<true, false>(tile, logN, g1 - g0, ldr, tw, p);
+    block_ntt<M, true, false>(tile, g1 - g0, ldr, tw, p);
     for (int gi = g0; gi < g1; ++gi) {
       const int slot = c * SL + gi;
       if (slot < slot_lo || slot >= slot_hi) continue;
@@ -737,25 +793,53 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
   }
 }
 
-// Two-pass inverse, first pass (rows): one workgroup per (row tile, prime,
-// transform).  For each chunk of groups (normally all groups of the four
-// convolutions at once): multiply-accumulate into LDS, inverse row NTTs,
-// twiddle w_N^{-j2 k1}, store the group rows.
+// Group rows [g0, g1) of the tile: times w_N^{-j2 k1}, stored to their slots.
+__device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u32* tile, const uint2* rtw,
+                                                 const int (&gofs)[4], int g0, int g1, int SL, int slot_lo,
+                                                 int slot_hi, int prime, int logN, size_t base, int m2, int nr,
+                                                 int ldr, u32 p) {
+  const int quads = (nr << m2) >> 2, N2 = 1 << m2;
+  for (int gi = g0; gi < g1; ++gi) {
+    const int c = gi >= gofs[3] ? 3 : gi >= gofs[2] ? 2 : gi >= gofs[1] ? 1 : 0;
+    const int slot = c * SL + gi - gofs[c];
+    if (slot < slot_lo || slot >= slot_hi) continue;
+    uint4* go = reinterpret_cast<uint4*>(G + d.G_off + ((size_t)(slot * 2 + prime) << logN) + base);
+    const u32* tv = tile + (gi - g0) * nr * ldr;
+    for (int q = threadIdx.x; q < quads; q += blockDim.x) {
+      const int e = q << 2, r = e >> m2, j2 = e & (N2 - 1);
+      uint4 v = *reinterpret_cast<const uint4*>(tv + r * ldr + pad8(j2));
+      const uint2 t0 = rtw[e], t1 = rtw[e + 1], t2 = rtw[e + 2], t3 = rtw[e + 3];
+      v.x = shoup_mul(v.x, t0.x, t0.y, p);
+      v.y = shoup_mul(v.y, t1.x, t1.y, p);
+      v.z = shoup_mul(v.z, t2.x, t2.y, p);
+      v.w = shoup_mul(v.w, t3.x, t3.y, p);
+      go[q] = v;
+    }
+  }
+}
+
+// Two-pass inverse, first pass (rows): one workgroup per (row tile, prime)
+// and run of up to tpw consecutive transforms of the list.  Per transform:
+// multiply-accumulate into LDS (normally all groups of the four
+// convolutions at once), inverse row NTTs, twiddle w_N^{-j2 k1}, store the
+// group rows.  The block roots, the row twiddles and (when each thread
+// owns one position pair and a transform's slices fit the register path)
+// the kernel-slice operands are set up once per run, and the slice spectra
+// of the next transform are loaded while the current one is transformed.
+template <int M2>
 __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, const TDesc* td, const TState* ts,
                                                           const KernelDesc* kd, const int* tlist, int count, int K,
                                                           int slot_lo, int slot_hi, NttGeom g, TwBlock tb,
-                                                          TwStep st) {
+                                                          TwStep st, int tpw) {
   extern __shared__ u32 smem[];
-  int pair, b;
-  decode_tile(blockIdx.x, 2 << (g.m1 - g.lrows_inv), count, pair, b);
-  const int t = tlist[b];
-  const TDesc& d = td[t];
-  const TState& s = ts[t];
-  if (s.status) return;
+  const int nruns = (count + tpw - 1) / tpw;
+  int pair, run;
+  decode_tile(blockIdx.x, 2 << (g.m1 - g.lrows_inv), nruns, pair, run);
+  const int b_lo = run * tpw, b_hi = min(count, b_lo + tpw);
   const int prime = pair & 1;
   const u32 p = prime_of(prime);
-  const KernelDesc& kk = kd[d.kd];
-  const int m2 = g.m2, N2 = 1 << m2, nr = 1 << g.lrows_inv, ldr = row_ld(N2), SL = K * K;
+  constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
+  const int nr = 1 << g.lrows_inv, SL = K * K;
   const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);
@@ -766,69 +850,189 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
   for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x)
     rtw[e] = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime], st.hi[1][prime], p);
   const size_t base = (size_t)i1_0 << m2;
-  const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, g.logN, prime, p, kk.kw[0], kk.kw[1]};
-  const int gofs[4] = {0, s.ngroups[0], s.ngroups[0] + s.ngroups[1], s.ngroups[0] + s.ngroups[1] + s.ngroups[2]};
-  const int gtot = gofs[3] + s.ngroups[3];
   const int quads = (nr << m2) >> 2;
-  for (int g0 = 0; g0 < gtot; g0 += gch) {
-    const int g1 = min(gtot, g0 + gch);
-    // tile vector (number - g0) * nr + r holds row r of that group
-    for (int q = threadIdx.x; q < 2 * quads; q += blockDim.x) {
-      const int e = q << 1, r = e >> m2, i = e & (N2 - 1);
-      mac_pair(ma, s, 0, 3, gofs, g0, g1, base + e, tile + r * ldr + pad8(i), nr * ldr);
+  // register path: one position pair (e_me, e_me + 1) per thread
+  const bool one_pair = 2 * quads == (int)blockDim.x;
+  const int e_loc = 2 * threadIdx.x;
+  u32* lds_me = tile + (e_loc >> m2) * ldr + pad8(e_loc & (N2 - 1));
+  WRegs wr;
+  int wkd = -1;
+  uint2 xr[KT], xi[KT];
+  auto fast = [&](int b) -> bool {
+    if (!one_pair || b >= b_hi) return false;
+    const int t = tlist[b];
+    const TState& s = ts[t];
+    const KernelDesc& kk = kd[td[t].kd];
+    const int gtot = s.ngroups[0] + s.ngroups[1] + s.ngroups[2] + s.ngroups[3];
+    return !s.status && s.kx[0] <= KT && s.kx[1] <= KT && kk.kw[0] <= KT && kk.kw[1] <= KT && gtot <= gch;
+  };
+  auto prefetch = [&](int b) {
+    if (!fast(b)) return;
+    const int t = tlist[b];
+    load_xregs(xr, xi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], base + e_loc);
+  };
+  prefetch(b_lo);
+  for (int b = b_lo; b < b_hi; ++b) {
+    const int t = tlist[b];
+    const TDesc& d = td[t];
+    const TState& s = ts[t];
+    if (s.status) {
+      prefetch(b + 1);
+      continue;
     }
-    __syncthreads();
-    block_ntt<true, false>(tile, m2, (g1 - g0) * nr, ldr, tw, p);
-    for (int gi = g0; gi < g1; ++gi) {
-      const int c = gi >= gofs[3] ? 3 : gi >= gofs[2] ? 2 : gi >= gofs[1] ? 1 : 0;
-      const int slot = c * SL + gi - gofs[c];
-      if (slot < slot_lo || slot >= slot_hi) continue;
-      uint4* go = reinterpret_cast<uint4*>(G + d.G_off + ((size_t)(slot * 2 + prime) << g.logN) + base);
-      const u32* tv = tile + (gi - g0) * nr * ldr;
-      for (int q = threadIdx.x; q < quads; q += blockDim.x) {
-        const int e = q << 2, r = e >> m2, j2 = e & (N2 - 1);
-        uint4 v = *reinterpret_cast<const uint4*>(tv + r * ldr + pad8(j2));
-        const uint2 t0 = rtw[e], t1 = rtw[e + 1], t2 = rtw[e + 2], t3 = rtw[e + 3];
-        v.x = shoup_mul(v.x, t0.x, t0.y, p);
-        v.y = shoup_mul(v.y, t1.x, t1.y, p);
-        v.z = shoup_mul(v.z, t2.x, t2.y, p);
-        v.w = shoup_mul(v.w, t3.x, t3.y, p);
-        go[q] = v;
+    const KernelDesc& kk = kd[d.kd];
+    const int gofs[4] = {0, s.ngroups[0], s.ngroups[0] + s.ngroups[1], s.ngroups[0] + s.ngroups[1] + s.ngroups[2]};
+    const int gtot = gofs[3] + s.ngroups[3];
+    if (fast(b)) {
+      if (d.kd != wkd) {
+        load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], base + e_loc);
+        wkd = d.kd;
       }
+      mac_regs(xr, xi, wr, s, kk.kw[0], kk.kw[1], gofs, 0, gtot, lds_me, nr * ldr, p);
+      prefetch(b + 1);
+      __syncthreads();
+      block_ntt<M2, true, false>(tile, gtot * nr, ldr, tw, p);
+      store_group_rows(G, d, tile, rtw, gofs, 0, gtot, SL, slot_lo, slot_hi, prime, g.logN, base, m2, nr, ldr, p);
+      __syncthreads();
+      continue;
     }
-    __syncthreads();
+    const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, g.logN, prime, p, kk.kw[0], kk.kw[1]};
+    for (int g0 = 0; g0 < gtot; g0 += gch) {
+      const int g1 = min(gtot, g0 + gch);
+      // tile vector (number - g0) * nr + r holds row r of that group
+      for (int q = threadIdx.x; q < 2 * quads; q += blockDim.x) {
+        const int e = q << 1, r = e >> m2, i = e & (N2 - 1);
+        mac_pair(ma, s, 0, 3, gofs, g0, g1, base + e, tile + r * ldr + pad8(i), nr * ldr);
+      }
+      __syncthreads();
+      block_ntt<M2, true, false>(tile, (g1 - g0) * nr, ldr, tw, p);
+      store_group_rows(G, d, tile, rtw, gofs, g0, g1, SL, slot_lo, slot_hi, prime, g.logN, base, m2, nr, ldr, p);
+      __syncthreads();
+    }
+    prefetch(b + 1);
   }
 }
 
-// Two-pass inverse, second pass (columns): blockIdx.y = slot*2 + prime.
-// Writes the first n natural-order outputs to the compact buffer.
+// Two-pass inverse, second pass (columns).  The group vectors of a transform
+// are numbered j = 2 gi + prime over the Alg. 8 groups gi of all four
+// convolutions; workgroup (x, y, z) takes column tile x of vectors
+// [y vpw, (y + 1) vpw) of transform z.  The tile of the next vector is
+// loaded into registers while the current one is transformed, and the first
+// n natural-order outputs go to the compact buffer.
+constexpr int COL_PF = 8;        // 16-byte registers per thread staging the next tile (tile <= 16K words)
+
+struct ColVecs {                 // group vectors of one transform (numbering j = 2 gi + prime)
+  int gofs[4], SL, slot_lo, slot_hi, j_hi;
+  __device__ __forceinline__ int slot_of(int j) const {
+    const int gi = j >> 1;
+    // selects rather than an indexed lookup (keeps gofs in registers)
+    const int c = gi >= gofs[3] ? 3 : gi >= gofs[2] ? 2 : gi >= gofs[1] ? 1 : 0;
+    const int o = gi >= gofs[3] ? gofs[3] : gi >= gofs[2] ? gofs[2] : gi >= gofs[1] ? gofs[1] : 0;
+    return c * SL + gi - o;
+  }
+  // first vector >= j whose slot lies in [slot_lo, slot_hi), or j_hi
+  __device__ __forceinline__ int next(int j) const {
+    for (; j < j_hi; ++j) {
+      const int sl = slot_of(j);
+      if (sl >= slot_lo && sl < slot_hi) break;
+    }
+    return j;
+  }
+};
+
+// The staged tile, in native 4-lane vectors (copies of the HIP uint4 struct
+// go through memcpy, which kept the stage in scratch memory).
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+struct ColStage {
+  u32x4 v0, v1, v2, v3, v4, v5, v6, v7;
+  template <int U>
+  __device__ __forceinline__ u32x4& at() {
+    static_assert(U >= 0 && U < COL_PF, "stage index");
+    if constexpr (U == 0) return v0;
+    else if constexpr (U == 1) return v1;
+    else if constexpr (U == 2) return v2;
+    else if constexpr (U == 3) return v3;
+    else if constexpr (U == 4) return v4;
+    else if constexpr (U == 5) return v5;
+    else if constexpr (U == 6) return v6;
+    else return v7;
+  }
+};
+// part u of the tile: uint4 number q = threadIdx.x + u blockDim.x, row i, columns c4..c4+3
+template <int U = 0>
+__device__ __forceinline__ void fetch_col_tile(ColStage& b, const u32* __restrict__ gv, int tot4, int lq, int m2,
+                                               int j2_0) {
+  if constexpr (U < COL_PF) {
+    const int q = threadIdx.x + U * blockDim.x;
+    if (q < tot4) {
+      const int i = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+      b.at<U>() = *reinterpret_cast<const u32x4*>(gv + (i << m2) + j2_0 + c4);
+    }
+    fetch_col_tile<U + 1>(b, gv, tot4, lq, m2, j2_0);
+  }
+}
+template <int U = 0>
+__device__ __forceinline__ void put_col_tile(ColStage& b, u32* tile, int tot4, int lq, int lc) {
+  if constexpr (U < COL_PF) {
+    const int q = threadIdx.x + U * blockDim.x;
+    if (q < tot4) {
+      const int i = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+      *reinterpret_cast<u32x4*>(tile + (i << lc) + c4) = b.at<U>();
+    }
+    put_col_tile<U + 1>(b, tile, tot4, lq, lc);
+  }
+}
+
+template <int M1>
 __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, const TDesc* td, const TState* ts,
-                                                          const int* tlist, int K, int slot_lo, NttGeom g,
-                                                          TwBlock tb) {
+                                                          const int* tlist, int K, int slot_lo, int slot_hi,
+                                                          NttGeom g, TwBlock tb, int vpw) {
   extern __shared__ u32 smem[];
   const int t = tlist[blockIdx.z];
   const TDesc& d = td[t];
   const TState& s = ts[t];
-  const int slot = slot_lo + (blockIdx.y >> 1), prime = blockIdx.y & 1;
-  const int SL = K * K, c = slot / SL, gidx = slot % SL;
-  if (s.status || gidx >= s.ngroups[c]) return;
-  const u32 p = prime_of(prime);
-  const int m1 = g.m1, m2 = g.m2, lc = g.lc, lq = lc - 2;
-  uint2* tw = reinterpret_cast<uint2*>(smem);
-  u32* tile = smem + (1 << m1);
-  load_block_tw(tw, tb.inv[prime], m1);
+  if (s.status) return;
+  ColVecs cv;
+  cv.gofs[0] = 0;
+  cv.gofs[1] = s.ngroups[0];
+  cv.gofs[2] = cv.gofs[1] + s.ngroups[1];
+  cv.gofs[3] = cv.gofs[2] + s.ngroups[2];
+  cv.SL = K * K;
+  cv.slot_lo = slot_lo;
+  cv.slot_hi = slot_hi;
+  const int gtot = cv.gofs[3] + s.ngroups[3];
+  const int j_lo = blockIdx.y * vpw;
+  cv.j_hi = min(2 * gtot, j_lo + vpw);
+  if (j_lo >= cv.j_hi) return;
+  constexpr int m1 = M1;
+  const int m2 = g.m2, lc = g.lc, lq = lc - 2, n = d.n;
+  uint2* tw0 = reinterpret_cast<uint2*>(smem);             // roots of both primes, 2^(m1-1) entries each
+  uint2* tw1 = tw0 + (1 << (m1 - 1));
+  u32* tile = smem + (2 << m1);
+  load_block_tw(tw0, tb.inv[0], m1);
+  load_block_tw(tw1, tb.inv[1], m1);
   const int j2_0 = col_tile(blockIdx.x, m2 - lc) << lc;
-  const u32* gv = G + d.G_off + ((size_t)(slot * 2 + prime) << g.logN);
-  load_cols(tile, gv, m1, m2, lc, j2_0, 1 << 30);
-  __syncthreads();
-  block_ntt<true, true>(tile, m1, lc, 0, tw, p);
-  u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.zs;   // rows padded to a multiple of 4
-  const int n = d.n;
   const int tot4 = 1 << (m1 + lq);
-  for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
-    const int j1 = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
-    const int gi = (j1 << m2) + j2_0 + c4;
-    if (gi < n) *reinterpret_cast<uint4*>(zo + gi) = *reinterpret_cast<const uint4*>(tile + (j1 << lc) + c4);
+  const u32* gbase = G + d.G_off;
+  ColStage buf;
+  int j = cv.next(j_lo);
+  if (j < cv.j_hi) fetch_col_tile(buf, gbase + ((size_t)(cv.slot_of(j) * 2 + (j & 1)) << g.logN), tot4, lq, m2, j2_0);
+  __syncthreads();                    // root tables
+  while (j < cv.j_hi) {
+    const int prime = j & 1, slot = cv.slot_of(j);
+    put_col_tile(buf, tile, tot4, lq, lc);
+    __syncthreads();
+    const int jn = cv.next(j + 1);
+    if (jn < cv.j_hi) fetch_col_tile(buf, gbase + ((size_t)(cv.slot_of(jn) * 2 + (jn & 1)) << g.logN), tot4, lq, m2, j2_0);
+    block_ntt<M1, true, true>(tile, lc, 0, prime ? tw1 : tw0, prime_of(prime));
+    u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.zs;   // rows padded to a multiple of 4
+    for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
+      const int j1 = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+      const int gi = (j1 << m2) + j2_0 + c4;
+      if (gi < n) *reinterpret_cast<uint4*>(zo + gi) = *reinterpret_cast<const uint4*>(tile + (j1 << lc) + c4);
+    }
+    __syncthreads();
+    j = jn;
   }
 }
 
@@ -879,6 +1083,7 @@ NttGeom ntt_geom(int logN, int lc_override, int lrows_override) {
 }
 
 static size_t smem_cols(const NttGeom& g) { return ((size_t)(1 << g.m1) + ((size_t)1 << (g.m1 + g.lc))) * 4; }
+static size_t smem_inv_cols(const NttGeom& g) { return ((size_t)(2 << g.m1) + ((size_t)1 << (g.m1 + g.lc))) * 4; }
 static size_t smem_rows(const NttGeom& g) {
   return ((size_t)(1 << g.m2) + ((size_t)row_ld(1 << g.m2) << g.lrows) + rowtw_words(g.m2, 1 << g.lrows)) * 4;
 }
@@ -892,63 +1097,115 @@ static size_t smem_inv_single(int logN) {
   return ((size_t)(1 << logN) + (size_t)row_ld(1 << logN) * (size_t)inv_vmax(logN)) * 4;
 }
 
-static hipError_t allow_big_lds() {
-  static bool done = false;
-  if (done) return hipSuccess;
-  const int lim = 160 * 1024;
-  const void* fns[] = {(const void*)k_std_single, (const void*)k_std_fwd_cols, (const void*)k_std_fwd_rows,
-                       (const void*)k_std_inv_rows, (const void*)k_std_inv_cols, (const void*)k_fwd_single,
-                       (const void*)k_fwd_cols, (const void*)k_fwd_rows, (const void*)k_inv_single,
-                       (const void*)k_inv_rows, (const void*)k_inv_cols};
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
+// Kernels are instantiated per block length: calls f(integral_constant<M>)
+// for m in [LO, HI]; false when m is out of range.
+template <int LO, int HI, typename F>
+static bool with_m(int m, F&& f) {
+  if constexpr (LO > HI) {
+    return false;
+  } else {
+    if (m == LO) {
+      f(std::integral_constant<int, LO>{});
+      return true;
+    }
+    return with_m<LO + 1, HI>(m, std::forward<F>(f));
   }
-  done = true;
-  return hipSuccess;
+}
+// Column lengths 2^m1 and row lengths 2^m2 of the two-pass geometry
+// (N = 2^13 .. 2^24) and single-workgroup lengths (N <= 2^12).
+constexpr int M1_LO = 7, M1_HI = 12, M2_LO = 6, M2_HI = 12;
+
+// Opts a kernel into the full 160 KiB of LDS once per process.
+static hipError_t big_lds(const void* fn) {
+  static std::mutex mu;
+  static std::unordered_set<const void*> done;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count(fn)) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess) done.insert(fn);
+  return e;
 }
 
 hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool inverse, const NttGeom& g,
                                  const TwBlock& tb, const TwStep& ts, hipStream_t s) {
-  hipError_t e = allow_big_lds();
-  if (e != hipSuccess) return e;
   if (count <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
   if (!g.two_pass()) {
-    hipLaunchKernelGGL(k_std_single, dim3(1, 1, count), dim3(NTT_THREADS), smem_single(logN), s, data, logN, prime,
-                       inverse, tb);
-    return hipGetLastError();
+    if (!with_m<0, LOG2_BLOCK_MAX>(logN, [&](auto mc) {
+          constexpr int M = decltype(mc)::value;
+          if ((e = big_lds((const void*)k_std_single<M>)) != hipSuccess) return;
+          hipLaunchKernelGGL(k_std_single<M>, dim3(1, 1, count), dim3(NTT_THREADS), smem_single(logN), s, data, prime,
+                             inverse, tb);
+        }))
+      return hipErrorInvalidValue;
+    return e != hipSuccess ? e : hipGetLastError();
   }
   const dim3 gc(1u << (g.m2 - g.lc), 1, count), gr(1u << (g.m1 - g.lrows), 1, count);
+  auto cols = [&](auto mc) {
+    constexpr int M1 = decltype(mc)::value;
+    if (!inverse) {
+      if ((e = big_lds((const void*)k_std_fwd_cols<M1>)) != hipSuccess) return;
+      hipLaunchKernelGGL(k_std_fwd_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, ts);
+    } else {
+      if ((e = big_lds((const void*)k_std_inv_cols<M1>)) != hipSuccess) return;
+      hipLaunchKernelGGL(k_std_inv_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb);
+    }
+  };
+  auto rows = [&](auto mc) {
+    constexpr int M2 = decltype(mc)::value;
+    if (!inverse) {
+      if ((e = big_lds((const void*)k_std_fwd_rows<M2>)) != hipSuccess) return;
+      hipLaunchKernelGGL(k_std_fwd_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
+    } else {
+      if ((e = big_lds((const void*)k_std_inv_rows<M2>)) != hipSuccess) return;
+      hipLaunchKernelGGL(k_std_inv_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
+    }
+  };
   if (!inverse) {
-    hipLaunchKernelGGL(k_std_fwd_cols, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, ts);
-    hipLaunchKernelGGL(k_std_fwd_rows, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
+    if (!with_m<M1_LO, M1_HI>(g.m1, cols)) return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+    if (!with_m<M2_LO, M2_HI>(g.m2, rows)) return hipErrorInvalidValue;
   } else {
-    hipLaunchKernelGGL(k_std_inv_rows, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
-    hipLaunchKernelGGL(k_std_inv_cols, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb);
+    if (!with_m<M2_LO, M2_HI>(g.m2, rows)) return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+    if (!with_m<M1_LO, M1_HI>(g.m1, cols)) return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, bool valid_full,
                             int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb, const TwStep& st, int which,
                             hipStream_t s) {
-  hipError_t e = allow_big_lds();
-  if (e != hipSuccess) return e;
   const int nv = vi_hi - vi_lo;
   if (count <= 0 || nv <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
   if (!g.two_pass()) {
     if (which == 2) return hipSuccess;
-    hipLaunchKernelGGL(k_fwd_single, dim3(1, nv, count), dim3(NTT_THREADS), smem_single(g.logN), s, X, td, ts, tlist,
-                       K, valid_full, vi_lo, g.logN, tb);
-    return hipGetLastError();
+    if (!with_m<0, LOG2_BLOCK_MAX>(g.logN, [&](auto mc) {
+          constexpr int M = decltype(mc)::value;
+          if ((e = big_lds((const void*)k_fwd_single<M>)) != hipSuccess) return;
+          hipLaunchKernelGGL(k_fwd_single<M>, dim3(1, nv, count), dim3(NTT_THREADS), smem_single(g.logN), s, X, td, ts,
+                             tlist, K, valid_full, vi_lo, tb);
+        }))
+      return hipErrorInvalidValue;
+    return e != hipSuccess ? e : hipGetLastError();
   }
-  if (which != 2)
-    hipLaunchKernelGGL(k_fwd_cols, dim3(1u << (g.m2 - g.lc), nv, count), dim3(COL_THREADS), smem_cols(g), s, X, td,
-                       ts, tlist, K, valid_full, vi_lo, g, tb, st);
-  if (which != 1)
-    hipLaunchKernelGGL(k_fwd_rows, dim3(1u << (g.m1 - g.lrows), nv, count), dim3(NTT_THREADS), smem_rows(g), s, X,
-                       td, ts, tlist, K, valid_full, vi_lo, g, tb, st);
-  return hipGetLastError();
+  if (which != 2 && !with_m<M1_LO, M1_HI>(g.m1, [&](auto mc) {
+        constexpr int M1 = decltype(mc)::value;
+        if ((e = big_lds((const void*)k_fwd_cols<M1>)) != hipSuccess) return;
+        hipLaunchKernelGGL(k_fwd_cols<M1>, dim3(1u << (g.m2 - g.lc), nv, count), dim3(COL_THREADS), smem_cols(g), s, X,
+                           td, ts, tlist, K, valid_full, vi_lo, g, tb, st);
+      }))
+    return hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
+  if (which != 1 && !with_m<M2_LO, M2_HI>(g.m2, [&](auto mc) {
+        constexpr int M2 = decltype(mc)::value;
+        if ((e = big_lds((const void*)k_fwd_rows<M2>)) != hipSuccess) return;
+        hipLaunchKernelGGL(k_fwd_rows<M2>, dim3(1u << (g.m1 - g.lrows), nv, count), dim3(NTT_THREADS), smem_rows(g), s,
+                           X, td, ts, tlist, K, valid_full, vi_lo, g, tb, st);
+      }))
+    return hipErrorInvalidValue;
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K,
@@ -960,22 +1217,49 @@ hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const 
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
                             const TwBlock& tb, const TwStep& st, int which, hipStream_t s) {
-  hipError_t e = allow_big_lds();
-  if (e != hipSuccess) return e;
   if (count <= 0 || slot_hi <= slot_lo) return hipSuccess;
+  hipError_t e = hipSuccess;
   if (!g.two_pass()) {
     if (which == 2) return hipSuccess;
-    hipLaunchKernelGGL(k_inv_single, dim3(8 * count), dim3(NTT_THREADS), smem_inv_single(g.logN), s, X, Z, td, ts,
-                       kd, tlist, count, K, slot_lo, slot_hi, g.logN, tb);
-    return hipGetLastError();
+    if (!with_m<0, LOG2_BLOCK_MAX>(g.logN, [&](auto mc) {
+          constexpr int M = decltype(mc)::value;
+          if ((e = big_lds((const void*)k_inv_single<M>)) != hipSuccess) return;
+          hipLaunchKernelGGL(k_inv_single<M>, dim3(8 * count), dim3(NTT_THREADS), smem_inv_single(g.logN), s, X, Z, td,
+                             ts, kd, tlist, count, K, slot_lo, slot_hi, tb);
+        }))
+      return hipErrorInvalidValue;
+    return e != hipSuccess ? e : hipGetLastError();
   }
-  if (which != 2)
-    hipLaunchKernelGGL(k_inv_rows, dim3((2u << (g.m1 - g.lrows_inv)) * count), dim3(NTT_THREADS), smem_inv_rows(g), s,
-                       X, G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st);
-  if (which != 1)
-    hipLaunchKernelGGL(k_inv_cols, dim3(1u << (g.m2 - g.lc), 2 * (slot_hi - slot_lo), count), dim3(COL_THREADS),
-                       smem_cols(g), s, G, Z, td, ts, tlist, K, slot_lo, g, tb);
-  return hipGetLastError();
+  if (which != 2) {
+    // runs of up to four transforms per workgroup while the grid keeps
+    // at least about four workgroups per CU slot (3 per CU on 256 CUs)
+    const long pairs = 2l << (g.m1 - g.lrows_inv);
+    int tpw = 1;
+    while (tpw < 4 && 2 * tpw <= count && pairs * ((count + 2 * tpw - 1) / (2 * tpw)) >= 3072) tpw *= 2;
+    const long runs = (count + tpw - 1) / tpw;
+    if (!with_m<M2_LO, M2_HI>(g.m2, [&](auto mc) {
+          constexpr int M2 = decltype(mc)::value;
+          if ((e = big_lds((const void*)k_inv_rows<M2>)) != hipSuccess) return;
+          hipLaunchKernelGGL(k_inv_rows<M2>, dim3((unsigned)(pairs * runs)), dim3(NTT_THREADS), smem_inv_rows(g), s, X,
+                             G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
+        }))
+      return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+  }
+  if (which != 1) {
+    // the staged next tile must fit COL_PF 16-byte registers per thread
+    if (g.m1 + g.lc > 14) return hipErrorInvalidValue;
+    const int vecs = 8 * K * K, vpw = 4;    // group vectors (at most 4 K^2 groups, two primes)
+    const dim3 grid(1u << (g.m2 - g.lc), (vecs + vpw - 1) / vpw, count);
+    if (!with_m<M1_LO, M1_HI>(g.m1, [&](auto mc) {
+          constexpr int M1 = decltype(mc)::value;
+          if ((e = big_lds((const void*)k_inv_cols<M1>)) != hipSuccess) return;
+          hipLaunchKernelGGL(k_inv_cols<M1>, grid, dim3(COL_THREADS), smem_inv_cols(g), s, G, Z, td, ts, tlist, K,
+                             slot_lo, slot_hi, g, tb, vpw);
+        }))
+      return hipErrorInvalidValue;
+  }
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts,

@@ -194,7 +194,9 @@ static int autotune_geom(fft_ozaki_plan_s* p, int logN, NttGeom* out) {
   if (!def.two_pass()) return FFT_OZAKI_OK;
   const std::string key = tune_key(logN);
   int lc = -1, lr = -1;
-  if (tune_lookup(p->tune_cache, key, &lc, &lr)) {
+  // a cached entry is used only if it is one of the shapes tried below
+  if (tune_lookup(p->tune_cache, key, &lc, &lr) && lc >= 2 && lc <= 6 && def.m1 + lc <= 14 && lc <= def.m2 &&
+      lr >= 0 && lr <= 4 && def.m2 + lr <= 14 && lr <= def.m1) {
     *out = ntt_geom(logN, lc, lr);
     return FFT_OZAKI_OK;
   }
@@ -209,7 +211,7 @@ static int autotune_geom(fft_ozaki_plan_s* p, int logN, NttGeom* out) {
   HIPCHK(hipEventCreate(&e1));
   float best = 1e30f;
   for (int c = 2; c <= 6; ++c) {
-    if (def.m1 + c > 15 || c > def.m2) continue;
+    if (def.m1 + c > 14 || c > def.m2) continue;
     for (int r = 0; r <= 4; ++r) {
       if (def.m2 + r > 14 || r > def.m1) continue;
       NttGeom g = ntt_geom(logN, c, r);
