@@ -566,11 +566,22 @@ __device__ __forceinline__ void mac_acc(uint2& acc, const uint2& x, const uint2&
   acc.y = add_mod(acc.y, shoup_mul(x.y, w.y, q.y, p), p);
 }
 
-// one convolution from register-held slices (kA, kB <= KT)
-__device__ __forceinline__ void walk_regs(const uint2 (&xv)[KT], const uint2 (&wv)[KT], const uint2 (&qv)[KT], int kA,
-                                          int kB, u64 gend, int gbase, int g0, int g1, u32* lds0, int rstride, u32 p) {
+__device__ __forceinline__ void mac_acc(u32& acc, u32 x, u32 w, u32 q, u32 p) {
+  acc = add_mod(acc, shoup_mul(x, w, q, p), p);
+}
+__device__ __forceinline__ void zero_acc(uint2& a) { a = make_uint2(0, 0); }
+__device__ __forceinline__ void zero_acc(u32& a) { a = 0; }
+__device__ __forceinline__ void put_acc(u32* ptr, const uint2& a) { *reinterpret_cast<uint2*>(ptr) = a; }
+__device__ __forceinline__ void put_acc(u32* ptr, u32 a) { *ptr = a; }
+
+// one convolution from register-held slices (kA, kB <= KT); V is u32 (one
+// position) or uint2 (two adjacent positions)
+template <typename V>
+__device__ __forceinline__ void walk_regs(const V (&xv)[KT], const V (&wv)[KT], const V (&qv)[KT], int kA, int kB,
+                                          u64 gend, int gbase, int g0, int g1, u32* lds0, int rstride, u32 p) {
   int w = 0, g = gbase;
-  uint2 acc = make_uint2(0, 0);
+  V acc;
+  zero_acc(acc);
 #pragma unroll
   for (int d = 2 * KT - 2; d >= 0; --d) {
 #pragma unroll
@@ -579,8 +590,8 @@ __device__ __forceinline__ void walk_regs(const uint2 (&xv)[KT], const uint2 (&w
       if (ss < kA && tt < kB) {
         mac_acc(acc, xv[ss], wv[tt], qv[tt], p);
         if ((gend >> w) & 1) {
-          if (g >= g0 && g < g1) *reinterpret_cast<uint2*>(lds0 + (g - g0) * rstride) = acc;
-          acc = make_uint2(0, 0);
+          if (g >= g0 && g < g1) put_acc(lds0 + (g - g0) * rstride, acc);
+          zero_acc(acc);
           ++g;
         }
         ++w;
@@ -613,10 +624,14 @@ __device__ void walk_mem(const MacArgs& a, const TState& s, int c, int gbase, in
 
 // Kernel-slice operands of positions e, e+1 held in registers (<= KT slices
 // per part): Re w* slices with companions (w0, q0), Im w* (w1, q1).
+template <typename V>
 struct WRegs {
-  uint2 w0[KT], q0[KT], w1[KT], q1[KT];
+  V w0[KT], q0[KT], w1[KT], q1[KT];
 };
-__device__ __forceinline__ void load_wregs(WRegs& r, const u32* W, const u32* Wq, int K, int logN, int prime,
+__device__ __forceinline__ void ldv(uint2& v, const u32* ptr) { v = ld2(ptr); }
+__device__ __forceinline__ void ldv(u32& v, const u32* ptr) { v = *ptr; }
+template <typename V>
+__device__ __forceinline__ void load_wregs(WRegs<V>& r, const u32* W, const u32* Wq, int K, int logN, int prime,
                                            int kw0, int kw1, size_t e) {
   const size_t N = (size_t)1 << logN, sstride = 2 * N, part = (size_t)K * sstride;
   const u32* wb = W + (size_t)prime * N + e;
@@ -624,29 +639,31 @@ __device__ __forceinline__ void load_wregs(WRegs& r, const u32* W, const u32* Wq
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     if (k < kw0) {
-      r.w0[k] = ld2(wb + k * sstride);
-      r.q0[k] = ld2(qb + k * sstride);
+      ldv(r.w0[k], wb + k * sstride);
+      ldv(r.q0[k], qb + k * sstride);
     }
     if (k < kw1) {
-      r.w1[k] = ld2(wb + part + k * sstride);
-      r.q1[k] = ld2(qb + part + k * sstride);
+      ldv(r.w1[k], wb + part + k * sstride);
+      ldv(r.q1[k], qb + part + k * sstride);
     }
   }
 }
 // Slice spectra of Re x' (xr) and Im x' (xi) at positions e, e+1.
-__device__ __forceinline__ void load_xregs(uint2 (&xr)[KT], uint2 (&xi)[KT], const u32* X, int K, int logN,
-                                           int prime, int kx0, int kx1, size_t e) {
+template <typename V>
+__device__ __forceinline__ void load_xregs(V (&xr)[KT], V (&xi)[KT], const u32* X, int K, int logN, int prime, int kx0,
+                                           int kx1, size_t e) {
   const size_t N = (size_t)1 << logN, sstride = 2 * N, part = (size_t)K * sstride;
   const u32* xb = X + (size_t)prime * N + e;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
-    if (k < kx0) xr[k] = ld2(xb + k * sstride);
-    if (k < kx1) xi[k] = ld2(xb + part + k * sstride);
+    if (k < kx0) ldv(xr[k], xb + k * sstride);
+    if (k < kx1) ldv(xi[k], xb + part + k * sstride);
   }
 }
 // All four convolutions from register operands; groups [g0, g1) go to LDS.
 // Re x' feeds ReRe (0) and ReIm (3); Im x' feeds ImIm (1) and ImRe (2).
-__device__ __forceinline__ void mac_regs(const uint2 (&xr)[KT], const uint2 (&xi)[KT], const WRegs& r,
+template <typename V>
+__device__ __forceinline__ void mac_regs(const V (&xr)[KT], const V (&xi)[KT], const WRegs<V>& r,
                                          const TState& s, int kw0, int kw1, const int (&gofs)[4], int g0, int g1,
                                          u32* lds0, int rstride, u32 p) {
   const int kx0 = s.kx[0], kx1 = s.kx[1];
@@ -822,10 +839,85 @@ __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u
 // and run of up to tpw consecutive transforms of the list.  Per transform:
 // multiply-accumulate into LDS (normally all groups of the four
 // convolutions at once), inverse row NTTs, twiddle w_N^{-j2 k1}, store the
-// group rows.  The block roots, the row twiddles and (when each thread
-// owns one position pair and a transform's slices fit the register path)
-// the kernel-slice operands are set up once per run, and the slice spectra
-// of the next transform are loaded while the current one is transformed.
+// group rows.  The block roots and the row twiddles are set up once per run.
+//
+// Register form (K <= KT, row tile of INV_ROW_THREADS positions): one
+// position per thread, the kernel-slice operands stay in registers for the
+// run and the slice spectra of the next transform load while the current
+// one is transformed; more groups than one chunk holds recompute the
+// products from the registers per chunk.
+constexpr int INV_ROW_THREADS = 512;
+template <int M2>
+__global__ void __launch_bounds__(INV_ROW_THREADS) k_inv_rows_reg(const u32* X, u32* G, const TDesc* td,
+                                                                  const TState* ts, const KernelDesc* kd,
+                                                                  const int* tlist, int count, int K, int slot_lo,
+                                                                  int slot_hi, NttGeom g, TwBlock tb, TwStep st,
+                                                                  int tpw) {
+  extern __shared__ u32 smem[];
+  const int nruns = (count + tpw - 1) / tpw;
+  int pair, run;
+  decode_tile(blockIdx.x, 2 << (g.m1 - g.lrows_inv), nruns, pair, run);
+  const int b_lo = run * tpw, b_hi = min(count, b_lo + tpw);
+  const int prime = pair & 1;
+  const u32 p = prime_of(prime);
+  constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
+  const int nr = 1 << g.lrows_inv, SL = K * K;
+  const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
+  const u32 Nmask = (1u << g.logN) - 1;
+  uint2* tw = reinterpret_cast<uint2*>(smem);
+  uint2* rtw = tw + (N2 >> 1);                                // w_N^{-j2 k1} per tile element
+  u32* tile = smem + N2 + 2 * (nr << m2);
+  load_block_tw(tw, tb.inv[prime], m2);
+  const int i1_0 = (pair >> 1) << g.lrows_inv;
+  for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x)
+    rtw[e] = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime], st.hi[1][prime], p);
+  const size_t base = (size_t)i1_0 << m2;
+  const int e_loc = threadIdx.x;                              // this thread's position in the tile
+  u32* lds_me = tile + (e_loc >> m2) * ldr + pad8(e_loc & (N2 - 1));
+  WRegs<u32> wr;
+  int wkd = -1;
+  u32 xr[KT], xi[KT];
+  int bn = b_lo;                                              // transform whose slices are in xr, xi
+  while (bn < b_hi && ts[tlist[bn]].status) ++bn;
+  if (bn < b_hi) {
+    const int t = tlist[bn];
+    load_xregs(xr, xi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], base + e_loc);
+  }
+  while (bn < b_hi) {
+    const int t = tlist[bn];
+    const TDesc& d = td[t];
+    const TState& s = ts[t];
+    const KernelDesc& kk = kd[d.kd];
+    if (d.kd != wkd) {
+      load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], base + e_loc);
+      wkd = d.kd;
+    }
+    const int gofs[4] = {0, s.ngroups[0], s.ngroups[0] + s.ngroups[1], s.ngroups[0] + s.ngroups[1] + s.ngroups[2]};
+    const int gtot = gofs[3] + s.ngroups[3];
+    int b2 = bn + 1;
+    while (b2 < b_hi && ts[tlist[b2]].status) ++b2;
+    for (int g0 = 0; g0 < gtot; g0 += gch) {
+      const int g1 = min(gtot, g0 + gch);
+      mac_regs(xr, xi, wr, s, kk.kw[0], kk.kw[1], gofs, g0, g1, lds_me, nr * ldr, p);
+      if (g1 == gtot && b2 < b_hi) {                          // slices consumed: fetch the next transform's
+        const int t2 = tlist[b2];
+        load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], base + e_loc);
+      }
+      __syncthreads();
+      block_ntt<M2, true, false>(tile, (g1 - g0) * nr, ldr, tw, p);
+      store_group_rows(G, d, tile, rtw, gofs, g0, g1, SL, slot_lo, slot_hi, prime, g.logN, base, m2, nr, ldr, p);
+      __syncthreads();
+    }
+    if (gtot == 0 && b2 < b_hi) {                             // no groups (all-zero input): still advance
+      const int t2 = tlist[b2];
+      load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], base + e_loc);
+    }
+    bn = b2;
+  }
+}
+
+// General form (any slice counts and tile shape): operands read per
+// position pair from memory, one transform after the other.
 template <int M2>
 __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, const TDesc* td, const TState* ts,
                                                           const KernelDesc* kd, const int* tlist, int count, int K,
@@ -851,51 +943,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
     rtw[e] = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime], st.hi[1][prime], p);
   const size_t base = (size_t)i1_0 << m2;
   const int quads = (nr << m2) >> 2;
-  // register path: one position pair (e_me, e_me + 1) per thread
-  const bool one_pair = 2 * quads == (int)blockDim.x;
-  const int e_loc = 2 * threadIdx.x;
-  u32* lds_me = tile + (e_loc >> m2) * ldr + pad8(e_loc & (N2 - 1));
-  WRegs wr;
-  int wkd = -1;
-  uint2 xr[KT], xi[KT];
-  auto fast = [&](int b) -> bool {
-    if (!one_pair || b >= b_hi) return false;
-    const int t = tlist[b];
-    const TState& s = ts[t];
-    const KernelDesc& kk = kd[td[t].kd];
-    const int gtot = s.ngroups[0] + s.ngroups[1] + s.ngroups[2] + s.ngroups[3];
-    return !s.status && s.kx[0] <= KT && s.kx[1] <= KT && kk.kw[0] <= KT && kk.kw[1] <= KT && gtot <= gch;
-  };
-  auto prefetch = [&](int b) {
-    if (!fast(b)) return;
-    const int t = tlist[b];
-    load_xregs(xr, xi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], base + e_loc);
-  };
-  prefetch(b_lo);
   for (int b = b_lo; b < b_hi; ++b) {
     const int t = tlist[b];
     const TDesc& d = td[t];
     const TState& s = ts[t];
-    if (s.status) {
-      prefetch(b + 1);
-      continue;
-    }
+    if (s.status) continue;
     const KernelDesc& kk = kd[d.kd];
     const int gofs[4] = {0, s.ngroups[0], s.ngroups[0] + s.ngroups[1], s.ngroups[0] + s.ngroups[1] + s.ngroups[2]};
     const int gtot = gofs[3] + s.ngroups[3];
-    if (fast(b)) {
-      if (d.kd != wkd) {
-        load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], base + e_loc);
-        wkd = d.kd;
-      }
-      mac_regs(xr, xi, wr, s, kk.kw[0], kk.kw[1], gofs, 0, gtot, lds_me, nr * ldr, p);
-      prefetch(b + 1);
-      __syncthreads();
-      block_ntt<M2, true, false>(tile, gtot * nr, ldr, tw, p);
-      store_group_rows(G, d, tile, rtw, gofs, 0, gtot, SL, slot_lo, slot_hi, prime, g.logN, base, m2, nr, ldr, p);
-      __syncthreads();
-      continue;
-    }
     const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, g.logN, prime, p, kk.kw[0], kk.kw[1]};
     for (int g0 = 0; g0 < gtot; g0 += gch) {
       const int g1 = min(gtot, g0 + gch);
@@ -909,7 +964,6 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
       store_group_rows(G, d, tile, rtw, gofs, g0, g1, SL, slot_lo, slot_hi, prime, g.logN, base, m2, nr, ldr, p);
       __syncthreads();
     }
-    prefetch(b + 1);
   }
 }
 
@@ -1237,11 +1291,20 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
     int tpw = 1;
     while (tpw < 4 && 2 * tpw <= count && pairs * ((count + 2 * tpw - 1) / (2 * tpw)) >= 3072) tpw *= 2;
     const long runs = (count + tpw - 1) / tpw;
+    // register form: slices fit the registers and the row tile has one
+    // position per thread
+    const bool reg = K <= KT && (1 << (g.m2 + g.lrows_inv)) == INV_ROW_THREADS;
     if (!with_m<M2_LO, M2_HI>(g.m2, [&](auto mc) {
           constexpr int M2 = decltype(mc)::value;
-          if ((e = big_lds((const void*)k_inv_rows<M2>)) != hipSuccess) return;
-          hipLaunchKernelGGL(k_inv_rows<M2>, dim3((unsigned)(pairs * runs)), dim3(NTT_THREADS), smem_inv_rows(g), s, X,
-                             G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
+          if (reg) {
+            if ((e = big_lds((const void*)k_inv_rows_reg<M2>)) != hipSuccess) return;
+            hipLaunchKernelGGL(k_inv_rows_reg<M2>, dim3((unsigned)(pairs * runs)), dim3(INV_ROW_THREADS),
+                               smem_inv_rows(g), s, X, G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
+          } else {
+            if ((e = big_lds((const void*)k_inv_rows<M2>)) != hipSuccess) return;
+            hipLaunchKernelGGL(k_inv_rows<M2>, dim3((unsigned)(pairs * runs)), dim3(NTT_THREADS), smem_inv_rows(g), s,
+                               X, G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
+          }
         }))
       return hipErrorInvalidValue;
     if (e != hipSuccess) return e;

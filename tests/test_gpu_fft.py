@@ -189,6 +189,31 @@ def test_special_inputs(torch_mod):
         assert max_ulp(y[b], tr["y"]) == 0
 
 
+def test_special_inputs_two_pass_runs(torch_mod):
+    """Special transforms inside the multi-transform runs of the two-pass
+    inverse (64 x n = 2^14, two transforms per inverse-row workgroup): an
+    all-zero transform (no groups), a non-finite one and an out-of-range one
+    (status set, skipped), one whose premultiplied input is real (no slices
+    of Im x'), and their neighbours, all bit-identical to the oracle."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 16384
+    x = wl.batch_16k(1)
+    x[1] = 0
+    x[2, 100] = np.inf
+    x[3] *= 2.0 ** 1000
+    x[4] = 0
+    x[4, 0] = 1.5             # x' = x (.) w is real: one slice of Re x', none of Im x'
+    x[6, 9] = 1e-300
+    plan = oz.Plan(n, 64)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan(n, 3, 3)
+    for b in (0, 1, 2, 3, 4, 5, 6, 7, 63):
+        tr = bl.forward_trace(x[b], 3, 3, kp)
+        assert plan.transform_info(b)["status"] == tr["status"], b
+        assert max_ulp(y[b], tr["y"]) == 0, b
+
+
 def test_batch_16k_roundtrip(torch_mod):
     """64 transforms at n = 2^14 (N = 2^15): two sampled transforms compared
     with the oracle, all 64 round-tripped through the inverse."""
