@@ -64,7 +64,7 @@ constexpr int KT = 3;            // slices per operand handled from registers in
 // compile-time offsets from tw + (off << s).  When ST = 1 (off = 0) the roots
 // of the round are the same for every group (`twr`, preloaded) and those with
 // j mod hd = 0 are 1, so those butterflies skip the product.
-template <int RL, int S0, int ST, bool INV>
+template <int RL, int S0, int ST, bool INV, bool HOIST>
 __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const uint2* __restrict__ tw,
                                               const uint2 (&twr)[1 << RL], u32 p) {
   constexpr int R = 1 << RL;
@@ -80,7 +80,7 @@ __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const 
       const int jj = j & (hd - 1);
       const bool trivial = (ST == 1) && jj == 0;
       uint2 w = make_uint2(1u, 0u);
-      if (!trivial) w = (ST == 1) ? twr[hd + jj] : tws[(jj * ST) << s];
+      if (!trivial) w = (ST == 1 || HOIST) ? twr[hd + jj] : tws[(jj * ST) << s];
       const u32 x = a[j], y = a[j + hd];
       if (!INV) {
         a[j] = add_mod(x, y, p);
@@ -94,21 +94,13 @@ __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const 
   }
 }
 
-// One round of a length-2^M block NTT over the vectors of a tile.
-// nv: number of vectors (row layout) or log2 of it (column layout).
-template <int M, int S0, int RL, bool INV, bool COLS>
-__device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* __restrict__ tw, u32 p) {
+// The groups of one round.  HOIST: every group a thread visits has the same
+// offset (row layout with blockDim a multiple of the groups per vector), so
+// its roots were loaded into twr once for the round.
+template <int M, int S0, int RL, bool INV, bool COLS, bool HOIST>
+__device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const uint2* __restrict__ tw,
+                                             const uint2 (&twr)[1 << RL], u32 p) {
   constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
-  uint2 twr[R];
-  if (ST == 1) {
-    // roots of this round, shared by all groups: stage S0+ss uses twr[hd + jj] = w^(jj << s)
-#pragma unroll
-    for (int ss = 0; ss < RL; ++ss) {
-      const int hd = R >> (ss + 1);
-#pragma unroll
-      for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = tw[jj << (S0 + ss)];
-    }
-  }
   const int total = COLS ? (1 << (nv + LGPV)) : (nv << LGPV);
   const int sst = COLS ? (ST << nv) : 0;     // element stride of a group, column layout
   for (int g = threadIdx.x; g < total; g += blockDim.x) {
@@ -133,20 +125,55 @@ __device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* 
         a[j + 2] = t.z;
         a[j + 3] = t.w;
       }
-      radix_group_t<RL, S0, ST, INV>(a, off, tw, twr, p);
+      radix_group_t<RL, S0, ST, INV, HOIST>(a, off, tw, twr, p);
 #pragma unroll
       for (int j = 0; j < R; j += 4) *reinterpret_cast<uint4*>(p0 + j) = make_uint4(a[j], a[j + 1], a[j + 2], a[j + 3]);
       continue;
     }
 #pragma unroll
     for (int j = 0; j < R; ++j) a[j] = COLS ? p0[j * sst] : p0[pad8(j * ST)];
-    radix_group_t<RL, S0, ST, INV>(a, off, tw, twr, p);
+    radix_group_t<RL, S0, ST, INV, HOIST>(a, off, tw, twr, p);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       if (COLS) p0[j * sst] = a[j];
       else p0[pad8(j * ST)] = a[j];
     }
   }
+}
+
+// One round of a length-2^M block NTT over the vectors of a tile.
+// nv: number of vectors (row layout) or log2 of it (column layout).  The
+// roots a thread needs are read from LDS once per round when they are the
+// same for all its groups (twr[hd + jj] for stage S0 + ss, hd = R >> (ss+1)):
+// always when ST = 1, and in the row layout when blockDim is a multiple of
+// the groups per vector (then the lanes of a stage would otherwise read the
+// strided table w^((off + jj ST) 2^s) once per group, on few LDS banks).
+template <int M, int S0, int RL, bool INV, bool COLS>
+__device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* __restrict__ tw, u32 p) {
+  constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
+  uint2 twr[R];
+  if (ST == 1) {
+#pragma unroll
+    for (int ss = 0; ss < RL; ++ss) {
+      const int hd = R >> (ss + 1);
+#pragma unroll
+      for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = tw[jj << (S0 + ss)];
+    }
+    round_groups<M, S0, RL, INV, COLS, false>(lds, nv, ldr, tw, twr, p);
+    return;
+  }
+  if (!COLS && (blockDim.x & ((1u << LGPV) - 1)) == 0) {
+    const int off = (int)(threadIdx.x & ((1u << LGPV) - 1)) & (ST - 1);
+#pragma unroll
+    for (int ss = 0; ss < RL; ++ss) {
+      const int hd = R >> (ss + 1);
+#pragma unroll
+      for (int jj = 0; jj < hd; ++jj) twr[hd + jj] = tw[(off + jj * ST) << (S0 + ss)];
+    }
+    round_groups<M, S0, RL, INV, COLS, true>(lds, nv, ldr, tw, twr, p);
+    return;
+  }
+  round_groups<M, S0, RL, INV, COLS, false>(lds, nv, ldr, tw, twr, p);
 }
 
 // Rounds I.. of a length-2^M block NTT: ceil(M/3) rounds, the M stages spread
@@ -811,7 +838,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
 }
 
 // Group rows [g0, g1) of the tile: times w_N^{-j2 k1}, stored to their slots.
-__device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u32* tile, const uint2* rtw,
+__device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u32* tile, const u32* rtw,
                                                  const int (&gofs)[4], int g0, int g1, int SL, int slot_lo,
                                                  int slot_hi, int prime, int logN, size_t base, int m2, int nr,
                                                  int ldr, u32 p) {
@@ -825,11 +852,13 @@ __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u
     for (int q = threadIdx.x; q < quads; q += blockDim.x) {
       const int e = q << 2, r = e >> m2, j2 = e & (N2 - 1);
       uint4 v = *reinterpret_cast<const uint4*>(tv + r * ldr + pad8(j2));
-      const uint2 t0 = rtw[e], t1 = rtw[e + 1], t2 = rtw[e + 2], t3 = rtw[e + 3];
-      v.x = shoup_mul(v.x, t0.x, t0.y, p);
-      v.y = shoup_mul(v.y, t1.x, t1.y, p);
-      v.z = shoup_mul(v.z, t2.x, t2.y, p);
-      v.w = shoup_mul(v.w, t3.x, t3.y, p);
+      // roots and companions in separate arrays: 16 contiguous bytes per lane
+      const uint4 w = *reinterpret_cast<const uint4*>(rtw + e);
+      const uint4 wq = *reinterpret_cast<const uint4*>(rtw + (nr << m2) + e);
+      v.x = shoup_mul(v.x, w.x, wq.x, p);
+      v.y = shoup_mul(v.y, w.y, wq.y, p);
+      v.z = shoup_mul(v.z, w.z, wq.z, p);
+      v.w = shoup_mul(v.w, w.w, wq.w, p);
       go[q] = v;
     }
   }
@@ -865,12 +894,16 @@ __global__ void __launch_bounds__(INV_ROW_THREADS) k_inv_rows_reg(const u32* X, 
   const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);
-  uint2* rtw = tw + (N2 >> 1);                                // w_N^{-j2 k1} per tile element
+  u32* rtw = smem + N2;                                       // w_N^{-j2 k1} per tile element, then companions
   u32* tile = smem + N2 + 2 * (nr << m2);
   load_block_tw(tw, tb.inv[prime], m2);
   const int i1_0 = (pair >> 1) << g.lrows_inv;
-  for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x)
-    rtw[e] = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime], st.hi[1][prime], p);
+  for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x) {
+    const uint2 r = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime],
+                              st.hi[1][prime], p);
+    rtw[e] = r.x;
+    rtw[(nr << m2) + e] = r.y;
+  }
   const size_t base = (size_t)i1_0 << m2;
   const int e_loc = threadIdx.x;                              // this thread's position in the tile
   u32* lds_me = tile + (e_loc >> m2) * ldr + pad8(e_loc & (N2 - 1));
@@ -935,12 +968,16 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
   const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);
-  uint2* rtw = tw + (N2 >> 1);                                // w_N^{-j2 k1} per tile element
+  u32* rtw = smem + N2;                                       // w_N^{-j2 k1} per tile element, then companions
   u32* tile = smem + N2 + 2 * (nr << m2);
   load_block_tw(tw, tb.inv[prime], m2);
   const int i1_0 = (pair >> 1) << g.lrows_inv;
-  for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x)
-    rtw[e] = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime], st.hi[1][prime], p);
+  for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x) {
+    const uint2 r = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime],
+                              st.hi[1][prime], p);
+    rtw[e] = r.x;
+    rtw[(nr << m2) + e] = r.y;
+  }
   const size_t base = (size_t)i1_0 << m2;
   const int quads = (nr << m2) >> 2;
   for (int b = b_lo; b < b_hi; ++b) {
