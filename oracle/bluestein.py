@@ -16,7 +16,11 @@ Pipeline for y = DFT(x), x in (F64 + i F64)^n, parameters (K, L):
    convolutions that use it (the split caching of Sec. 4.5).
 4. residues mod p0, p1, zero padding of the x' slices and wrap-around
    padding of the w* slices to N = 2^ceil(log2(2n-1)) (Sec. 3.2, ZeroPad and
-   ZeroPad+-), forward NTTs.
+   ZeroPad+-), forward NTTs.  For a power-of-two n the paper notes that the
+   convolution is already cyclic of length n (Sec. 3.2): w*(j) depends on
+   j^2 mod 2n, which for even n has period n in j and is even in j, so the
+   length-n cyclic convolution with w* itself gives the same sums; this
+   embedding (N = n, no padding) is selected with ``cyclic=True``.
 5. four real convolutions Re*Re, Im*Im, Im*Re, Re*Im (Sec. 4.5), each by
    Alg. 8: walk the anti-diagonals s+t = k from k_x+k_y-2 down to 0 and
    accumulate X^(s) (.) Y^(t) in the NTT domain, starting a new group when L
@@ -61,11 +65,20 @@ def _cplx(re, im):
     return out
 
 
-def conv_length(n: int) -> int:
+def is_pow2(n: int) -> bool:
+    return n >= 1 and (n & (n - 1)) == 0
+
+
+def conv_length(n: int, cyclic: bool = False) -> int:
     """Bluestein cyclic-convolution length: smallest power of two >= 2n-1
-    (Sec. 3.2, N >= 2n - 1)."""
+    (Sec. 3.2, N >= 2n - 1); with ``cyclic`` and a power-of-two n, n itself
+    (the paper's special case, Sec. 3.2)."""
     if n < 1:
         raise ValueError("n must be positive")
+    if cyclic:
+        if not is_pow2(n):
+            raise ValueError("the cyclic embedding N = n needs a power-of-two n")
+        return n
     return 1 << (2 * n - 2).bit_length() if n > 1 else 1
 
 
@@ -114,8 +127,11 @@ def pad_input(a, N: int) -> np.ndarray:
 
 def pad_kernel(b, N: int) -> np.ndarray:
     """ZeroPad+-(b, N): b(j) for j < n, 0 for n <= j < N-n+1, b(N-j) for
-    N-n+1 <= j < N (Sec. 3.2)."""
+    N-n+1 <= j < N (Sec. 3.2).  With N = n (cyclic embedding of a
+    power-of-two n) the kernel is b itself."""
     n = len(b)
+    if N == n:
+        return np.asarray(b, dtype=np.int64).copy()
     out = np.zeros(N, dtype=np.int64)
     out[:n] = b
     for j in range(N - n + 1, N):
@@ -170,9 +186,9 @@ class KernelPlan:
     """Input-independent part for one length n: chirp, splits of Re w* and
     Im w* and their forward NTTs (Sec. 4.5, precomputed offline)."""
 
-    def __init__(self, n: int, K: int | None = DEFAULT_K, L: int = DEFAULT_L):
-        self.n, self.K, self.L = n, K, L
-        self.N = conv_length(n)
+    def __init__(self, n: int, K: int | None = DEFAULT_K, L: int = DEFAULT_L, cyclic: bool = False):
+        self.n, self.K, self.L, self.cyclic = n, K, L, cyclic
+        self.N = conv_length(n, cyclic)
         self.alpha = oz.alpha_crt(n, L)
         self.c, self.s = chirp(n)
         self.slices = []   # per part: list of (a, E)

@@ -281,3 +281,92 @@ def test_signed_zeros_follow_ieee_products():
     assert np.array_equal(np.signbit(y.real), np.signbit(want_r))
     assert np.array_equal(np.signbit(y.imag), np.signbit(want_i))
     assert np.any(np.signbit(y.imag))
+
+
+# ---------------------------------------------------------------------------
+# Power-of-two special case: cyclic embedding N = n (Sec. 3.2)
+
+def test_chirp_index_has_period_n_for_even_n():
+    """q(j) = j^2 mod 2n: (j + n)^2 = j^2 + 2jn + n^2 and n^2 = 2n (n/2), so for
+    even n the index (and with it w*) has period n and is even in j; for odd n
+    it does not, which is why the embedding is limited to even (here
+    power-of-two) n."""
+    for n in (2, 4, 6, 8, 10, 64, 1000):
+        q = [(j * j) % (2 * n) for j in range(3 * n)]
+        assert all(q[j + n] == q[j] for j in range(2 * n))
+        assert all(q[(n - j) % n] == q[j] for j in range(n))
+    for n in (3, 5, 7, 9):
+        assert any(((j + n) ** 2) % (2 * n) != (j * j) % (2 * n) for j in range(n))
+
+
+def test_cyclic_conv_length():
+    for n in (1, 2, 4, 1024, 1 << 18):
+        assert bl.conv_length(n, cyclic=True) == n
+    for n in (3, 6, 10007):
+        with pytest.raises(ValueError):
+            bl.conv_length(n, cyclic=True)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 64])
+def test_cyclic_embedding_exact_uncapped(n):
+    """N = n, K uncapped: y' must still be RN of the exact linear convolution
+    of x' with the chirp (closed form, no NTT)."""
+    x = wl.uniform(n, seed=200 + n)[0]
+    plan = bl.KernelPlan(n, None, 1, cyclic=True)
+    tr = bl.forward_trace(x, None, 1, plan)
+    assert tr["N"] == n
+    yr, yi = bl.exact_convolution_rounded(tr["xpr"], tr["xpi"], plan.c, plan.s)
+    assert np.array_equal(yr, tr["ypr"]) and np.array_equal(yi, tr["ypi"])
+
+
+@pytest.mark.parametrize("n,K,L", [(8, 3, 3), (32, 2, 1), (64, 3, 3)])
+def test_cyclic_embedding_exact_capped(n, K, L):
+    """N = n, K capped: direct rational evaluation of the retained slice
+    products over |k - j| (the linear Bluestein convolution)."""
+    x = wl.paper_phi(n, 1.0, seed=n + 1)[0]
+    plan = bl.KernelPlan(n, K, L, cyclic=True)
+    tr = bl.forward_trace(x, K, L, plan)
+    alpha = tr["alpha"]
+    X = [_truncated_exact(tr["slices"][v], alpha) for v in range(2)]
+    W = [_truncated_exact(plan.slices[v], alpha) for v in range(2)]
+    for tgt, out in ((0, tr["ypr"]), (1, tr["ypi"])):
+        for k in range(n):
+            acc = Fraction(0)
+            for (pa, pb, t, sg) in bl.CONVS:
+                if t != tgt or not X[pa] or not W[pb]:
+                    continue
+                acc += sg * sum(X[pa][j] * W[pb][abs(k - j)] for j in range(n))
+            assert out[k] == bl._round_fraction(acc), (tgt, k)
+
+
+@pytest.mark.parametrize("n", [2, 16, 256, 1024])
+def test_cyclic_embedding_equals_padded(n):
+    """Same slices, exponents, groups and CRT integers as the padded
+    embedding, so the outputs are bit-identical."""
+    x = wl.paper_phi(n, 4.0, seed=7)[0]
+    tp = bl.forward_trace(x, 3, 3, bl.KernelPlan(n, 3, 3))
+    tc = bl.forward_trace(x, 3, 3, bl.KernelPlan(n, 3, 3, cyclic=True))
+    assert tc["N"] == n and tp["N"] == bl.conv_length(n)
+    assert tc["groups"] == tp["groups"]
+    for gc, gp in zip(tc["group_z"], tp["group_z"]):
+        for (zc, ec), (zp, ep) in zip(gc, gp):
+            assert ec == ep and np.array_equal(zc, zp)
+    assert np.array_equal(tc["y"].view(np.uint64), tp["y"].view(np.uint64))
+
+
+def test_cyclic_embedding_without_wrap_is_caught_by_pin(monkeypatch):
+    """Planted mistake: a length-n kernel whose negative lags are dropped
+    (b(j) only for the first half, zeros after) breaks the closed-form pin."""
+    n = 16
+
+    def half(b, N):
+        out = np.zeros(N, dtype=np.int64)
+        out[: n // 2] = np.asarray(b)[: n // 2]
+        return out
+
+    x = wl.uniform(n, seed=12)[0]
+    monkeypatch.setattr(bl, "pad_kernel", half)
+    plan = bl.KernelPlan(n, None, 1, cyclic=True)
+    tr = bl.forward_trace(x, None, 1, plan)
+    yr, yi = bl.exact_convolution_rounded(tr["xpr"], tr["xpi"], plan.c, plan.s)
+    assert not (np.array_equal(yr, tr["ypr"]) and np.array_equal(yi, tr["ypi"]))
