@@ -72,25 +72,40 @@ enum {
   FFT_OZAKI_MODE_BATCHED = 1       /* all transforms per launch, device-side schedule, HIP graph replay */
 };
 
+/* Convolution embedding (Sec. 3.2).  PADDED: cyclic convolution of length
+ * N = 2^ceil(log2(2n-1)) with the input zero-padded and the chirp kernel
+ * wrapped (ZeroPad, ZeroPad+-).  AUTO: for a power-of-two n the convolution
+ * is already cyclic of length n (the chirp index j^2 mod 2n has period n
+ * and is even in j for even n), so N = n and nothing is padded; other n
+ * are padded.  Both give bit-identical outputs: the slices, groups and CRT
+ * integers are the same, only the NTT length differs. */
+enum {
+  FFT_OZAKI_EMBED_PADDED = 0,
+  FFT_OZAKI_EMBED_AUTO = 1
+};
+
 /* Plan options.  K: cap on slices per vector (Sec. 4.4), 1..8, default 3.
  * L: NTT-domain accumulation bound (Sec. 4.4, Alg. 8), >= 1, default 3.
  * mode: FFT_OZAKI_MODE_*, default batched.  autotune: 1 = time the NTT tile
  * shapes at plan time and keep the fastest (results are identical for every
  * shape); tune_cache: optional file path where tuned shapes are stored and
- * looked up (NULL = none). */
+ * looked up (NULL = none).  embedding: FFT_OZAKI_EMBED_*, default AUTO. */
 typedef struct {
   int K;
   int L;
   int mode;
   int autotune;
   const char* tune_cache;
+  int embedding;
 } fft_ozaki_options;
 
-/* Fills *opt with the defaults (K = 3, L = 3, batched, no autotune). */
+/* Fills *opt with the defaults (K = 3, L = 3, batched, no autotune, AUTO
+ * embedding). */
 int fft_ozaki_default_options(fft_ozaki_options* opt);
 
 /* Plan `batch` transforms of length n (uniform batch) with default options.
- * n >= 1 with convolution length N = 2^ceil(log2(2n-1)) <= 2^24; batch >= 1. */
+ * n >= 1 with convolution length N <= 2^24 (N = n for a power-of-two n,
+ * else 2^ceil(log2(2n-1))); batch >= 1. */
 int fft_ozaki_plan(fft_ozaki_plan_t* plan, int64_t n, int64_t batch);
 
 /* Plan `count` transforms of the given (possibly different) lengths.
@@ -114,6 +129,7 @@ typedef struct {
   int64_t total_length;            /* sum of the lengths */
   int K, L, mode, num_length_classes;
   int64_t workspace_bytes;         /* device memory held by the plan */
+  int embedding;                   /* FFT_OZAKI_EMBED_* */
 } fft_ozaki_info;
 int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info);
 

@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(_PKG, "libfft_ozaki.so")
 
 FORWARD, INVERSE, ADJOINT = 0, 1, 2
 MODE_PLAIN, MODE_BATCHED = 0, 1
+EMBED_PADDED, EMBED_AUTO = 0, 1
 _MODES = {"plain": MODE_PLAIN, "batched": MODE_BATCHED}
 
 
@@ -37,13 +38,13 @@ class FftOzakiError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("L", ctypes.c_int), ("mode", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
+                ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p), ("embedding", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64), ("total_length", ctypes.c_int64), ("K", ctypes.c_int),
                 ("L", ctypes.c_int), ("mode", ctypes.c_int), ("num_length_classes", ctypes.c_int),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("embedding", ctypes.c_int)]
 
 
 class _TInfo(ctypes.Structure):
@@ -105,17 +106,23 @@ def _stream_handle(torch, device) -> int:
 
 
 class Plan:
-    """A plan for `lengths` transforms (or `batch` transforms of length `n`)."""
+    """A plan for `lengths` transforms (or `batch` transforms of length `n`).
+
+    cyclic: for power-of-two lengths use the cyclic embedding N = n instead of
+    padding to N = 2^ceil(log2(2n-1)) (Sec. 3.2); the outputs are the same
+    bit for bit, the NTTs half as long."""
 
     def __init__(self, n: int | None = None, batch: int = 1, *, lengths=None, K: int = 3, L: int = 3,
-                 mode: str = "batched", autotune: bool = False, tune_cache: str | None = None):
+                 mode: str = "batched", autotune: bool = False, tune_cache: str | None = None,
+                 cyclic: bool = True):
         if lengths is None:
             if n is None:
                 raise ValueError("give n (and batch) or lengths")
             lengths = [int(n)] * int(batch)
         self.lengths = [int(v) for v in lengths]
         self.K, self.L, self.mode = K, L, mode
-        opts = _Options(K, L, _MODES[mode], int(bool(autotune)), tune_cache.encode() if tune_cache else None)
+        opts = _Options(K, L, _MODES[mode], int(bool(autotune)), tune_cache.encode() if tune_cache else None,
+                        EMBED_AUTO if cyclic else EMBED_PADDED)
         arr = (ctypes.c_int64 * len(self.lengths))(*self.lengths)
         h = ctypes.c_void_p()
         _check(lib().fft_ozaki_plan_ex(ctypes.byref(h), arr, len(self.lengths), ctypes.byref(opts)))

@@ -55,9 +55,15 @@ static int alpha_for(i64 n, int L) {
   return a;
 }
 
-// Bluestein convolution length: N = 2^ceil(log2(2n - 1)) (Sec. 3.2).
-static int conv_log2(i64 n) {
+// Bluestein convolution length: N = 2^ceil(log2(2n - 1)) (Sec. 3.2), or
+// N = n for a power-of-two n with the cyclic embedding (Sec. 3.2).
+static int conv_log2(i64 n, bool cyclic) {
   if (n <= 1) return 0;
+  if (cyclic && (n & (n - 1)) == 0) {
+    int l = 0;
+    while (((i64)1 << l) < n) ++l;
+    return l;
+  }
   int l = 0;
   while (((i64)1 << l) < 2 * n - 1) ++l;
   return l;
@@ -94,6 +100,7 @@ struct fft_ozaki_plan_s {
   int device = 0;
   int K = 3, L = 3, mode = FFT_OZAKI_MODE_BATCHED;
   int autotune = 0;
+  bool cyclic = true;               // FFT_OZAKI_EMBED_AUTO
   std::string tune_cache;
   std::vector<fo::i64> lengths;
   fo::i64 total = 0;
@@ -328,12 +335,12 @@ static int build_plan(fft_ozaki_plan_s* p) {
     if (!kidx.count(n)) {
       KernelHost kh;
       kh.n = n;
-      kh.logN = conv_log2(n);
+      kh.logN = conv_log2(n, p->cyclic);
       kh.alpha = alpha_for(n, p->L);
       kidx[n] = (int)p->kernels.size();
       p->kernels.push_back(kh);
     }
-    const int lg = conv_log2(n);
+    const int lg = conv_log2(n, p->cyclic);
     if (!cidx.count(lg)) {
       LengthClass lc;
       lc.logN = lg;
@@ -366,7 +373,7 @@ static int build_plan(fft_ozaki_plan_s* p) {
     const i64 n = p->lengths[t];
     TDesc d{};
     d.n = (int)n;
-    d.logN = conv_log2(n);
+    d.logN = conv_log2(n, p->cyclic);
     d.N = 1 << d.logN;
     d.alpha = alpha_for(n, p->L);
     d.kd = kidx[n];
@@ -598,6 +605,7 @@ int fft_ozaki_default_options(fft_ozaki_options* opt) {
   opt->mode = FFT_OZAKI_MODE_BATCHED;
   opt->autotune = 0;
   opt->tune_cache = nullptr;
+  opt->embedding = FFT_OZAKI_EMBED_AUTO;
   return FFT_OZAKI_OK;
 }
 
@@ -614,11 +622,14 @@ int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t co
   if (o.L < 1 || o.L > (1 << 20)) return fail(FFT_OZAKI_ERR_INVALID, "L must be in [1, 2^20]");
   if (o.mode != FFT_OZAKI_MODE_PLAIN && o.mode != FFT_OZAKI_MODE_BATCHED)
     return fail(FFT_OZAKI_ERR_INVALID, "mode must be 0 (plain) or 1 (batched)");
+  if (o.embedding != FFT_OZAKI_EMBED_PADDED && o.embedding != FFT_OZAKI_EMBED_AUTO)
+    return fail(FFT_OZAKI_ERR_INVALID, "embedding must be 0 (padded) or 1 (auto)");
+  const bool cyclic = o.embedding == FFT_OZAKI_EMBED_AUTO;
   i64 total = 0;
   for (int64_t i = 0; i < count; ++i) {
     const i64 n = lengths[i];
     if (n < 1) return fail(FFT_OZAKI_ERR_INVALID, "lengths must be >= 1");
-    if (conv_log2(n) > MAX_LOG2_N) return fail(FFT_OZAKI_ERR_INVALID, "convolution length 2^ceil(log2(2n-1)) exceeds 2^24");
+    if (conv_log2(n, cyclic) > MAX_LOG2_N) return fail(FFT_OZAKI_ERR_INVALID, "convolution length exceeds 2^24");
     const int a = alpha_for(n, o.L);
     if (a < 1 || a > 30) return fail(FFT_OZAKI_ERR_INVALID, "split width alpha < 1 for this n and L");
     total += n;
@@ -630,6 +641,7 @@ int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t co
   p->L = o.L;
   p->mode = o.mode;
   p->autotune = o.autotune;
+  p->cyclic = cyclic;
   p->tune_cache = o.tune_cache ? o.tune_cache : "";
   p->lengths.assign(lengths, lengths + count);
   int rc = build_plan(p);
@@ -687,6 +699,7 @@ int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info) {
   info->mode = plan->mode;
   info->num_length_classes = (int)plan->classes.size();
   info->workspace_bytes = plan->bytes;
+  info->embedding = plan->cyclic ? FFT_OZAKI_EMBED_AUTO : FFT_OZAKI_EMBED_PADDED;
   return FFT_OZAKI_OK;
 }
 

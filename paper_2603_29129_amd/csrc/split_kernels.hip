@@ -294,7 +294,7 @@ hipError_t launch_split_plan(const TDesc* td, TState* ts, const int* tlist, int 
 // blockIdx.y = part.  Slices k >= start are written as residues mod p0, p1
 // into X[(part*K + k)*2 + prime][.]; input slices go to positions j < n (the
 // NTT treats the rest as zero), kernel slices are placed by ZeroPad+-
-// (positions j and N - j).
+// (positions j and N - j), or at j alone when N = n (cyclic embedding).
 __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts, const int* tlist, int K,
                                 bool kernel_mode) {
   const int t = tlist[blockIdx.z];
@@ -329,7 +329,7 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
         u32* v1 = v0 + N;
         v0[j] = r0;
         v1[j] = r1;
-        if (kernel_mode && j > 0) {
+        if (kernel_mode && j > 0 && N != (size_t)d.n) {   // ZeroPad+- (no wrap when N = n: cyclic)
           v0[N - j] = r0;
           v1[N - j] = r1;
         }

@@ -34,10 +34,15 @@ def _gpu(torch, x):
 _KPLANS = {}
 
 
-def kplan(n, K, L):
-    key = (n, K, L)
+def kplan(n, K, L, cyclic=None):
+    """Oracle plan with the library's embedding: by default (cyclic=None) the
+    cyclic N = n for power-of-two n, as the library's default plans."""
+    if cyclic is None:
+        cyclic = bl.is_pow2(n)
+    cyclic = bool(cyclic) and bl.is_pow2(n)
+    key = (n, K, L, cyclic)
     if key not in _KPLANS:
-        _KPLANS[key] = bl.KernelPlan(n, K, L)
+        _KPLANS[key] = bl.KernelPlan(n, K, L, cyclic=cyclic)
     return _KPLANS[key]
 
 
@@ -86,15 +91,16 @@ def check_stages(plan, idx, tr, kp, K):
                 assert np.array_equal(Z[c * K * K + g, ip].astype(np.uint64), want), (c, g, ip)
 
 
+@pytest.mark.parametrize("cyclic", [True, False])
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 16, 17, 31, 64, 100, 127, 1000, 1024, 2047, 2048, 2049, 4097])
-def test_forward_small(torch_mod, n):
+def test_forward_small(torch_mod, n, cyclic):
     import paper_2603_29129_amd as oz
     torch = torch_mod
     K, L = 3, 3
     x = wl.paper_phi(n, 1.0, seed=n, batch=2)
-    plan = oz.Plan(n, 2, K=K, L=L)
+    plan = oz.Plan(n, 2, K=K, L=L, cyclic=cyclic)
     y = plan.forward(_gpu(torch, x)).cpu().numpy()
-    kp = kplan(n, K, L)
+    kp = kplan(n, K, L, cyclic)
     for b in range(2):
         tr = bl.forward_trace(x[b], K, L, kp)
         check_stages(plan, b, tr, kp, K)
@@ -102,18 +108,48 @@ def test_forward_small(torch_mod, n):
 
 
 def test_plain_1k_config(torch_mod):
-    """One transform, n = 2^10 (N = 2048), uniform[-1, 1], seed 0."""
+    """One transform, n = 2^10 with the padded convolution length N = 2048,
+    uniform[-1, 1], seed 0; the cyclic embedding (N = 1024) gives the same
+    bits."""
     import paper_2603_29129_amd as oz
     torch = torch_mod
     x = wl.plain_1k(0)
-    for mode in ("plain", "batched"):
-        plan = oz.Plan(1024, 1, mode=mode)
-        y = plan.forward(_gpu(torch, x)).cpu().numpy()
-        kp = kplan(1024, 3, 3)
-        tr = bl.forward_trace(x[0], 3, 3, kp)
-        check_stages(plan, 0, tr, kp, 3)
-        assert max_ulp(y[0], tr["y"]) == 0
-        assert ref.rel_l2_error(y[0], ref.dft_longdouble(x[0])) < 1e-15
+    ys = []
+    for cyclic, N in ((False, 2048), (True, 1024)):
+        for mode in ("plain", "batched"):
+            plan = oz.Plan(1024, 1, mode=mode, cyclic=cyclic)
+            y = plan.forward(_gpu(torch, x)).cpu().numpy()
+            kp = kplan(1024, 3, 3, cyclic)
+            tr = bl.forward_trace(x[0], 3, 3, kp)
+            assert plan.transform_info(0)["N"] == N
+            check_stages(plan, 0, tr, kp, 3)
+            assert max_ulp(y[0], tr["y"]) == 0
+            assert ref.rel_l2_error(y[0], ref.dft_longdouble(x[0])) < 1e-15
+            ys.append(y)
+    assert all(np.array_equal(v.view(np.uint64), ys[0].view(np.uint64)) for v in ys)
+
+
+@pytest.mark.parametrize("n", [8192, 1 << 16])
+def test_cyclic_embedding_two_pass(torch_mod, n):
+    """Power-of-two n in the two-pass NTT range: the cyclic embedding's
+    intermediates match the cyclic oracle and its outputs are bit-identical
+    to the padded embedding's, batched and plain."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = wl.paper_phi(n, 1.0, seed=5, batch=3)
+    xd = _gpu(torch, x)
+    outs = []
+    for cyclic in (True, False):
+        for mode in ("batched", "plain"):
+            plan = oz.Plan(n, 3, mode=mode, cyclic=cyclic)
+            outs.append(plan.forward(xd).cpu().numpy())
+            assert plan.transform_info(0)["N"] == (n if cyclic else 2 * n)
+            if cyclic and mode == "batched" and n == 8192:
+                kp = kplan(n, 3, 3, True)
+                tr = bl.forward_trace(x[1], 3, 3, kp)
+                check_stages(plan, 1, tr, kp, 3)
+                assert max_ulp(outs[-1][1], tr["y"]) == 0
+    assert all(np.array_equal(v.view(np.uint64), outs[0].view(np.uint64)) for v in outs)
 
 
 @pytest.mark.parametrize("K,L", [(1, 1), (2, 1), (3, 1), (2, 2), (4, 3), (6, 1), (8, 8)])
@@ -205,9 +241,9 @@ def test_special_inputs_two_pass_runs(torch_mod):
     x[4] = 0
     x[4, 0] = 1.5             # x' = x (.) w is real: one slice of Re x', none of Im x'
     x[6, 9] = 1e-300
-    plan = oz.Plan(n, 64)
+    plan = oz.Plan(n, 64, cyclic=False)         # N = 2^15: two transforms per inverse-row workgroup
     y = plan.forward(_gpu(torch, x)).cpu().numpy()
-    kp = kplan(n, 3, 3)
+    kp = kplan(n, 3, 3, False)
     for b in (0, 1, 2, 3, 4, 5, 6, 7, 63):
         tr = bl.forward_trace(x[b], 3, 3, kp)
         assert plan.transform_info(b)["status"] == tr["status"], b
