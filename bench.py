@@ -31,9 +31,75 @@ if ROOT not in sys.path:
 
 METRIC = "FP64-accurate FFT GFLOP/s (5n·log2n) at n=2^18, batched vs plain; rel. error"
 HBM_PEAK_GBS = 8000.0
+# 32-bit integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# operation per lane per cycle (no fused pair for integer work)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# int32 operations of the algorithm (Shoup products, fully reduced results):
+# forward DIF butterfly: add_mod 3 + (x - y + p) 2 + product 6; inverse DIT
+# butterfly: product 6 + add_mod 3 + sub_mod 3; twiddle product 6; NTT-domain
+# multiply-accumulate: product 6 + add_mod 3.  Butterflies whose root is 1
+# are counted at full cost (the textbook (N/2) log2 N products).
+OPS_FWD_BFLY, OPS_INV_BFLY, OPS_TWIDDLE, OPS_MAC = 11, 12, 6, 9
+PASS_STAGES = (4, 5, 6, 7, 8)
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2603_29129_amd", "csrc")
 
-# stage id -> kernel launched by that stage (uniform batch: one launch per stage)
-STAGE_KERNELS = {4: "k_fwd_cols", 5: "k_fwd_rows", 6: "k_inv_rows", 7: "k_inv_cols", 8: "k_recombine"}
+
+def stage_kernels(info, K):
+    """Kernel launched by each pass stage (one launch per stage for a uniform
+    batch), by the name rocprofv3 reports."""
+    logN, m1 = info["N"].bit_length() - 1, info["ntt_log2N1"]
+    m2 = logN - m1
+    li = min(max(9 - m2, 0), m1)
+    rows = "k_inv_rows_reg" if (K <= 3 and m2 + li == 9) else "k_inv_rows"
+    return {4: f"k_fwd_cols<{m1}>", 5: f"k_fwd_rows<{m2}>", 6: f"{rows}<{m2}>", 7: f"k_inv_cols<{m1}>",
+            8: "k_recombine"}
+
+
+def algorithmic_ops(infos):
+    """Algorithmic int32 operations per launch of the NTT pass kernels."""
+    out = {4: 0, 5: 0, 6: 0, 7: 0}
+    for d in infos:
+        N = d["N"]
+        logN, m1 = N.bit_length() - 1, d["ntt_log2N1"]
+        m2 = logN - m1
+        N1, N2 = 1 << m1, 1 << m2
+        vf = 2 * (d["kx"][0] + d["kx"][1])          # forward vectors (part, slice, prime)
+        vi = 2 * sum(d["ngroups"])                   # inverse vectors (group, prime)
+        pairs = sum(d["kx"][pa] * d["kw"][pb] for pa, pb in ((0, 0), (1, 1), (1, 0), (0, 1)))
+        out[4] += vf * N2 * (N1 // 2) * m1 * OPS_FWD_BFLY
+        out[5] += vf * (N * OPS_TWIDDLE + N1 * (N2 // 2) * m2 * OPS_FWD_BFLY)
+        out[6] += vi * (N1 * (N2 // 2) * m2 * OPS_INV_BFLY + N * OPS_TWIDDLE) + 2 * N * pairs * OPS_MAC
+        out[7] += vi * N2 * (N1 // 2) * m1 * OPS_INV_BFLY
+    return out
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE and
+    WRITE_SIZE counter summary, scaled by the copy-kernel calibration; None
+    when no summary exists or the kernel sources changed since it was taken."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*hbm_traffic*.md"))):
+        with open(path) as fh:
+            text = fh.read()
+        if "```json" not in text:
+            continue
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        if blob.get("source_sha256") != source_digest() or kernel not in blob.get("kernels", {}):
+            continue
+        k, cal = blob["kernels"][kernel], blob["calibration"]
+        return round(k["fetch_kib"] * 1024 * cal["fetch_factor"] + k["write_kib"] * 1024 * cal["write_factor"])
+    return None
 
 
 def algorithmic_bytes(infos, K):
@@ -159,15 +225,25 @@ def main():
     print("# stages (ms): " + ", ".join(f"{k}:{v:.3f}" for k, v in stage_ms.items()), file=sys.stderr, flush=True)
 
     alg = algorithmic_bytes(infos, 3)
-    dom = max(STAGE_KERNELS, key=lambda s: stage_ms[s])
-    achieved = alg[dom] / (stage_ms[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": STAGE_KERNELS[dom], "kernel_ms": round(stage_ms[dom], 4),
-                "algorithmic_bytes_per_launch": alg[dom]}
-    per_kernel = {STAGE_KERNELS[s]: {"ms": round(stage_ms[s], 4),
-                                     "alg_GBps": round(alg[s] / (stage_ms[s] * 1e-3) / 1e9, 1)}
-                  for s in STAGE_KERNELS}
+    ops = algorithmic_ops(infos)
+    names = stage_kernels(infos[0], 3)
+    # the dominant kernel (longest pass) is bound by its integer VALU work
+    dom = max((4, 5, 6, 7), key=lambda s: stage_ms[s])
+    achieved = ops[dom] / (stage_ms[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s",
+                "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": measured_traffic(names[dom]),
+                "kernel": names[dom], "kernel_ms": round(stage_ms[dom], 4),
+                "algorithmic_int32_ops_per_launch": ops[dom], "algorithmic_bytes_per_launch": alg[dom],
+                "hbm_achieved_GBps": round(alg[dom] / (stage_ms[dom] * 1e-3) / 1e9, 1),
+                "hbm_frac": round(alg[dom] / (stage_ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    per_kernel = {}
+    for s in PASS_STAGES:
+        e = {"ms": round(stage_ms[s], 4), "alg_GBps": round(alg[s] / (stage_ms[s] * 1e-3) / 1e9, 1),
+             "traffic": measured_traffic(names[s])}
+        if s in ops:
+            e["alu_TOPs"] = round(ops[s] / (stage_ms[s] * 1e-3) / 1e12, 3)
+            e["alu_frac"] = round(ops[s] / (stage_ms[s] * 1e-3) / 1e12 / ALU_PEAK_TOPS, 4)
+        per_kernel[names[s]] = e
 
     plain = None
     if not args.no_plain:
