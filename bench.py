@@ -53,7 +53,7 @@ def stage_kernels(info, K):
     li = min(max(9 - m2, 0), m1)
     rows = "k_inv_rows_reg" if (K <= 3 and m2 + li == 9) else "k_inv_rows"
     return {4: f"k_fwd_cols<{m1}>", 5: f"k_fwd_rows<{m2}>", 6: f"{rows}<{m2}>", 7: f"k_inv_cols<{m1}>",
-            8: "k_recombine"}
+            8: "k_recombine<false>"}
 
 
 def algorithmic_ops(infos):

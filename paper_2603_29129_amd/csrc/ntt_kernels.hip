@@ -96,14 +96,19 @@ __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const 
 
 // The groups of one round.  HOIST: every group a thread visits has the same
 // offset (row layout with blockDim a multiple of the groups per vector), so
-// its roots were loaded into twr once for the round.
+// its roots were loaded into twr once for the round.  In the column layout
+// a thread transforms two groups per iteration (g and g + blockDim): their
+// independent instruction streams interleave and hide the latency of the
+// dependent product chains (at the tail the second group repeats the first
+// and is not stored).  The row kernels keep one group per iteration: there
+// the extra registers cost a wave per SIMD, which is worth more.
 template <int M, int S0, int RL, bool INV, bool COLS, bool HOIST>
 __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const uint2* __restrict__ tw,
                                              const uint2 (&twr)[1 << RL], u32 p) {
   constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
   const int total = COLS ? (1 << (nv + LGPV)) : (nv << LGPV);
   const int sst = COLS ? (ST << nv) : 0;     // element stride of a group, column layout
-  for (int g = threadIdx.x; g < total; g += blockDim.x) {
+  auto locate = [&](int g, int& off) -> u32* {
     int v, q;
     if (COLS) {
       v = g & ((1 << nv) - 1);
@@ -112,10 +117,11 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
       v = g >> LGPV;
       q = g & ((1 << LGPV) - 1);
     }
-    const int off = q & (ST - 1);
+    off = q & (ST - 1);
     const int base = ((q >> LST) << LBK) + off;
-    u32 a[R];
-    u32* p0 = COLS ? lds + (base << nv) + v : lds + v * ldr + pad8(base);
+    return COLS ? lds + (base << nv) + v : lds + v * ldr + pad8(base);
+  };
+  auto load = [&](u32 (&a)[R], const u32* p0) {
     if (!COLS && ST == 1 && R >= 4) {
 #pragma unroll
       for (int j = 0; j < R; j += 4) {
@@ -125,19 +131,47 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
         a[j + 2] = t.z;
         a[j + 3] = t.w;
       }
-      radix_group_t<RL, S0, ST, INV, HOIST>(a, off, tw, twr, p);
+    } else {
+#pragma unroll
+      for (int j = 0; j < R; ++j) a[j] = COLS ? p0[j * sst] : p0[pad8(j * ST)];
+    }
+  };
+  auto store = [&](const u32 (&a)[R], u32* p0) {
+    if (!COLS && ST == 1 && R >= 4) {
 #pragma unroll
       for (int j = 0; j < R; j += 4) *reinterpret_cast<uint4*>(p0 + j) = make_uint4(a[j], a[j + 1], a[j + 2], a[j + 3]);
-      continue;
-    }
+    } else {
 #pragma unroll
-    for (int j = 0; j < R; ++j) a[j] = COLS ? p0[j * sst] : p0[pad8(j * ST)];
-    radix_group_t<RL, S0, ST, INV, HOIST>(a, off, tw, twr, p);
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      if (COLS) p0[j * sst] = a[j];
-      else p0[pad8(j * ST)] = a[j];
+      for (int j = 0; j < R; ++j) {
+        if (COLS) p0[j * sst] = a[j];
+        else p0[pad8(j * ST)] = a[j];
+      }
     }
+  };
+  if (!COLS) {
+    for (int g = threadIdx.x; g < total; g += blockDim.x) {
+      int off;
+      u32* p0 = locate(g, off);
+      u32 a[R];
+      load(a, p0);
+      radix_group_t<RL, S0, ST, INV, HOIST>(a, off, tw, twr, p);
+      store(a, p0);
+    }
+    return;
+  }
+  for (int g = threadIdx.x; g < total; g += 2 * blockDim.x) {
+    const int g2 = g + blockDim.x;
+    const bool two = g2 < total;
+    int off1, off2;
+    u32* p1 = locate(g, off1);
+    u32* p2 = locate(two ? g2 : g, off2);
+    u32 a[R], b[R];
+    load(a, p1);
+    load(b, p2);
+    radix_group_t<RL, S0, ST, INV, HOIST>(a, off1, tw, twr, p);
+    radix_group_t<RL, S0, ST, INV, HOIST>(b, off2, tw, twr, p);
+    store(a, p1);
+    if (two) store(b, p2);
   }
 }
 

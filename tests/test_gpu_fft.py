@@ -250,6 +250,29 @@ def test_special_inputs_two_pass_runs(torch_mod):
         assert max_ulp(y[b], tr["y"]) == 0, b
 
 
+@pytest.mark.parametrize("n", [1000, 8192])
+def test_wide_exponent_span(torch_mod, n):
+    """Half the entries 2^-300 times the others (K = 8): the split jumps from
+    the O(1) entries to the tiny ones, the group exponents of one output
+    component span about 400 bits and the recombination takes its wide
+    accumulator; transforms with ordinary spans in the same launch take the
+    fast one.  All bit-identical to the oracle."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = wl.uniform(n, batch=3, seed=21)
+    x[1, ::2] *= 2.0 ** -300
+    plan = oz.Plan(n, 3, K=8, L=3)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan(n, 8, 3)
+    for b in range(3):
+        tr = bl.forward_trace(x[b], 8, 3, kp)
+        if b == 1:
+            es = [e for conv in tr["group_z"] for (_z, e) in conv]
+            assert max(es) - min(es) > 300
+            check_stages(plan, b, tr, kp, 8)
+        assert max_ulp(y[b], tr["y"]) == 0, b
+
+
 def test_batch_16k_roundtrip(torch_mod):
     """64 transforms at n = 2^14 (N = 2^15): two sampled transforms compared
     with the oracle, all 64 round-tripped through the inverse."""
