@@ -179,6 +179,20 @@ __device__ __forceinline__ u64 wave_max_u64(u64 v) {
   }
   return v;
 }
+// Maximum over the workgroup (blockDim a multiple of 64, at most 1024),
+// valid in thread 0; every thread must call it.  One atomic per workgroup
+// instead of one per wave keeps the per-transform maxima from serialising.
+__device__ __forceinline__ u64 block_max_u64(u64 v) {
+  __shared__ u64 part[16];
+  v = wave_max_u64(v);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  u64 m = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = part[w] > m ? part[w] : m;
+  __syncthreads();
+  return m;
+}
 
 __global__ void k_premul(const double2* in, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
                          const int* tlist, int dir, bool kernel_mode) {
@@ -186,6 +200,7 @@ __global__ void k_premul(const double2* in, double2* xp, const TDesc* td, const 
   const TDesc& d = td[t];
   const double2* ch = kd[d.kd].chirp;
   u64 m0 = 0, m1 = 0;
+#pragma unroll 4
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
     double re, im;
     const double2 w = ch[j];
@@ -203,16 +218,17 @@ __global__ void k_premul(const double2* in, double2* xp, const TDesc* td, const 
     m0 = a > m0 ? a : m0;
     m1 = b > m1 ? b : m1;
   }
-  m0 = wave_max_u64(m0);
-  m1 = wave_max_u64(m1);
-  if ((threadIdx.x & 63) == 0) {
+  m0 = block_max_u64(m0);
+  m1 = block_max_u64(m1);
+  if (threadIdx.x == 0) {
     if (m0) atomicMax((unsigned long long*)&ts[t].mu[0][0], (unsigned long long)m0);
     if (m1) atomicMax((unsigned long long*)&ts[t].mu[1][0], (unsigned long long)m1);
   }
 }
 
+// Workgroups of 256 threads per vector: 8 elements per thread.
 static int chunks_for(int nmax) {
-  int b = (nmax + 1023) / 1024;
+  int b = (nmax + 2047) / 2048;
   if (b < 1) b = 1;
   if (b > 1024) b = 1024;
   return b;
@@ -313,6 +329,7 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
   for (int k = 0; k < KMAX; ++k) mloc[k] = 0;
   u32* Xb = X + d.X_off;
   const size_t N = (size_t)1 << d.logN;
+#pragma unroll 4
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
     const double2 v = xp[d.xp_off + j];
     double r = part ? v.y : v.x;
@@ -339,8 +356,8 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
     }
   }
   for (int k = start; k < kend && k + 1 < K; ++k) {
-    const u64 m = wave_max_u64(mloc[k]);
-    if ((threadIdx.x & 63) == 0 && m) atomicMax((unsigned long long*)&s.mu[part][k + 1], (unsigned long long)m);
+    const u64 m = block_max_u64(mloc[k]);
+    if (threadIdx.x == 0 && m) atomicMax((unsigned long long*)&s.mu[part][k + 1], (unsigned long long)m);
   }
 }
 
@@ -402,20 +419,30 @@ __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
   const TDesc& d = td[t];
   TState& s = ts[t];
   const KernelDesc& kk = kd[d.kd];
+  // the slice exponents, read by the walk in data-dependent order, staged in
+  // LDS (one row per thread) so the walk does not wait on global loads
+  __shared__ int sE[64][2][KMAX], sW[64][2][KMAX];
+  int (&E)[2][KMAX] = sE[threadIdx.x];
+  int (&Ew)[2][KMAX] = sW[threadIdx.x];
+  for (int part = 0; part < 2; ++part)
+    for (int k = 0; k < KMAX; ++k) {
+      E[part][k] = s.E[part][k];
+      Ew[part][k] = kk.Ew[part][k];
+    }
   int emin[2] = {0x7FFFFFFF, 0x7FFFFFFF}, emax[2] = {-0x7FFFFFFF, -0x7FFFFFFF};
   for (int c = 0; c < 4; ++c) {
     const int pa = c_pa[c], pb = c_pb[c];
     const int kA = s.status ? 0 : s.kx[pa], kB = kk.kw[pb];
     int np = 0, ng = 0;
     if (kA > 0 && kB > 0) {
-      int key = s.E[pa][kA - 1] + kk.Ew[pb][kB - 1];
+      int key = E[pa][kA - 1] + Ew[pb][kB - 1];
       int cnt = 0, gstart = 0;
       for (int dg = kA + kB - 2; dg >= 0; --dg) {
         const int s0 = dg - kB + 1 > 0 ? dg - kB + 1 : 0;
         const int s1 = kA - 1 < dg ? kA - 1 : dg;
         for (int ss = s0; ss <= s1; ++ss) {
           const int tt = dg - ss;
-          const int k2 = s.E[pa][ss] + kk.Ew[pb][tt];
+          const int k2 = E[pa][ss] + Ew[pb][tt];
           if (cnt >= L || k2 != key) {
             s.groups[c][ng].start = gstart;
             s.groups[c][ng].count = cnt;
