@@ -872,29 +872,39 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
 }
 
 // Group rows [g0, g1) of the tile: times w_N^{-j2 k1}, stored to their slots.
+// The (row, quad) items of all groups are spread over the whole workgroup;
+// when blockDim is a multiple of the quads per group row, a thread always
+// handles the same quad, so its four twiddles are loaded once.
 __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u32* tile, const u32* rtw,
                                                  const int (&gofs)[4], int g0, int g1, int SL, int slot_lo,
                                                  int slot_hi, int prime, int logN, size_t base, int m2, int nr,
                                                  int ldr, u32 p) {
   const int quads = (nr << m2) >> 2, N2 = 1 << m2;
-  for (int gi = g0; gi < g1; ++gi) {
+  const int items = (g1 - g0) * quads;
+  const bool fixed = (blockDim.x % quads) == 0;
+  uint4 w = make_uint4(0, 0, 0, 0), wq = w;
+  if (fixed && (int)threadIdx.x < items) {
+    const int e = ((int)threadIdx.x % quads) << 2;
+    w = *reinterpret_cast<const uint4*>(rtw + e);          // roots and companions in separate arrays
+    wq = *reinterpret_cast<const uint4*>(rtw + (nr << m2) + e);
+  }
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    const int gi = g0 + it / quads, q = it % quads;
     const int c = gi >= gofs[3] ? 3 : gi >= gofs[2] ? 2 : gi >= gofs[1] ? 1 : 0;
-    const int slot = c * SL + gi - gofs[c];
+    const int co = gi >= gofs[3] ? gofs[3] : gi >= gofs[2] ? gofs[2] : gi >= gofs[1] ? gofs[1] : 0;
+    const int slot = c * SL + gi - co;
     if (slot < slot_lo || slot >= slot_hi) continue;
-    uint4* go = reinterpret_cast<uint4*>(G + d.G_off + ((size_t)(slot * 2 + prime) << logN) + base);
-    const u32* tv = tile + (gi - g0) * nr * ldr;
-    for (int q = threadIdx.x; q < quads; q += blockDim.x) {
-      const int e = q << 2, r = e >> m2, j2 = e & (N2 - 1);
-      uint4 v = *reinterpret_cast<const uint4*>(tv + r * ldr + pad8(j2));
-      // roots and companions in separate arrays: 16 contiguous bytes per lane
-      const uint4 w = *reinterpret_cast<const uint4*>(rtw + e);
-      const uint4 wq = *reinterpret_cast<const uint4*>(rtw + (nr << m2) + e);
-      v.x = shoup_mul(v.x, w.x, wq.x, p);
-      v.y = shoup_mul(v.y, w.y, wq.y, p);
-      v.z = shoup_mul(v.z, w.z, wq.z, p);
-      v.w = shoup_mul(v.w, w.w, wq.w, p);
-      go[q] = v;
+    const int e = q << 2, r = e >> m2, j2 = e & (N2 - 1);
+    uint4 v = *reinterpret_cast<const uint4*>(tile + ((gi - g0) * nr + r) * ldr + pad8(j2));
+    if (!fixed) {
+      w = *reinterpret_cast<const uint4*>(rtw + e);
+      wq = *reinterpret_cast<const uint4*>(rtw + (nr << m2) + e);
     }
+    v.x = shoup_mul(v.x, w.x, wq.x, p);
+    v.y = shoup_mul(v.y, w.y, wq.y, p);
+    v.z = shoup_mul(v.z, w.z, wq.z, p);
+    v.w = shoup_mul(v.w, w.w, wq.w, p);
+    reinterpret_cast<uint4*>(G + d.G_off + ((size_t)(slot * 2 + prime) << logN) + base)[q] = v;
   }
 }
 
