@@ -40,9 +40,20 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # multiply-accumulate: product 6 + add_mod 3.  Butterflies whose root is 1
 # are counted at full cost (the textbook (N/2) log2 N products).
 OPS_FWD_BFLY, OPS_INV_BFLY, OPS_TWIDDLE, OPS_MAC = 11, 12, 6, 9
+# CRT and exact accumulation per output and group: Garner (z0 mod p1 2,
+# sub_mod 3, product 6, 64-bit z0 + h p0 4, symmetric fold 3) = 18; adding
+# z 2^sh to the 256-bit accumulator: one add-with-carry per 32-bit limb = 8
+OPS_CRT, OPS_ACC = 18, 8
 PASS_STAGES = (4, 5, 6, 7, 8)
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2603_29129_amd", "csrc")
+
+
+def fused_columns(info):
+    """The batched form fuses the inverse column pass with the CRT and the
+    recombination for 2^7 <= N1 <= 2^9."""
+    logN, m1 = info["N"].bit_length() - 1, info["ntt_log2N1"]
+    return logN > 12 and 7 <= m1 <= 9 and 12 - m1 <= logN - m1
 
 
 def stage_kernels(info, K):
@@ -52,6 +63,9 @@ def stage_kernels(info, K):
     m2 = logN - m1
     li = min(max(9 - m2, 0), m1)
     rows = "k_inv_rows_reg" if (K <= 3 and m2 + li == 9) else "k_inv_rows"
+    if fused_columns(info):
+        return {4: f"k_fwd_cols<{m1}>", 5: f"k_fwd_rows<{m2}>", 6: f"{rows}<{m2}>", 7: f"k_inv_cols_rec<{m1}>",
+                8: "k_recombine<true>"}
     return {4: f"k_fwd_cols<{m1}>", 5: f"k_fwd_rows<{m2}>", 6: f"{rows}<{m2}>", 7: f"k_inv_cols<{m1}>",
             8: "k_recombine<false>"}
 
@@ -71,6 +85,8 @@ def algorithmic_ops(infos):
         out[5] += vf * (N * OPS_TWIDDLE + N1 * (N2 // 2) * m2 * OPS_FWD_BFLY)
         out[6] += vi * (N1 * (N2 // 2) * m2 * OPS_INV_BFLY + N * OPS_TWIDDLE) + 2 * N * pairs * OPS_MAC
         out[7] += vi * N2 * (N1 // 2) * m1 * OPS_INV_BFLY
+        if fused_columns(d):
+            out[7] += d["n"] * (vi // 2) * (OPS_CRT + OPS_ACC)
     return out
 
 
@@ -118,8 +134,11 @@ def algorithmic_bytes(infos, K):
         if key not in kernels_seen:                    # kernel spectra + Shoup companions, once per length
             kernels_seen.add(key)
             out[6] += 2 * (d["kw"][0] + d["kw"][1]) * 8 * N
-        out[7] += grp * (4 * N + 4 * n)                # read N, write the first n
-        out[8] += grp * 4 * n + 16 * n + 16 * n        # residues + chirp in, y out
+        if fused_columns(d):
+            out[7] += grp * 4 * N + 16 * n + 16 * n    # read the group rows; chirp in, y out
+        else:
+            out[7] += grp * (4 * N + 4 * n)            # read N, write the first n
+            out[8] += grp * 4 * n + 16 * n + 16 * n    # residues + chirp in, y out
     return out
 
 

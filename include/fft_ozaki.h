@@ -156,7 +156,9 @@ int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_tr
  *   1  x' = x (.) w                          double2[n]
  *   2  forward NTTs of the x' slices         uint32[2][K][2][N]  (part, slice, prime; NTT-domain order)
  *   3  inverse NTT outputs per group         uint32[4*K*K][2][n4] (slot = conv*K*K + group, prime;
- *                                            n4 = n rounded up to a multiple of 4, first n valid)
+ *                                            n4 = n rounded up to a multiple of 4, first n valid; where
+ *                                            the batched form fuses the column pass with the CRT these
+ *                                            are rebuilt from the stored row-pass output by the call)
  *   4  kernel NTTs times N^{-1}              uint32[2][K][2][N]
  *   5  chirp (cos, sin)                      double2[n]
  * `bytes` must be at least the stage size (FFT_OZAKI_ERR_INVALID otherwise);
@@ -171,7 +173,10 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
  * 2 Alg. 8 group tables, 3 forward NTTs (both passes), 4 forward column
  * pass, 5 forward row pass, 6 inverse row pass with the fused NTT-domain
  * multiply-accumulate (for N <= 4096: the whole inverse), 7 inverse column
- * pass, 8 CRT/recombination/postmultiply.  Stages 3-5 transform the slice
+ * pass (for 2^13 <= N <= 2^18 fused with the CRT, recombination and
+ * postmultiply), 8 CRT/recombination/postmultiply (for the fused lengths:
+ * only the unfused fallback of transforms whose exponent span needs the wide
+ * accumulator).  Stages 3-5 transform the slice
  * buffers again in place, so intermediates read with fft_ozaki_debug_dump
  * afterwards are not those of the last execution.  Batched plans only. */
 int fft_ozaki_profile_stage(fft_ozaki_plan_t plan, int stage, int reps, void* stream);

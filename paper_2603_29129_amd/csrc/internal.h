@@ -61,9 +61,19 @@ hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, co
 hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K,
                             bool valid_full, int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb,
                             const TwStep& st, int which, hipStream_t s);
+// only_wide: the column pass skips transforms the fused column pass handles.
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
-                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s);
+                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s, bool only_wide = false);
+
+// Fused inverse column pass + CRT + recombination + postmultiply for the
+// two-pass lengths with 2^7 <= N1 <= 2^9 (fused_cols_ok); transforms whose
+// exponent span needs the wide accumulator are left out (they take the
+// column pass with only_wide and launch_recombine_wide).
+bool fused_cols_ok(const NttGeom& g);
+hipError_t launch_inv_cols_rec(const u32* G, double2* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                               const int* tlist, int count, int K, const NttGeom& g, const TwBlock& tb, int dir,
+                               hipStream_t s);
 
 // Kernel slices: multiply by N^{-1} and build Shoup companions.
 hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s);
@@ -86,5 +96,9 @@ hipError_t launch_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
 hipError_t launch_recombine(const u32* Z, double2* out, const TDesc* td, const TState* ts,
                             const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
                             int dir, hipStream_t s);
+// Only the transforms whose exponent span needs the wide accumulator.
+hipError_t launch_recombine_wide(const u32* Z, double2* out, const TDesc* td, const TState* ts,
+                                 const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
+                                 int dir, hipStream_t s);
 
 }  // namespace fo

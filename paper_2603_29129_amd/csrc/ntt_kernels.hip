@@ -30,6 +30,7 @@
 //    registers.  N^{-1} is folded into the precomputed kernel transforms.
 #include <algorithm>
 
+#include "crt_dev.h"
 #include "internal.h"
 
 #include <mutex>
@@ -1121,12 +1122,13 @@ __device__ __forceinline__ void put_col_tile(ColStage& b, u32* tile, int tot4, i
 template <int M1>
 __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, const TDesc* td, const TState* ts,
                                                           const int* tlist, int K, int slot_lo, int slot_hi,
-                                                          NttGeom g, TwBlock tb, int vpw) {
+                                                          NttGeom g, TwBlock tb, int vpw, int only_wide) {
   extern __shared__ u32 smem[];
   const int t = tlist[blockIdx.z];
   const TDesc& d = td[t];
   const TState& s = ts[t];
   if (s.status) return;
+  if (only_wide && !span_wide(s, 0) && !span_wide(s, 1)) return;   // done by the fused pass
   ColVecs cv;
   cv.gofs[0] = 0;
   cv.gofs[1] = s.ngroups[0];
@@ -1168,6 +1170,173 @@ __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, 
     }
     __syncthreads();
     j = jn;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused inverse column pass, Garner CRT, exact recombination and chirp
+// postmultiply (two-pass lengths with N1 <= 512, i.e. N <= 2^18; the tile
+// rows of longer lengths would be 16 bytes).  One workgroup of
+// REC_THREADS per (column tile of 2^(12 - M1) columns, transform): for every
+// Alg. 8 group the column vectors of both primes are transformed together,
+// combined by Garner's formula and added, shifted by the group's exponent,
+// to exact per-output accumulators held in registers (REC_OUT outputs per
+// thread); the Re y' groups come first, then the Im y' groups, so one set of
+// accumulators serves both components.  The group residues never go to
+// memory.  Transforms whose exponent span needs the wide accumulator are
+// left to the unfused column pass and recombination.
+
+// One round of the inverse column transforms of two tiles (prime 0 and 1):
+// the groups of tile 1 follow those of tile 0, so every wave works on one
+// prime.
+template <int M, int S0, int RL>
+__device__ __forceinline__ void round_dual(u32* tile0, u32* tile1, int nv, const uint2* tw0, const uint2* tw1) {
+  constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
+  const int per = 1 << (nv + LGPV);
+  const int sst = ST << nv;
+  for (int g = threadIdx.x; g < 2 * per; g += blockDim.x) {
+    const bool hi = g >= per;
+    const int gg = hi ? g - per : g;
+    u32* lds = hi ? tile1 : tile0;
+    const uint2* tw = hi ? tw1 : tw0;
+    const u32 p = hi ? P1 : P0;
+    uint2 twr[R];
+    if (ST == 1) {
+#pragma unroll
+      for (int ss = 0; ss < RL; ++ss) {
+        const int hd = R >> (ss + 1);
+#pragma unroll
+        for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = tw[jj << (S0 + ss)];
+      }
+    }
+    const int v = gg & ((1 << nv) - 1), q = gg >> nv;
+    const int off = q & (ST - 1);
+    const int base = ((q >> LST) << LBK) + off;
+    u32* p0 = lds + (base << nv) + v;
+    u32 a[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) a[j] = p0[j * sst];
+    radix_group_t<RL, S0, ST, true, false>(a, off, tw, twr, p);
+#pragma unroll
+    for (int j = 0; j < R; ++j) p0[j * sst] = a[j];
+  }
+}
+template <int M, int I>
+__device__ __forceinline__ void rounds_dual(u32* tile0, u32* tile1, int nv, const uint2* tw0, const uint2* tw1) {
+  constexpr int NR = (M + 2) / 3, RB = NR ? M / NR : 0, RX = NR ? M % NR : 0;
+  if constexpr (I < NR) {
+    constexpr int IDX = NR - 1 - I;                           // inverse: rounds in reverse order
+    constexpr int S0 = IDX * RB + (IDX < RX ? IDX : RX);
+    constexpr int RL = RB + (IDX < RX ? 1 : 0);
+    round_dual<M, S0, RL>(tile0, tile1, nv, tw0, tw1);
+    __syncthreads();
+    rounds_dual<M, I + 1>(tile0, tile1, nv, tw0, tw1);
+  }
+}
+
+constexpr int REC_THREADS = 1024, REC_OUT = 4;   // 4096-position tiles
+template <int M1>
+__global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, double2* out, const TDesc* td,
+                                                              const TState* ts, const KernelDesc* kd,
+                                                              const int* tlist, int K, int m2, TwBlock tb, int dir) {
+  constexpr int LC = 12 - M1, LQ = LC - 2, TILE = 1 << 12;
+  static_assert(LC >= 2 && TILE == REC_THREADS * REC_OUT, "tile shape");
+  extern __shared__ u32 smem[];
+  const int t = tlist[blockIdx.z];
+  const TDesc& d = td[t];
+  const TState& s = ts[t];
+  if (!s.status && (span_wide(s, 0) || span_wide(s, 1))) return;    // unfused path
+  const int n = d.n, N2 = 1 << m2;
+  const int j2_0 = col_tile(blockIdx.x, m2 - LC) << LC;
+  const double2* ch = kd[d.kd].chirp;
+  double2* yo = out + d.io_off;
+  if (s.status) {
+#pragma unroll
+    for (int k = 0; k < REC_OUT; ++k) {
+      const int o = threadIdx.x + k * REC_THREADS;
+      const int j = (o >> LC) * N2 + j2_0 + (o & ((1 << LC) - 1));
+      if (j < n) yo[j] = make_double2(__builtin_nan(""), __builtin_nan(""));
+    }
+    return;
+  }
+  uint2* tw0 = reinterpret_cast<uint2*>(smem);               // inverse roots, 2^(M1-1) per prime
+  uint2* tw1 = tw0 + (1 << (M1 - 1));
+  u32* tile0 = smem + (2 << M1);
+  u32* tile1 = tile0 + TILE;
+  load_block_tw(tw0, tb.inv[0], M1);
+  load_block_tw(tw1, tb.inv[1], M1);
+  ColVecs cv;                                                 // group numbering (slot_of)
+  cv.gofs[0] = 0;
+  cv.gofs[1] = s.ngroups[0];
+  cv.gofs[2] = cv.gofs[1] + s.ngroups[1];
+  cv.gofs[3] = cv.gofs[2] + s.ngroups[2];
+  cv.SL = K * K;
+  const int V = cv.gofs[3] + s.ngroups[3];                    // groups; Re y' groups are [0, gofs[2])
+  const u32* gb = G + d.G_off;
+  // this thread's quad of the tile: row i, columns c4 .. c4 + 3
+  const int qi = threadIdx.x >> LQ, qc = (threadIdx.x & ((1 << LQ) - 1)) << 2;
+  const size_t goff = ((size_t)qi << m2) + j2_0 + qc;
+  u32x4 st0 = {0, 0, 0, 0}, st1 = {0, 0, 0, 0};
+  auto fetch = [&](int v) {
+    const u32* vec = gb + ((size_t)(cv.slot_of(2 * v) * 2) << d.logN);
+    st0 = *reinterpret_cast<const u32x4*>(vec + goff);
+    st1 = *reinterpret_cast<const u32x4*>(vec + ((size_t)1 << d.logN) + goff);
+  };
+  u32 acc[REC_OUT][NL_FAST];
+  double pr[REC_OUT];
+#pragma unroll
+  for (int k = 0; k < REC_OUT; ++k) {
+    pr[k] = 0.0;
+#pragma unroll
+    for (int l = 0; l < NL_FAST; ++l) acc[k][l] = 0;
+  }
+  if (V > 0) fetch(0);
+  __syncthreads();                                            // root tables
+  for (int v = 0; v < V; ++v) {
+    if (v == cv.gofs[2] && v > 0) {                           // Re y' complete
+#pragma unroll
+      for (int k = 0; k < REC_OUT; ++k) {
+        u64 a64[W_FAST];
+#pragma unroll
+        for (int w = 0; w < W_FAST; ++w) a64[w] = (u64)acc[k][2 * w] | ((u64)acc[k][2 * w + 1] << 32);
+        pr[k] = acc_round<W_FAST>(a64, s.emin[0]);
+#pragma unroll
+        for (int l = 0; l < NL_FAST; ++l) acc[k][l] = 0;
+      }
+    }
+    *reinterpret_cast<u32x4*>(tile0 + (qi << LC) + qc) = st0;
+    *reinterpret_cast<u32x4*>(tile1 + (qi << LC) + qc) = st1;
+    __syncthreads();
+    if (v + 1 < V) fetch(v + 1);
+    rounds_dual<M1, 0>(tile0, tile1, LC, tw0, tw1);
+    const int c = v >= cv.gofs[3] ? 3 : v >= cv.gofs[2] ? 2 : v >= cv.gofs[1] ? 1 : 0;
+    const int gidx = v - (v >= cv.gofs[3] ? cv.gofs[3] : v >= cv.gofs[2] ? cv.gofs[2] : v >= cv.gofs[1] ? cv.gofs[1] : 0);
+    const int sh = s.groups[c][gidx].e - (c >= 2 ? s.emin[1] : s.emin[0]);
+#pragma unroll
+    for (int k = 0; k < REC_OUT; ++k) {
+      const int o = threadIdx.x + k * REC_THREADS;
+      i64 z = garner(tile0[o], tile1[o]);
+      if (c == 1) z = -z;                                     // Re y' = ReRe - ImIm
+      limb_add(acc[k], z, sh);
+    }
+    __syncthreads();
+  }
+  double pi[REC_OUT];
+  const bool has_im = V > cv.gofs[2];
+#pragma unroll
+  for (int k = 0; k < REC_OUT; ++k) {
+    u64 a64[W_FAST];
+#pragma unroll
+    for (int w = 0; w < W_FAST; ++w) a64[w] = (u64)acc[k][2 * w] | ((u64)acc[k][2 * w + 1] << 32);
+    const double r = acc_round<W_FAST>(a64, has_im ? s.emin[1] : s.emin[0]);
+    pi[k] = has_im ? r : 0.0;
+    if (!has_im) pr[k] = r;
+  }
+#pragma unroll
+  for (int k = 0; k < REC_OUT; ++k) {
+    const int o = threadIdx.x + k * REC_THREADS;
+    const int j = (o >> LC) * N2 + j2_0 + (o & ((1 << LC) - 1));
+    if (j < n) yo[j] = finish(pr[k], pi[k], ch[j], dir, n);
   }
 }
 
@@ -1351,7 +1520,7 @@ hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const 
 
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
-                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s) {
+                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s, bool only_wide) {
   if (count <= 0 || slot_hi <= slot_lo) return hipSuccess;
   hipError_t e = hipSuccess;
   if (!g.two_pass()) {
@@ -1399,17 +1568,38 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
           constexpr int M1 = decltype(mc)::value;
           if ((e = big_lds((const void*)k_inv_cols<M1>)) != hipSuccess) return;
           hipLaunchKernelGGL(k_inv_cols<M1>, grid, dim3(COL_THREADS), smem_inv_cols(g), s, G, Z, td, ts, tlist, K,
-                             slot_lo, slot_hi, g, tb, vpw);
+                             slot_lo, slot_hi, g, tb, vpw, only_wide ? 1 : 0);
         }))
       return hipErrorInvalidValue;
   }
   return e != hipSuccess ? e : hipGetLastError();
 }
 
+bool fused_cols_ok(const NttGeom& g) {
+  return g.two_pass() && g.m1 >= 7 && g.m1 <= 9 && 12 - g.m1 <= g.m2;
+}
+
+hipError_t launch_inv_cols_rec(const u32* G, double2* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                               const int* tlist, int count, int K, const NttGeom& g, const TwBlock& tb, int dir,
+                               hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (!fused_cols_ok(g)) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+  with_m<7, 9>(g.m1, [&](auto mc) {
+    constexpr int M1 = decltype(mc)::value;
+    constexpr int LC = 12 - M1;
+    const size_t smem = ((size_t)(2 << M1) + 2 * 4096) * 4;
+    if ((e = big_lds((const void*)k_inv_cols_rec<M1>)) != hipSuccess) return;
+    hipLaunchKernelGGL(k_inv_cols_rec<M1>, dim3(1u << (g.m2 - LC), 1, count), dim3(REC_THREADS), smem, s, G, out, td,
+                       ts, kd, tlist, K, g.m2, tb, dir);
+  });
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
 hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts,
                                const KernelDesc* kd, const int* tlist, int count, int K, int slot_lo, int slot_hi,
                                const NttGeom& g, const TwBlock& tb, const TwStep& st, hipStream_t s) {
-  return launch_inv_stage(X, G, Z, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, 0, s);
+  return launch_inv_stage(X, G, Z, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, 0, s, false);
 }
 
 hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s) {

@@ -451,11 +451,23 @@ static int enqueue_batched(fft_ozaki_plan_s* p, const double2* in, double2* out,
   for (auto& lc : p->classes)
     HIPCHK(launch_fwd_pipeline(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K, lc.geom,
                                p->tb, step_for(p, lc.logN), s));
-  for (auto& lc : p->classes)
-    HIPCHK(launch_inv_pipeline(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), K, 0,
-                               4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), s));
-  for (auto& lc : p->classes)
-    HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, dir, s));
+  for (auto& lc : p->classes) {
+    const int cnt = (int)lc.tids.size();
+    if (fused_cols_ok(lc.geom)) {
+      // rows; fused columns + CRT + recombination; the unfused path for the
+      // transforms that need the wide accumulator
+      HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
+                              p->tb, step_for(p, lc.logN), 1, s));
+      HIPCHK(launch_inv_cols_rec(p->G, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir, s));
+      HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
+                              p->tb, step_for(p, lc.logN), 2, s, true));
+      HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
+    } else {
+      HIPCHK(launch_inv_pipeline(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K,
+                                 lc.geom, p->tb, step_for(p, lc.logN), s));
+      HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
+    }
+  }
   return FFT_OZAKI_OK;
 }
 
@@ -570,14 +582,31 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
       }
       return FFT_OZAKI_OK;
     case 6:
-    case 7:
       for (auto& lc : p->classes)
         HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), K, 0,
-                                4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), stage - 5, s));
+                                4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), 1, s));
       return FFT_OZAKI_OK;
-    case 8:
-      for (auto& lc : p->classes)
-        HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, dir, s));
+    case 7:   // column pass (fused with CRT and recombination where the length allows)
+      for (auto& lc : p->classes) {
+        const int cnt = (int)lc.tids.size();
+        if (fused_cols_ok(lc.geom))
+          HIPCHK(launch_inv_cols_rec(p->G, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir, s));
+        else
+          HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K,
+                                  lc.geom, p->tb, step_for(p, lc.logN), 2, s));
+      }
+      return FFT_OZAKI_OK;
+    case 8:   // recombination (for fused lengths: the wide-accumulator fallback only)
+      for (auto& lc : p->classes) {
+        const int cnt = (int)lc.tids.size();
+        if (fused_cols_ok(lc.geom)) {
+          HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K,
+                                  lc.geom, p->tb, step_for(p, lc.logN), 2, s, true));
+          HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
+        } else {
+          HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
+        }
+      }
       return FFT_OZAKI_OK;
     default:
       return fail(FFT_OZAKI_ERR_INVALID, "unknown stage");
@@ -766,6 +795,17 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
   HIPCHK(hipGetDevice(&cur));
   HIPCHK(hipSetDevice(plan->device));
   HIPCHK(hipDeviceSynchronize());
+  if (stage == 3 && plan->mode == FFT_OZAKI_MODE_BATCHED) {
+    // the fused column pass keeps the group residues in registers; rebuild
+    // them for this transform's length class from the stored row-pass output
+    for (auto& lc : plan->classes) {
+      if (lc.logN != d.logN || !fused_cols_ok(lc.geom)) continue;
+      HIPCHK(launch_inv_stage(plan->X, plan->G, plan->Z, plan->d_td, plan->d_ts, plan->d_kd, lc.d_tlist,
+                              (int)lc.tids.size(), K, 0, 4 * K * K, lc.geom, plan->tb, step_for(plan, lc.logN), 2,
+                              nullptr));
+      HIPCHK(hipDeviceSynchronize());
+    }
+  }
   HIPCHK(hipMemcpy(host_dst, src, sz, hipMemcpyDeviceToHost));
   (void)hipSetDevice(cur);
   return FFT_OZAKI_OK;

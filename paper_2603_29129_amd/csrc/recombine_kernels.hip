@@ -11,117 +11,9 @@
 // rounded once to binary64, round to nearest even, subnormals and overflow
 // included.  The chirp postmultiply y = y' (.) w (Sec. 3.2 Step 3) uses the
 // same unfused product rule as the premultiply.
-#include "internal.h"
+#include "crt_dev.h"
 
 namespace fo {
-
-constexpr u32 P0INV_Q = (u32)(((u64)P0_INV_MOD_P1 << 32) / P1);
-
-__device__ __forceinline__ i64 garner(u32 z0, u32 z1) {
-  const u32 z0m = umin32(z0, z0 - P1);                 // z0 mod p1 (z0 < p0 < 2 p1)
-  const u32 dl = sub_mod(z1, z0m, P1);
-  const u32 h = shoup_mul(dl, P0_INV_MOD_P1, P0INV_Q, P1);
-  const u64 z = (u64)z0 + (u64)h * P0;                  // in [0, p0 p1)
-  return z > PP_HALF ? (i64)(z - PP) : (i64)z;
-}
-
-template <int W>
-__device__ __forceinline__ void acc_add(u64 (&acc)[W], i64 z, int sh) {
-  const int wi = sh >> 6, b = sh & 63;
-  const u64 ext = z < 0 ? ~0ull : 0ull;
-  const u64 lo = (u64)z << b;
-  const u64 hi = b ? (u64)(z >> (64 - b)) : ext;
-  u64 carry = 0;
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    const u64 add = w < wi ? 0ull : (w == wi ? lo : (w == wi + 1 ? hi : ext));
-    const u64 s1 = acc[w] + add;
-    const u64 c1 = s1 < add;
-    const u64 s2 = s1 + carry;
-    const u64 c2 = s2 < carry;
-    acc[w] = s2;
-    carry = c1 | c2;
-  }
-}
-
-// RN(acc * 2^emin) with acc a W-word two's complement integer.
-template <int W>
-__device__ double acc_round(u64 (&acc)[W], int emin) {
-  const bool neg = (i64)acc[W - 1] < 0;
-  if (neg) {
-    u64 carry = 1;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const u64 v = ~acc[w] + carry;
-      carry = (carry && v == 0) ? 1 : 0;
-      acc[w] = v;
-    }
-  }
-  int wt = -1;
-#pragma unroll
-  for (int w = 0; w < W; ++w)
-    if (acc[w]) wt = w;
-  if (wt < 0) return 0.0;
-  u64 top = 0, below = 0;
-  bool lower_nz = false;
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    if (w == wt) top = acc[w];
-    if (w == wt - 1) below = acc[w];
-    if (w < wt - 1 && acc[w]) lower_nz = true;
-  }
-  const int lz = __clzll(top);
-  const int Lb = 64 * wt + 63 - lz;                     // leading bit position
-  const u64 T = lz ? ((top << lz) | (below >> (64 - lz))) : top;
-  const bool sticky = lower_nz || (lz ? ((below << lz) != 0) : (below != 0));
-  const int E2 = Lb + emin;                             // value in [2^E2, 2^(E2+1))
-  const int kept = E2 >= -1022 ? 53 : E2 + 1075;
-  double res;
-  if (kept <= 0) {
-    res = (kept == 0 && (T != (1ull << 63) || sticky)) ? 0x1p-1074 : 0.0;
-  } else {
-    const int sh = 64 - kept;
-    u64 mant = T >> sh;
-    const u64 rem = T & ((1ull << sh) - 1);
-    const u64 half = 1ull << (sh - 1);
-    if (rem > half || (rem == half && (sticky || (mant & 1)))) ++mant;
-    res = ldexp((double)mant, E2 - kept + 1);
-  }
-  return neg ? -res : res;
-}
-
-// Fast path: the accumulator as 2 W_FAST 32-bit limbs; z 2^sh is added at
-// limb sh / 32 with one add-with-carry chain (the limb index is the same for
-// every lane, so the chain is chosen by a scalar branch).
-constexpr int NL_FAST = 2 * W_FAST;
-template <int L>
-__device__ __forceinline__ void limb_add_at(u32 (&acc)[NL_FAST], u32 l0, u32 l1, u32 l2, u32 ext) {
-  u32 c;
-  acc[L] = __builtin_addc(acc[L], l0, 0u, &c);
-  if constexpr (L + 1 < NL_FAST) acc[L + 1] = __builtin_addc(acc[L + 1], l1, c, &c);
-  if constexpr (L + 2 < NL_FAST) acc[L + 2] = __builtin_addc(acc[L + 2], l2, c, &c);
-#pragma unroll
-  for (int k = L + 3; k < NL_FAST; ++k) acc[k] = __builtin_addc(acc[k], ext, c, &c);
-}
-// acc += z 2^sh, two's complement; the caller guarantees the sum fits (sh <= span).
-__device__ __forceinline__ void limb_add(u32 (&acc)[NL_FAST], i64 z, int sh) {
-  const int b = sh & 31;
-  const u64 lo = (u64)z << b;                                  // bits 0..63 of z 2^b
-  const u32 l2 = (u32)((z >> 32) >> (32 - b));                 // bits 64..95 (b = 0: the sign)
-  const u32 ext = (u32)(z >> 63);
-  const u32 l0 = (u32)lo, l1 = (u32)(lo >> 32);
-  switch (sh >> 5) {
-    case 0: limb_add_at<0>(acc, l0, l1, l2, ext); break;
-    case 1: limb_add_at<1>(acc, l0, l1, l2, ext); break;
-    case 2: limb_add_at<2>(acc, l0, l1, l2, ext); break;
-    case 3: limb_add_at<3>(acc, l0, l1, l2, ext); break;
-    case 4: limb_add_at<4>(acc, l0, l1, l2, ext); break;
-    case 5: limb_add_at<5>(acc, l0, l1, l2, ext); break;
-    case 6: limb_add_at<6>(acc, l0, l1, l2, ext); break;
-    default: limb_add_at<7>(acc, l0, l1, l2, ext); break;
-  }
-}
-static_assert(NL_FAST == 8, "limb_add dispatches over eight limbs");
 
 __device__ __constant__ int c_tconv[2][2] = {{0, 1}, {2, 3}};
 __device__ __constant__ int c_tsign[2][2] = {{1, -1}, {1, 1}};
@@ -182,21 +74,6 @@ __device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, 
   return acc_round<W>(acc, emin);
 }
 
-// Postmultiply and direction handling of one output.
-__device__ __forceinline__ double2 finish(double pr, double pi, double2 w, int dir, int n) {
-  double yr = pr * w.x + pi * w.y;     // RN(RN(y'r c) + RN(y'i s))
-  double yi = pi * w.x - pr * w.y;     // RN(RN(y'i c) - RN(y'r s))
-  if (dir) {                           // inverse / adjoint: conj(F(conj x)) [/ n]
-    yi = -yi;
-    if (dir == 1) {
-      const double nn = (double)n;
-      yr = yr / nn;
-      yi = yi / nn;
-    }
-  }
-  return make_double2(yr, yi);
-}
-
 // WIDE = false: transforms whose exponent spans fit the fast accumulator (and
 // those with a status, which get NaN), two outputs per thread;
 // WIDE = true: the others, one output per thread.
@@ -206,7 +83,7 @@ __global__ void k_recombine(const u32* Z, double2* out, const TDesc* td, const T
   const int t = tlist[blockIdx.z];
   const TDesc& d = td[t];
   const TState& s = ts[t];
-  const bool wide0 = s.span[0] > 64 * W_FAST - 71, wide1 = s.span[1] > 64 * W_FAST - 71;
+  const bool wide0 = span_wide(s, 0), wide1 = span_wide(s, 1);
   if (WIDE != (!s.status && (wide0 || wide1))) return;
   const double2* ch = kd[d.kd].chirp;
   const int SL = K * K;
@@ -247,4 +124,16 @@ hipError_t launch_recombine(const u32* Z, double2* out, const TDesc* td, const T
   return hipGetLastError();
 }
 
+}  // namespace fo
+
+namespace fo {
+hipError_t launch_recombine_wide(const u32* Z, double2* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                                 const int* tlist, int count, int nmax, int K, int dir, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int b = (nmax + 255) / 256;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir);
+  return hipGetLastError();
+}
 }  // namespace fo
