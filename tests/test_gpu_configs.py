@@ -142,3 +142,32 @@ def test_autograd_gradcheck_small(torch_mod):
     torch = torch_mod
     x = _gpu(torch, wl.uniform(12, batch=2, seed=1)).requires_grad_(True)
     assert torch.autograd.gradcheck(lambda t: oz.OzakiDFT.apply(t), (x,), eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+@pytest.mark.parametrize("n", [1 << 24, (1 << 23) - 1])
+def test_maximum_length(torch_mod, n):
+    """The largest convolution length both primes support, N = 2^24 (cyclic
+    n = 2^24; padded n = 2^23 - 1, the largest length that is not a power
+    of two; 2^23 + 1 is rejected at plan time): the oracle cannot run this size in
+    seconds, so the checks are properties that hold at any size: accuracy
+    against numpy's complex128 FFT, the inverse round trip, and bit-identity
+    of a transform computed in a batch of two with the same transform alone."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = wl.uniform(n, batch=1, seed=3)
+    xd = _gpu(torch, x)
+    plan = oz.Plan(n, 1)
+    assert plan.transform_info(0)["N"] == 1 << 24
+    y = plan.forward(xd)
+    ref_y = np.fft.fft(x[0])
+    yh = y.cpu().numpy()[0]
+    assert np.linalg.norm(yh - ref_y) / np.linalg.norm(ref_y) < 1e-14
+    z = plan.inverse(y).cpu().numpy()[0]
+    assert np.max(np.abs(z - x[0])) < 1e-13
+    del plan
+    torch.cuda.empty_cache()
+    if n == 1 << 24:
+        x2 = np.concatenate([wl.uniform(n, batch=1, seed=4), x])
+        p2 = oz.Plan(n, 2)
+        y2 = p2.forward(_gpu(torch, x2)).cpu().numpy()
+        assert np.array_equal(y2[1].view(np.uint64), yh.view(np.uint64))

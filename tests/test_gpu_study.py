@@ -1,0 +1,44 @@
+"""The accuracy and NTT-count study (the paper's Sec. 5 grid) on small n:
+every count equals the oracle's for the same transforms, the paper's
+printed totals hold, and the errors behave as the paper reports (K = 3
+at the level of K = inf, K = 1 far worse)."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import bluestein as bl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("phi", [0.0, 1.0, 4.0])
+def test_study_counts_match_oracle(phi):
+    import paper_2603_29129_amd.study as st
+    n, batch = 1024, 2
+    for K, L in st.KL_GRID:
+        r = st.run_case(n, K, L, phi, batch=batch, seed=0)
+        k = st.K_INF if K == "inf" else K
+        x = wl.paper_phi(n, phi, seed=0, batch=batch)
+        kp = bl.KernelPlan(n, k, L, cyclic=True)
+        counts = [bl.ntt_counts(bl.forward_trace(x[b], k, L, kp), kp) for b in range(batch)]
+        assert r["ntt_runtime"] == max(c["runtime"] for c in counts), (K, L)
+        assert r["ntt_offline"] == counts[0]["forward_offline"]
+        if (K, L) == (3, 3) and phi < 4:
+            assert r["ntt_runtime"] == 52 and r["ntt_total"] == 64       # printed in Sec. 5.2
+        if (K, L) == (3, 3) and phi == 4:
+            assert r["ntt_total"] <= 80
+        if (K, L) == (3, 1):
+            assert r["ntt_total"] == 96
+        assert r["status"] == 0
+
+
+def test_study_error_levels():
+    import paper_2603_29129_amd.study as st
+    n = 4096
+    res = {(K, L): st.run_case(n, K, L, 1.0, batch=2) for K, L in st.KL_GRID}
+    assert res[("inf", 1)]["rel_l2_error"] < 1e-15
+    assert res[(3, 3)]["rel_l2_error"] < 1e-15
+    assert res[(3, 1)]["rel_l2_error"] < 1e-15
+    assert res[(1, 1)]["rel_l2_error"] > 1e-9          # one slice of about 20 bits
+    assert res[(2, 1)]["rel_l2_error"] < res[(1, 1)]["rel_l2_error"]
