@@ -56,18 +56,33 @@ def fused_columns(info):
     return logN > 12 and 7 <= m1 <= 9 and 12 - m1 <= logN - m1
 
 
-def stage_kernels(info, K):
-    """Kernel launched by each pass stage (one launch per stage for a uniform
-    batch), by the name rocprofv3 reports."""
+def folded_rows(info, K):
+    """The batched form folds the forward row pass into the inverse row pass
+    (register form, K <= 3, 512-position row tiles that hold the 2K forward
+    slice rows)."""
     logN, m1 = info["N"].bit_length() - 1, info["ntt_log2N1"]
     m2 = logN - m1
     li = min(max(9 - m2, 0), m1)
-    rows = "k_inv_rows_reg" if (K <= 3 and m2 + li == 9) else "k_inv_rows"
+    gch = max(1, (20 if m2 <= 9 else 20 >> (m2 - 9)) >> li)
+    return logN > 12 and K <= 3 and m2 + li == 9 and 2 * K <= gch
+
+
+def stage_kernels(info, K):
+    """Kernel launched by each pass stage (one launch per stage for a uniform
+    batch), by the name rocprofv3 reports (None: the stage launches nothing)."""
+    logN, m1 = info["N"].bit_length() - 1, info["ntt_log2N1"]
+    m2 = logN - m1
+    li = min(max(9 - m2, 0), m1)
+    if K <= 3 and m2 + li == 9:
+        rows = f"k_inv_rows_reg<{m2}, {'true' if folded_rows(info, K) else 'false'}>"
+    else:
+        rows = f"k_inv_rows<{m2}>"
+    out = {4: f"k_fwd_cols<{m1}>", 5: None if folded_rows(info, K) else f"k_fwd_rows<{m2}>", 6: rows}
     if fused_columns(info):
-        return {4: f"k_fwd_cols<{m1}>", 5: f"k_fwd_rows<{m2}>", 6: f"{rows}<{m2}>", 7: f"k_inv_cols_rec<{m1}>",
-                8: "k_recombine<true>"}
-    return {4: f"k_fwd_cols<{m1}>", 5: f"k_fwd_rows<{m2}>", 6: f"{rows}<{m2}>", 7: f"k_inv_cols<{m1}>",
-            8: "k_recombine<false>"}
+        out.update({7: f"k_inv_cols_rec<{m1}>", 8: "k_recombine<true>"})
+    else:
+        out.update({7: f"k_inv_cols<{m1}>", 8: "k_recombine<false>"})
+    return out
 
 
 def algorithmic_ops(infos):
@@ -82,7 +97,8 @@ def algorithmic_ops(infos):
         vi = 2 * sum(d["ngroups"])                   # inverse vectors (group, prime)
         pairs = sum(d["kx"][pa] * d["kw"][pb] for pa, pb in ((0, 0), (1, 1), (1, 0), (0, 1)))
         out[4] += vf * N2 * (N1 // 2) * m1 * OPS_FWD_BFLY
-        out[5] += vf * (N * OPS_TWIDDLE + N1 * (N2 // 2) * m2 * OPS_FWD_BFLY)
+        # the forward row pass runs inside the inverse row pass where folded
+        out[6 if folded_rows(d, 3) else 5] += vf * (N * OPS_TWIDDLE + N1 * (N2 // 2) * m2 * OPS_FWD_BFLY)
         out[6] += vi * (N1 * (N2 // 2) * m2 * OPS_INV_BFLY + N * OPS_TWIDDLE) + 2 * N * pairs * OPS_MAC
         out[7] += vi * N2 * (N1 // 2) * m1 * OPS_INV_BFLY
         if fused_columns(d):
@@ -128,7 +144,8 @@ def algorithmic_bytes(infos, K):
         vecs = 2 * (d["kx"][0] + d["kx"][1])          # forward NTT vectors (part, slice, prime)
         grp = 2 * sum(d["ngroups"])                    # inverse NTT vectors (group, prime)
         out[4] += vecs * (4 * n + 4 * N)               # read the n non-zero inputs, write N
-        out[5] += vecs * 8 * N                         # read + write N
+        if not folded_rows(d, K):
+            out[5] += vecs * 8 * N                     # read + write N
         out[6] += vecs * 4 * N + grp * 4 * N           # read the slice spectra, write the group rows
         key = (n, N)
         if key not in kernels_seen:                    # kernel spectra + Shoup companions, once per length
@@ -261,7 +278,7 @@ def main():
     ops = algorithmic_ops(infos)
     names = stage_kernels(infos[0], 3)
     # the dominant kernel (longest pass) is bound by its integer VALU work
-    dom = max((4, 5, 6, 7), key=lambda s: stage_ms[s])
+    dom = max((s for s in (4, 5, 6, 7) if names[s]), key=lambda s: stage_ms[s])
     achieved = ops[dom] / (stage_ms[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": measured_traffic(names[dom]),
@@ -271,6 +288,8 @@ def main():
                 "hbm_frac": round(alg[dom] / (stage_ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     per_kernel = {}
     for s in PASS_STAGES:
+        if names[s] is None:
+            continue
         e = {"ms": round(stage_ms[s], 4), "alg_GBps": round(alg[s] / (stage_ms[s] * 1e-3) / 1e9, 1),
              "traffic": measured_traffic(names[s])}
         if s in ops:

@@ -65,7 +65,20 @@ constexpr int KT = 3;            // slices per operand handled from registers in
 // compile-time offsets from tw + (off << s).  When ST = 1 (off = 0) the roots
 // of the round are the same for every group (`twr`, preloaded) and those with
 // j mod hd = 0 are 1, so those butterflies skip the product.
-template <int RL, int S0, int ST, bool INV, bool HOIST>
+// Root w_M^e of a block transform from its table.  MIRROR: the table holds
+// the inverse roots w_M^-e for e <= M/2 (one entry more than usual) and the
+// forward root is taken from it as w^e = -w^(e - M/2) = -(w^-1)^(M/2 - e):
+// p minus the value, and the Shoup companion of p - w is the bitwise
+// complement of that of w (0 < w < p).  This lets a kernel that runs
+// inverse transforms also run forward ones with one table.
+template <int M, bool MIRROR>
+__device__ __forceinline__ uint2 block_root(const uint2* __restrict__ tw, int e, u32 p) {
+  if (!MIRROR) return tw[e];
+  const uint2 r = tw[(M >> 1) - e];
+  return make_uint2(p - r.x, ~r.y);
+}
+
+template <int RL, int S0, int ST, bool INV, bool HOIST, int MLEN = 0, bool MIRROR = false>
 __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const uint2* __restrict__ tw,
                                               const uint2 (&twr)[1 << RL], u32 p) {
   constexpr int R = 1 << RL;
@@ -81,7 +94,8 @@ __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const 
       const int jj = j & (hd - 1);
       const bool trivial = (ST == 1) && jj == 0;
       uint2 w = make_uint2(1u, 0u);
-      if (!trivial) w = (ST == 1 || HOIST) ? twr[hd + jj] : tws[(jj * ST) << s];
+      if (!trivial) w = (ST == 1 || HOIST) ? twr[hd + jj] : MIRROR ? block_root<MLEN, true>(tw, (off + jj * ST) << s, p)
+                                                                    : tws[(jj * ST) << s];
       const u32 x = a[j], y = a[j + hd];
       if (!INV) {
         a[j] = add_mod(x, y, p);
@@ -103,7 +117,7 @@ __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const 
 // dependent product chains (at the tail the second group repeats the first
 // and is not stored).  The row kernels keep one group per iteration: there
 // the extra registers cost a wave per SIMD, which is worth more.
-template <int M, int S0, int RL, bool INV, bool COLS, bool HOIST>
+template <int M, int S0, int RL, bool INV, bool COLS, bool HOIST, bool MIRROR = false>
 __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const uint2* __restrict__ tw,
                                              const uint2 (&twr)[1 << RL], u32 p) {
   constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
@@ -155,7 +169,7 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
       u32* p0 = locate(g, off);
       u32 a[R];
       load(a, p0);
-      radix_group_t<RL, S0, ST, INV, HOIST>(a, off, tw, twr, p);
+      radix_group_t<RL, S0, ST, INV, HOIST, (1 << M), MIRROR>(a, off, tw, twr, p);
       store(a, p0);
     }
     return;
@@ -169,8 +183,8 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
     u32 a[R], b[R];
     load(a, p1);
     load(b, p2);
-    radix_group_t<RL, S0, ST, INV, HOIST>(a, off1, tw, twr, p);
-    radix_group_t<RL, S0, ST, INV, HOIST>(b, off2, tw, twr, p);
+    radix_group_t<RL, S0, ST, INV, HOIST, (1 << M), MIRROR>(a, off1, tw, twr, p);
+    radix_group_t<RL, S0, ST, INV, HOIST, (1 << M), MIRROR>(b, off2, tw, twr, p);
     store(a, p1);
     if (two) store(b, p2);
   }
@@ -183,18 +197,19 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
 // always when ST = 1, and in the row layout when blockDim is a multiple of
 // the groups per vector (then the lanes of a stage would otherwise read the
 // strided table w^((off + jj ST) 2^s) once per group, on few LDS banks).
-template <int M, int S0, int RL, bool INV, bool COLS>
+template <int M, int S0, int RL, bool INV, bool COLS, bool MIRROR = false>
 __device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* __restrict__ tw, u32 p) {
   constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
+  constexpr int MM = 1 << M;
   uint2 twr[R];
   if (ST == 1) {
 #pragma unroll
     for (int ss = 0; ss < RL; ++ss) {
       const int hd = R >> (ss + 1);
 #pragma unroll
-      for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = tw[jj << (S0 + ss)];
+      for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = block_root<MM, MIRROR>(tw, jj << (S0 + ss), p);
     }
-    round_groups<M, S0, RL, INV, COLS, false>(lds, nv, ldr, tw, twr, p);
+    round_groups<M, S0, RL, INV, COLS, false, MIRROR>(lds, nv, ldr, tw, twr, p);
     return;
   }
   if (!COLS && (blockDim.x & ((1u << LGPV) - 1)) == 0) {
@@ -203,27 +218,27 @@ __device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* 
     for (int ss = 0; ss < RL; ++ss) {
       const int hd = R >> (ss + 1);
 #pragma unroll
-      for (int jj = 0; jj < hd; ++jj) twr[hd + jj] = tw[(off + jj * ST) << (S0 + ss)];
+      for (int jj = 0; jj < hd; ++jj) twr[hd + jj] = block_root<MM, MIRROR>(tw, (off + jj * ST) << (S0 + ss), p);
     }
-    round_groups<M, S0, RL, INV, COLS, true>(lds, nv, ldr, tw, twr, p);
+    round_groups<M, S0, RL, INV, COLS, true, MIRROR>(lds, nv, ldr, tw, twr, p);
     return;
   }
-  round_groups<M, S0, RL, INV, COLS, false>(lds, nv, ldr, tw, twr, p);
+  round_groups<M, S0, RL, INV, COLS, false, MIRROR>(lds, nv, ldr, tw, twr, p);
 }
 
 // Rounds I.. of a length-2^M block NTT: ceil(M/3) rounds, the M stages spread
 // evenly (the first M mod nr rounds take one stage more); the inverse runs
 // the mirrored rounds in reverse order.
-template <int M, int I, bool INV, bool COLS>
+template <int M, int I, bool INV, bool COLS, bool MIRROR = false>
 __device__ __forceinline__ void rounds_t(u32* lds, int nv, int ldr, const uint2* tw, u32 p) {
   constexpr int NR = (M + 2) / 3, RB = NR ? M / NR : 0, RX = NR ? M % NR : 0;
   if constexpr (I < NR) {
     constexpr int IDX = INV ? NR - 1 - I : I;
     constexpr int S0 = IDX * RB + (IDX < RX ? IDX : RX);
     constexpr int RL = RB + (IDX < RX ? 1 : 0);
-    round_t<M, S0, RL, INV, COLS>(lds, nv, ldr, tw, p);
+    round_t<M, S0, RL, INV, COLS, MIRROR>(lds, nv, ldr, tw, p);
     __syncthreads();
-    rounds_t<M, I + 1, INV, COLS>(lds, nv, ldr, tw, p);
+    rounds_t<M, I + 1, INV, COLS, MIRROR>(lds, nv, ldr, tw, p);
   }
 }
 
@@ -920,9 +935,19 @@ __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u
 // run and the slice spectra of the next transform load while the current
 // one is transformed; more groups than one chunk holds recompute the
 // products from the registers per chunk.
+//
+// FWD: the forward row pass of the slice vectors is done here too, so X
+// holds only the forward column pass's output: the thread's values are
+// multiplied by the row twiddle, the rows (one per slice present) are
+// transformed in LDS by the forward block NTT, and each thread reads back
+// the NTT-domain values of its position.  The forward twiddle w_N^{j2 k1} is
+// c T(N2 - j2) with T(m) = w_N^{-m k1} (the inverse row twiddles, T(N2) for
+// j2 = 0) and c = w_N^{N2 k1}; the factor c is folded into the thread's
+// kernel-slice operands, so the products come out unscaled.  The forward
+// block roots are read from the inverse table (block_root<.., true>).
 constexpr int INV_ROW_THREADS = 512;
-template <int M2>
-__global__ void __launch_bounds__(INV_ROW_THREADS) k_inv_rows_reg(const u32* X, u32* G, const TDesc* td,
+template <int M2, bool FWD>
+__global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* X, u32* G, const TDesc* td,
                                                                   const TState* ts, const KernelDesc* kd,
                                                                   const int* tlist, int count, int K, int slot_lo,
                                                                   int slot_hi, NttGeom g, TwBlock tb, TwStep st,
@@ -938,10 +963,11 @@ __global__ void __launch_bounds__(INV_ROW_THREADS) k_inv_rows_reg(const u32* X, 
   const int nr = 1 << g.lrows_inv, SL = K * K;
   const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
-  uint2* tw = reinterpret_cast<uint2*>(smem);
-  u32* rtw = smem + N2;                                       // w_N^{-j2 k1} per tile element, then companions
-  u32* tile = smem + N2 + 2 * (nr << m2);
+  uint2* tw = reinterpret_cast<uint2*>(smem);                // inverse roots, entries 0 .. N2/2
+  u32* rtw = smem + N2 + 4;                                   // w_N^{-j2 k1} per tile element, then companions
+  u32* tile = rtw + 2 * (nr << m2);
   load_block_tw(tw, tb.inv[prime], m2);
+  if (threadIdx.x == 0) tw[N2 >> 1] = make_uint2(p - 1, shoup_companion(p - 1, p));   // w^(-N2/2) = -1
   const int i1_0 = (pair >> 1) << g.lrows_inv;
   for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x) {
     const uint2 r = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime],
@@ -955,6 +981,18 @@ __global__ void __launch_bounds__(INV_ROW_THREADS) k_inv_rows_reg(const u32* X, 
   WRegs<u32> wr;
   int wkd = -1;
   u32 xr[KT], xi[KT];
+  // forward row twiddle T(N2 - j2) of this position (the factor c is formed
+  // where the kernel-slice operands are loaded)
+  uint2 ftw = make_uint2(0, 0);
+  const u32 e_c = FWD ? ((u32)N2 * bitrev(i1_0 + (e_loc >> m2), g.m1)) & Nmask : 0u;   // N2 k1 mod N
+  if (FWD) {
+    __syncthreads();                                          // rtw complete
+    const int r = e_loc >> m2, j2 = e_loc & (N2 - 1);
+    if (j2)
+      ftw = make_uint2(rtw[r * N2 + N2 - j2], rtw[(nr << m2) + r * N2 + N2 - j2]);
+    else
+      ftw = step_root(e_c, st.lo[1][prime], st.hi[1][prime], p);
+  }
   int bn = b_lo;                                              // transform whose slices are in xr, xi
   while (bn < b_hi && ts[tlist[bn]].status) ++bn;
   if (bn < b_hi) {
@@ -968,12 +1006,45 @@ __global__ void __launch_bounds__(INV_ROW_THREADS) k_inv_rows_reg(const u32* X, 
     const KernelDesc& kk = kd[d.kd];
     if (d.kd != wkd) {
       load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], base + e_loc);
+      if (FWD) {                                              // fold c into the kernel-slice operands
+        const uint2 cfac = step_root(e_c, st.lo[0][prime], st.hi[0][prime], p);
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+          if (k < kk.kw[0]) {
+            wr.w0[k] = shoup_mul(wr.w0[k], cfac.x, cfac.y, p);
+            wr.q0[k] = companion_dev(wr.w0[k], p);
+          }
+          if (k < kk.kw[1]) {
+            wr.w1[k] = shoup_mul(wr.w1[k], cfac.x, cfac.y, p);
+            wr.q1[k] = companion_dev(wr.w1[k], p);
+          }
+        }
+      }
       wkd = d.kd;
     }
     const int gofs[4] = {0, s.ngroups[0], s.ngroups[0] + s.ngroups[1], s.ngroups[0] + s.ngroups[1] + s.ngroups[2]};
     const int gtot = gofs[3] + s.ngroups[3];
     int b2 = bn + 1;
     while (b2 < b_hi && ts[tlist[b2]].status) ++b2;
+    const int kx0 = s.kx[0], kx1 = s.kx[1];
+    if (FWD && kx0 + kx1 > 0) {
+      // forward rows: slice k of Re x' in tile vector k, of Im x' in kx0 + k
+      const int r = e_loc >> m2;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        if (k < kx0) lds_me[(k * nr) * ldr] = shoup_mul(xr[k], ftw.x, ftw.y, p);
+        if (k < kx1) lds_me[((kx0 + k) * nr) * ldr] = shoup_mul(xi[k], ftw.x, ftw.y, p);
+      }
+      (void)r;
+      __syncthreads();
+      rounds_t<M2, 0, false, false, true>(tile, (kx0 + kx1) * nr, ldr, tw, p);
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        if (k < kx0) xr[k] = lds_me[(k * nr) * ldr];
+        if (k < kx1) xi[k] = lds_me[((kx0 + k) * nr) * ldr];
+      }
+      __syncthreads();                                        // the tile is rewritten by the products
+    }
     for (int g0 = 0; g0 < gtot; g0 += gch) {
       const int g1 = min(gtot, g0 + gch);
       mac_regs(xr, xi, wr, s, kk.kw[0], kk.kw[1], gofs, g0, g1, lds_me, nr * ldr, p);
@@ -1394,7 +1465,7 @@ static size_t smem_rows(const NttGeom& g) {
 static size_t smem_single(int logN) { return ((size_t)(1 << logN) + row_ld(1 << logN)) * 4; }
 static size_t smem_inv_rows(const NttGeom& g) {
   const int gch = std::max(1, inv_vmax(g.m2) >> g.lrows_inv);
-  return ((size_t)(1 << g.m2) + ((size_t)2 << (g.m2 + g.lrows_inv)) +
+  return ((size_t)(1 << g.m2) + 4 + ((size_t)2 << (g.m2 + g.lrows_inv)) +
           (size_t)row_ld(1 << g.m2) * (size_t)(gch << g.lrows_inv)) * 4;
 }
 static size_t smem_inv_single(int logN) {
@@ -1518,9 +1589,17 @@ hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const 
   return launch_fwd_stage(X, td, ts, tlist, count, K, valid_full, vi_lo, vi_hi, g, tb, st, 0, s);
 }
 
+bool fused_rows_ok(const NttGeom& g, int K) {
+  // the forward rows of the 2K slice vectors must fit the group tile
+  const int gch = std::max(1, inv_vmax(g.m2) >> g.lrows_inv);
+  return g.two_pass() && K <= KT && (1 << (g.m2 + g.lrows_inv)) == INV_ROW_THREADS && 2 * K <= gch;
+}
+
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
-                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s, bool only_wide) {
+                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s, bool only_wide,
+                            bool fused_fwd) {
+  if (fused_fwd && !fused_rows_ok(g, K)) return hipErrorInvalidValue;   // also keeps the forward rows inside the tile
   if (count <= 0 || slot_hi <= slot_lo) return hipSuccess;
   hipError_t e = hipSuccess;
   if (!g.two_pass()) {
@@ -1547,9 +1626,10 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
     if (!with_m<M2_LO, M2_HI>(g.m2, [&](auto mc) {
           constexpr int M2 = decltype(mc)::value;
           if (reg) {
-            if ((e = big_lds((const void*)k_inv_rows_reg<M2>)) != hipSuccess) return;
-            hipLaunchKernelGGL(k_inv_rows_reg<M2>, dim3((unsigned)(pairs * runs)), dim3(INV_ROW_THREADS),
-                               smem_inv_rows(g), s, X, G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
+            auto* kfn = fused_fwd ? &k_inv_rows_reg<M2, true> : &k_inv_rows_reg<M2, false>;
+            if ((e = big_lds((const void*)kfn)) != hipSuccess) return;
+            hipLaunchKernelGGL(kfn, dim3((unsigned)(pairs * runs)), dim3(INV_ROW_THREADS), smem_inv_rows(g), s, X, G,
+                               td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
           } else {
             if ((e = big_lds((const void*)k_inv_rows<M2>)) != hipSuccess) return;
             hipLaunchKernelGGL(k_inv_rows<M2>, dim3((unsigned)(pairs * runs)), dim3(NTT_THREADS), smem_inv_rows(g), s,

@@ -124,6 +124,9 @@ struct fft_ozaki_plan_s {
   const void* last_in = nullptr;
   void* last_out = nullptr;
   int last_dir = -1;
+  // the batched form left X with the forward column pass only for the
+  // lengths whose forward row pass is folded into the inverse row pass
+  bool x_rows_pending = false;
 };
 
 namespace fo {
@@ -448,23 +451,28 @@ static int enqueue_batched(fft_ozaki_plan_s* p, const double2* in, double2* out,
     HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
   }
   HIPCHK(launch_groups(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, p->L, s));
-  for (auto& lc : p->classes)
-    HIPCHK(launch_fwd_pipeline(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K, lc.geom,
-                               p->tb, step_for(p, lc.logN), s));
+  for (auto& lc : p->classes) {
+    // forward NTTs; where the forward row pass is folded into the inverse
+    // row pass, only the column pass here
+    const int which = fused_rows_ok(lc.geom, K) ? 1 : 0;
+    HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K, lc.geom,
+                            p->tb, step_for(p, lc.logN), which, s));
+  }
   for (auto& lc : p->classes) {
     const int cnt = (int)lc.tids.size();
     if (fused_cols_ok(lc.geom)) {
-      // rows; fused columns + CRT + recombination; the unfused path for the
-      // transforms that need the wide accumulator
+      // rows (with the forward rows where possible); fused columns + CRT +
+      // recombination; the unfused path for the transforms that need the
+      // wide accumulator
       HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
-                              p->tb, step_for(p, lc.logN), 1, s));
+                              p->tb, step_for(p, lc.logN), 1, s, false, fused_rows_ok(lc.geom, K)));
       HIPCHK(launch_inv_cols_rec(p->G, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir, s));
       HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
                               p->tb, step_for(p, lc.logN), 2, s, true));
       HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
     } else {
-      HIPCHK(launch_inv_pipeline(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K,
-                                 lc.geom, p->tb, step_for(p, lc.logN), s));
+      HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
+                              p->tb, step_for(p, lc.logN), 0, s, false, fused_rows_ok(lc.geom, K)));
       HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
     }
   }
@@ -472,6 +480,8 @@ static int enqueue_batched(fft_ozaki_plan_s* p, const double2* in, double2* out,
 }
 
 static int run_batched(fft_ozaki_plan_s* p, const double2* in, double2* out, int dir, hipStream_t s) {
+  for (auto& lc : p->classes)
+    if (fused_rows_ok(lc.geom, p->K)) p->x_rows_pending = true;
   for (auto& g : p->graphs) {
     if (g.in == in && g.out == out && g.dir == dir) {
       HIPCHK(hipGraphLaunch(g.exec, s));
@@ -577,14 +587,18 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
       for (auto& lc : p->classes) {
         NttGeom g = lc.geom;
         if (stage != 3 && !g.two_pass()) continue;
+        const bool rows_folded = fused_rows_ok(g, K);   // the forward rows run inside stage 6
+        if (stage == 5 && rows_folded) continue;
+        const int which = stage == 3 ? (rows_folded ? 1 : 0) : stage - 3;
         HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K, g, p->tb,
-                                step_for(p, lc.logN), stage == 3 ? 0 : stage - 3, s));
+                                step_for(p, lc.logN), which, s));
       }
       return FFT_OZAKI_OK;
     case 6:
       for (auto& lc : p->classes)
         HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), K, 0,
-                                4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), 1, s));
+                                4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), 1, s, false,
+                                fused_rows_ok(lc.geom, K)));
       return FFT_OZAKI_OK;
     case 7:   // column pass (fused with CRT and recombination where the length allows)
       for (auto& lc : p->classes) {
@@ -795,6 +809,17 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
   HIPCHK(hipGetDevice(&cur));
   HIPCHK(hipSetDevice(plan->device));
   HIPCHK(hipDeviceSynchronize());
+  if (stage == 2 && plan->mode == FFT_OZAKI_MODE_BATCHED && plan->x_rows_pending) {
+    // the batched form folds the forward row pass into the inverse row pass;
+    // complete the stored slice spectra with it (once per execution)
+    for (auto& lc : plan->classes) {
+      if (!fused_rows_ok(lc.geom, K)) continue;
+      HIPCHK(launch_fwd_stage(plan->X, plan->d_td, plan->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K,
+                              lc.geom, plan->tb, step_for(plan, lc.logN), 2, nullptr));
+    }
+    HIPCHK(hipDeviceSynchronize());
+    plan->x_rows_pending = false;
+  }
   if (stage == 3 && plan->mode == FFT_OZAKI_MODE_BATCHED) {
     // the fused column pass keeps the group residues in registers; rebuild
     // them for this transform's length class from the stored row-pass output
