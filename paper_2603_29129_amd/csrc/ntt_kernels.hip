@@ -258,14 +258,16 @@ __device__ __forceinline__ void load_block_tw(uint2* tw, const uint2* __restrict
   for (int e = threadIdx.x; e < half; e += blockDim.x) tw[e] = src[e << (LOG2_BLOCK_MAX - m)];
 }
 
-// floor(v 2^32 / p) for v < p, exactly: a binary64 estimate (off by at most
-// one) corrected with an exact 64-bit remainder.
+// floor(v 2^32 / p) for v < p, exactly.  p is one of the two NTT primes, so
+// 2^32 / p is a constant picked by a uniform select.  The binary64 product
+// v (2^32 / p) is below 2^32 with an error under 2^-19, so its truncation is
+// off by at most one either way; one step on the sign and size of the exact
+// 64-bit remainder fixes it (a single select, no loop, no division).
 __device__ __forceinline__ u32 companion_dev(u32 v, u32 p) {
-  u32 c = (u32)((double)v * (4294967296.0 / (double)p));
-  long long r = (long long)(((u64)v << 32) - (u64)c * p);
-  while (r < 0) { --c; r += p; }
-  while (r >= (long long)p) { ++c; r -= p; }
-  return c;
+  const double rp = p == P0 ? 4294967296.0 / (double)P0 : 4294967296.0 / (double)P1;
+  const u32 c = (u32)((double)v * rp);
+  const long long r = (long long)(((u64)v << 32) - (u64)c * p);
+  return r < 0 ? c - 1 : (r >= (long long)p ? c + 1 : c);
 }
 
 // (w_N^e, companion) from the two-level step tables.
@@ -706,35 +708,41 @@ struct WRegs {
   V w0[KT], q0[KT], w1[KT], q1[KT];
 };
 __device__ __forceinline__ void ldv(uint2& v, const u32* ptr) { v = ld2(ptr); }
+__device__ __forceinline__ const u32* at_byte(const u32* base, u32 byte_off) {
+  return reinterpret_cast<const u32*>(reinterpret_cast<const char*>(base) + byte_off);
+}
 __device__ __forceinline__ void ldv(u32& v, const u32* ptr) { v = *ptr; }
 template <typename V>
 __device__ __forceinline__ void load_wregs(WRegs<V>& r, const u32* W, const u32* Wq, int K, int logN, int prime,
-                                           int kw0, int kw1, size_t e) {
+                                           int kw0, int kw1, u32 e) {
+  // uniform row pointers plus a 32-bit byte offset per lane (e < N <= 2^24)
   const size_t N = (size_t)1 << logN, sstride = 2 * N, part = (size_t)K * sstride;
-  const u32* wb = W + (size_t)prime * N + e;
-  const u32* qb = Wq + (size_t)prime * N + e;
+  const u32 eb = e * 4u;
+  const u32* wb = W + (size_t)prime * N;
+  const u32* qb = Wq + (size_t)prime * N;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     if (k < kw0) {
-      ldv(r.w0[k], wb + k * sstride);
-      ldv(r.q0[k], qb + k * sstride);
+      ldv(r.w0[k], at_byte(wb + k * sstride, eb));
+      ldv(r.q0[k], at_byte(qb + k * sstride, eb));
     }
     if (k < kw1) {
-      ldv(r.w1[k], wb + part + k * sstride);
-      ldv(r.q1[k], qb + part + k * sstride);
+      ldv(r.w1[k], at_byte(wb + part + k * sstride, eb));
+      ldv(r.q1[k], at_byte(qb + part + k * sstride, eb));
     }
   }
 }
 // Slice spectra of Re x' (xr) and Im x' (xi) at positions e, e+1.
 template <typename V>
 __device__ __forceinline__ void load_xregs(V (&xr)[KT], V (&xi)[KT], const u32* X, int K, int logN, int prime, int kx0,
-                                           int kx1, size_t e) {
+                                           int kx1, u32 e) {
   const size_t N = (size_t)1 << logN, sstride = 2 * N, part = (size_t)K * sstride;
-  const u32* xb = X + (size_t)prime * N + e;
+  const u32 eb = e * 4u;
+  const u32* xb = X + (size_t)prime * N;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
-    if (k < kx0) ldv(xr[k], xb + k * sstride);
-    if (k < kx1) ldv(xi[k], xb + part + k * sstride);
+    if (k < kx0) ldv(xr[k], at_byte(xb + k * sstride, eb));
+    if (k < kx1) ldv(xi[k], at_byte(xb + part + k * sstride, eb));
   }
 }
 // All four convolutions from register operands; groups [g0, g1) go to LDS.
@@ -977,6 +985,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   }
   const size_t base = (size_t)i1_0 << m2;
   const int e_loc = threadIdx.x;                              // this thread's position in the tile
+  const u32 pos = (u32)base + (u32)e_loc;                     // its position in the N2 x N1 matrix (< N)
   u32* lds_me = tile + (e_loc >> m2) * ldr + pad8(e_loc & (N2 - 1));
   WRegs<u32> wr;
   int wkd = -1;
@@ -997,7 +1006,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   while (bn < b_hi && ts[tlist[bn]].status) ++bn;
   if (bn < b_hi) {
     const int t = tlist[bn];
-    load_xregs(xr, xi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], base + e_loc);
+    load_xregs(xr, xi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], pos);
   }
   while (bn < b_hi) {
     const int t = tlist[bn];
@@ -1005,7 +1014,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
     const TState& s = ts[t];
     const KernelDesc& kk = kd[d.kd];
     if (d.kd != wkd) {
-      load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], base + e_loc);
+      load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], pos);
       if (FWD) {                                              // fold c into the kernel-slice operands
         const uint2 cfac = step_root(e_c, st.lo[0][prime], st.hi[0][prime], p);
 #pragma unroll
@@ -1050,7 +1059,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
       mac_regs(xr, xi, wr, s, kk.kw[0], kk.kw[1], gofs, g0, g1, lds_me, nr * ldr, p);
       if (g1 == gtot && b2 < b_hi) {                          // slices consumed: fetch the next transform's
         const int t2 = tlist[b2];
-        load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], base + e_loc);
+        load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], pos);
       }
       __syncthreads();
       block_ntt<M2, true, false>(tile, (g1 - g0) * nr, ldr, tw, p);
@@ -1059,7 +1068,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
     }
     if (gtot == 0 && b2 < b_hi) {                             // no groups (all-zero input): still advance
       const int t2 = tlist[b2];
-      load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], base + e_loc);
+      load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], pos);
     }
     bn = b2;
   }
@@ -1625,12 +1634,16 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
     const bool reg = K <= KT && (1 << (g.m2 + g.lrows_inv)) == INV_ROW_THREADS;
     if (!with_m<M2_LO, M2_HI>(g.m2, [&](auto mc) {
           constexpr int M2 = decltype(mc)::value;
-          if (reg) {
-            auto* kfn = fused_fwd ? &k_inv_rows_reg<M2, true> : &k_inv_rows_reg<M2, false>;
-            if ((e = big_lds((const void*)kfn)) != hipSuccess) return;
-            hipLaunchKernelGGL(kfn, dim3((unsigned)(pairs * runs)), dim3(INV_ROW_THREADS), smem_inv_rows(g), s, X, G,
-                               td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
-          } else {
+          if constexpr ((1 << M2) <= INV_ROW_THREADS) {   // the register form exists only for these lengths
+            if (reg) {
+              auto* kfn = fused_fwd ? &k_inv_rows_reg<M2, true> : &k_inv_rows_reg<M2, false>;
+              if ((e = big_lds((const void*)kfn)) != hipSuccess) return;
+              hipLaunchKernelGGL(kfn, dim3((unsigned)(pairs * runs)), dim3(INV_ROW_THREADS), smem_inv_rows(g), s, X,
+                                 G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
+              return;
+            }
+          }
+          {
             if ((e = big_lds((const void*)k_inv_rows<M2>)) != hipSuccess) return;
             hipLaunchKernelGGL(k_inv_rows<M2>, dim3((unsigned)(pairs * runs)), dim3(NTT_THREADS), smem_inv_rows(g), s,
                                X, G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
