@@ -84,12 +84,30 @@ enum {
   FFT_OZAKI_EMBED_AUTO = 1
 };
 
+/* NTT-domain accumulation (Alg. 8, Sec. 4.4).  The complex convolution
+ * x' (*) w* is four real convolutions: ReRe and ImIm give Re y' = ReRe - ImIm,
+ * ImRe and ReIm give Im y' = ImRe + ReIm.  PER_CONV: Alg. 8 for each real
+ * convolution on its own (a group holds at most L products of one
+ * convolution), 2 inverse NTTs per group.  COMPLEX: the products of the two
+ * convolutions of one output component are walked together, anti-diagonal by
+ * anti-diagonal, and products of equal scale share a group (the ImIm ones
+ * subtracted) up to acc_limit products, the most for which the signed sum
+ * stays within the CRT range: acc_limit n 4^alpha <= (p0 p1 - 1) / 2.  Both
+ * give bit-identical outputs (every output is the exact sum of all products,
+ * rounded once); COMPLEX needs fewer inverse NTTs wherever the scales of the
+ * real and imaginary parts agree. */
+enum {
+  FFT_OZAKI_ACCUM_PER_CONV = 0,
+  FFT_OZAKI_ACCUM_COMPLEX = 1
+};
+
 /* Plan options.  K: cap on slices per vector (Sec. 4.4), 1..8, default 3.
  * L: NTT-domain accumulation bound (Sec. 4.4, Alg. 8), >= 1, default 3.
  * mode: FFT_OZAKI_MODE_*, default batched.  autotune: 1 = time the NTT tile
  * shapes at plan time and keep the fastest (results are identical for every
  * shape); tune_cache: optional file path where tuned shapes are stored and
- * looked up (NULL = none).  embedding: FFT_OZAKI_EMBED_*, default AUTO. */
+ * looked up (NULL = none).  embedding: FFT_OZAKI_EMBED_*, default AUTO.
+ * accumulation: FFT_OZAKI_ACCUM_*, default COMPLEX. */
 typedef struct {
   int K;
   int L;
@@ -97,10 +115,11 @@ typedef struct {
   int autotune;
   const char* tune_cache;
   int embedding;
+  int accumulation;
 } fft_ozaki_options;
 
 /* Fills *opt with the defaults (K = 3, L = 3, batched, no autotune, AUTO
- * embedding). */
+ * embedding, COMPLEX accumulation). */
 int fft_ozaki_default_options(fft_ozaki_options* opt);
 
 /* Plan `batch` transforms of length n (uniform batch) with default options.
@@ -130,6 +149,7 @@ typedef struct {
   int K, L, mode, num_length_classes;
   int64_t workspace_bytes;         /* device memory held by the plan */
   int embedding;                   /* FFT_OZAKI_EMBED_* */
+  int accumulation;                /* FFT_OZAKI_ACCUM_* */
 } fft_ozaki_info;
 int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info);
 
@@ -145,7 +165,8 @@ typedef struct {
   int Ex[2][8];                    /* their exponents E = ceil(log2 max|r|) */
   int kw[2];                       /* slices of Re w*, Im w* */
   int Ew[2][8];
-  int ngroups[4];                  /* Alg. 8 groups of ReRe, ImIm, ImRe, ReIm */
+  int ngroups[2];                  /* accumulation groups of Re y', Im y' */
+  int acc_limit;                   /* products per group: L (PER_CONV) or the CRT-range bound (COMPLEX) */
   int forward_runtime, forward_offline, inverse;
   int ntt_log2N1;                  /* NTT-domain layout: see fft_ozaki_ntt */
 } fft_ozaki_transform_info;
@@ -155,7 +176,8 @@ int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_tr
  * execution to host memory (synchronises the device).  Stages:
  *   1  x' = x (.) w                          double2[n]
  *   2  forward NTTs of the x' slices         uint32[2][K][2][N]  (part, slice, prime; NTT-domain order)
- *   3  inverse NTT outputs per group         uint32[4*K*K][2][n4] (slot = conv*K*K + group, prime;
+ *   3  inverse NTT outputs per group         uint32[4*K*K][2][n4] (slot = component*2*K*K + group,
+ *                                            component 0 = Re y', 1 = Im y'; prime;
  *                                            n4 = n rounded up to a multiple of 4, first n valid; where
  *                                            the batched form fuses the column pass with the CRT these
  *                                            are rebuilt from the stored row-pass output by the call)

@@ -29,6 +29,8 @@ LIB_PATH = os.path.join(_PKG, "libfft_ozaki.so")
 FORWARD, INVERSE, ADJOINT = 0, 1, 2
 MODE_PLAIN, MODE_BATCHED = 0, 1
 EMBED_PADDED, EMBED_AUTO = 0, 1
+ACCUM_PER_CONV, ACCUM_COMPLEX = 0, 1
+_ACCUMS = {"per_conv": ACCUM_PER_CONV, "complex": ACCUM_COMPLEX}
 _MODES = {"plain": MODE_PLAIN, "batched": MODE_BATCHED}
 
 
@@ -38,19 +40,21 @@ class FftOzakiError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("L", ctypes.c_int), ("mode", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p), ("embedding", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p), ("embedding", ctypes.c_int),
+                ("accumulation", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64), ("total_length", ctypes.c_int64), ("K", ctypes.c_int),
                 ("L", ctypes.c_int), ("mode", ctypes.c_int), ("num_length_classes", ctypes.c_int),
-                ("workspace_bytes", ctypes.c_int64), ("embedding", ctypes.c_int)]
+                ("workspace_bytes", ctypes.c_int64), ("embedding", ctypes.c_int), ("accumulation", ctypes.c_int)]
 
 
 class _TInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("N", ctypes.c_int64), ("alpha", ctypes.c_int), ("status", ctypes.c_int),
                 ("kx", ctypes.c_int * 2), ("Ex", (ctypes.c_int * 8) * 2), ("kw", ctypes.c_int * 2),
-                ("Ew", (ctypes.c_int * 8) * 2), ("ngroups", ctypes.c_int * 4), ("forward_runtime", ctypes.c_int),
+                ("Ew", (ctypes.c_int * 8) * 2), ("ngroups", ctypes.c_int * 2), ("acc_limit", ctypes.c_int),
+                ("forward_runtime", ctypes.c_int),
                 ("forward_offline", ctypes.c_int), ("inverse", ctypes.c_int), ("ntt_log2N1", ctypes.c_int)]
 
 
@@ -110,11 +114,16 @@ class Plan:
 
     cyclic: for power-of-two lengths use the cyclic embedding N = n instead of
     padding to N = 2^ceil(log2(2n-1)) (Sec. 3.2); the outputs are the same
-    bit for bit, the NTTs half as long."""
+    bit for bit, the NTTs half as long.
+
+    accumulation: "complex" (default) walks the two real convolutions of each
+    output component together so that products of equal scale share an
+    inverse NTT (ReRe - ImIm, ImRe + ReIm); "per_conv" is Alg. 8 applied to
+    each real convolution on its own.  Outputs are bit-identical."""
 
     def __init__(self, n: int | None = None, batch: int = 1, *, lengths=None, K: int = 3, L: int = 3,
                  mode: str = "batched", autotune: bool = False, tune_cache: str | None = None,
-                 cyclic: bool = True):
+                 cyclic: bool = True, accumulation: str = "complex"):
         if lengths is None:
             if n is None:
                 raise ValueError("give n (and batch) or lengths")
@@ -122,7 +131,7 @@ class Plan:
         self.lengths = [int(v) for v in lengths]
         self.K, self.L, self.mode = K, L, mode
         opts = _Options(K, L, _MODES[mode], int(bool(autotune)), tune_cache.encode() if tune_cache else None,
-                        EMBED_AUTO if cyclic else EMBED_PADDED)
+                        EMBED_AUTO if cyclic else EMBED_PADDED, _ACCUMS[accumulation])
         arr = (ctypes.c_int64 * len(self.lengths))(*self.lengths)
         h = ctypes.c_void_p()
         _check(lib().fft_ozaki_plan_ex(ctypes.byref(h), arr, len(self.lengths), ctypes.byref(opts)))

@@ -105,11 +105,36 @@ struct KernelDesc {
   int Ew[2][KMAX];         // slice exponents
 };
 
-// One group of the Alg. 8 schedule: consecutive walk positions [start,
-// start+count) of one convolution, all with the same exponent e.
+// NTT-domain accumulation schedule.  The four real convolutions of the
+// complex product x' (*) w* are c = 0: Re x' Re w*, 1: Im x' Im w*,
+// 2: Im x' Re w*, 3: Re x' Im w*; output component tg (0: Re y', 1: Im y')
+// takes convolutions 2 tg (sign +) and 2 tg + 1 (sign - for tg = 0, + for
+// tg = 1), so each component is one walk over the slice pairs of its two
+// convolutions.  A group is a run of consecutive walk positions
+// [start, start + count) of one component with the same exponent e; its
+// residues are the signed NTT-domain sum of the members' products.
+//
+// Walk order (acc_mode of the transform):
+//   ACC_PER_CONV  Alg. 8 for each convolution on its own: convolution 2 tg
+//                 then 2 tg + 1, anti-diagonals s + t descending, s
+//                 ascending; a group closes at L products, at a change of
+//                 scale and at the change of convolution.
+//   ACC_COMPLEX   anti-diagonals descending, on each the pairs of
+//                 convolution 2 tg and then of 2 tg + 1 (s ascending); a
+//                 group closes at a change of scale or when it holds
+//                 acc_limit products, the most whose signed sum stays within
+//                 the CRT range: acc_limit n 4^alpha <= (p0 p1 - 1) / 2.
+//                 Re y' = ReRe - ImIm and Im y' = ImRe + ReIm are then formed
+//                 in the NTT domain wherever the scales agree.
+constexpr int ACC_PER_CONV = 0;
+constexpr int ACC_COMPLEX = 1;
+constexpr int MAX_MEMBERS = 2 * MAX_PAIRS;      // walk positions per output component
 struct Group {
   int start, count, e;
 };
+// Buffer slot of group gi, groups numbered across the components (the ng0
+// groups of Re y' first); each component owns 2 K^2 slots, its most groups.
+__host__ __device__ inline int group_slot(int gi, int ng0, int K) { return gi < ng0 ? gi : 2 * K * K + gi - ng0; }
 
 // Per-transform state written by the kernels during one execution.
 struct TState {
@@ -120,11 +145,11 @@ struct TState {
   int start[2];            // first slice still to (re)extract
   int active[2];           // 1 while the part still needs an extraction pass
   int status;
-  int npairs[4];
-  unsigned char ps[4][MAX_PAIRS], pt[4][MAX_PAIRS];   // walk order pairs (s, t)
-  int ngroups[4];
-  Group groups[4][MAX_PAIRS];
-  u64 gend[4];             // bit w set: walk pair w closes its group
+  int nmem[2];             // per output component: walk positions
+  unsigned char mc[2][MAX_MEMBERS], ms[2][MAX_MEMBERS], mt[2][MAX_MEMBERS];   // convolution, s, t
+  int ngroups[2];
+  Group groups[2][MAX_MEMBERS];
+  u64 gend[2][2];          // bit w of the 128: walk position w closes its group
   int emin[2];             // per output component: smallest group exponent
   int span[2];             // per output component: largest shift above emin
 };
@@ -132,6 +157,8 @@ struct TState {
 // Static per-transform descriptor.
 struct TDesc {
   int n, N, logN, alpha;
+  int acc_mode;            // ACC_PER_CONV or ACC_COMPLEX
+  int acc_limit;           // products per group: L (ACC_PER_CONV) or the CRT-range bound (ACC_COMPLEX)
   int kd;                  // index into the KernelDesc array
   int zs;                  // row stride of the compact outputs: n rounded up to a multiple of 4
   i64 io_off;              // element offset of this transform in in/out

@@ -621,14 +621,14 @@ __device__ __constant__ int c_conv_pb[4] = {0, 1, 0, 1};
 
 // NTT-domain multiply-accumulate (Alg. 8) at the two positions e, e+1 of
 // the NTT domain: every group sum
-//     Z_g = sum over the pairs (s, t) of g of X_pa^s (.) W_pb^t   (mod p).
-// Groups are numbered across the convolutions (group g of convolution c has
-// number gofs[c] + g); those in [g0, g1) are written to LDS at
-// lds0 + (number - g0) * rstride.  Pairs are visited in Alg. 8's walk order
-// (anti-diagonals s + t from the last down to 0, s ascending) and `gend`
-// marks the pair closing each group.  With at most KT slices per operand
-// the slices of the two positions are loaded once into registers and every
-// convolution is formed from them.
+//     Z_g = sum over the members (c, s, t) of g of +- X_pa(c)^s (.) W_pb(c)^t   (mod p),
+// with the minus sign for convolution 1 (Im x' Im w*, subtracted in Re y').
+// Groups are numbered across the output components (group g of component tg
+// has number gofs[tg] + g); those in [g0, g1) are written to LDS at
+// lds0 + (number - g0) * rstride.  Members are visited in the component's
+// walk order and `gend` marks the position closing each group.  With at
+// most KT slices per operand the slices of the two positions are loaded
+// once into registers and every product is formed from them.
 struct MacArgs {
   const u32* X;      // this transform's slice spectra, [part][k][prime][N]
   const u32* W;      // kernel spectra of its length, same layout
@@ -648,52 +648,98 @@ __device__ __forceinline__ void mac_acc(uint2& acc, const uint2& x, const uint2&
 __device__ __forceinline__ void mac_acc(u32& acc, u32 x, u32 w, u32 q, u32 p) {
   acc = add_mod(acc, shoup_mul(x, w, q, p), p);
 }
+__device__ __forceinline__ void mac_sub(uint2& acc, const uint2& x, const uint2& w, const uint2& q, u32 p) {
+  acc.x = sub_mod(acc.x, shoup_mul(x.x, w.x, q.x, p), p);
+  acc.y = sub_mod(acc.y, shoup_mul(x.y, w.y, q.y, p), p);
+}
+__device__ __forceinline__ void mac_sub(u32& acc, u32 x, u32 w, u32 q, u32 p) {
+  acc = sub_mod(acc, shoup_mul(x, w, q, p), p);
+}
 __device__ __forceinline__ void zero_acc(uint2& a) { a = make_uint2(0, 0); }
 __device__ __forceinline__ void zero_acc(u32& a) { a = 0; }
 __device__ __forceinline__ void put_acc(u32* ptr, const uint2& a) { *reinterpret_cast<uint2*>(ptr) = a; }
 __device__ __forceinline__ void put_acc(u32* ptr, u32 a) { *ptr = a; }
 
-// one convolution from register-held slices (kA, kB <= KT); V is u32 (one
-// position) or uint2 (two adjacent positions)
-template <typename V>
-__device__ __forceinline__ void walk_regs(const V (&xv)[KT], const V (&wv)[KT], const V (&qv)[KT], int kA, int kB,
-                                          u64 gend, int gbase, int g0, int g1, u32* lds0, int rstride, u32 p) {
+// Both convolutions of one output component from register-held slices
+// (all slice counts <= KT), in the component's walk order: convolution a
+// (sign +) and b (sign - when NEGB).  V is u32 (one position) or uint2 (two
+// adjacent positions).  Position w of the walk closes a group when bit w of
+// gend is set; group g (numbered from gbase) goes to LDS row g - g0 when it
+// lies in [g0, g1).
+template <bool NEGB, typename V>
+__device__ __forceinline__ void walk_step(V& acc, int h, const V& x, const V& w, const V& q, u32 p) {
+  if (NEGB && h == 1) mac_sub(acc, x, w, q, p);
+  else mac_acc(acc, x, w, q, p);
+}
+template <bool MERGED, bool NEGB, typename V>
+__device__ __forceinline__ void walk_target(const V (&xa)[KT], const V (&wa)[KT], const V (&qa)[KT], int kAa, int kBa,
+                                            const V (&xb)[KT], const V (&wb)[KT], const V (&qb)[KT], int kAb, int kBb,
+                                            u64 gend, int gbase, int g0, int g1, u32* lds0, int rstride, u32 p) {
   int w = 0, g = gbase;
   V acc;
   zero_acc(acc);
+  auto close = [&]() {
+    if ((gend >> w) & 1) {
+      if (g >= g0 && g < g1) put_acc(lds0 + (g - g0) * rstride, acc);
+      zero_acc(acc);
+      ++g;
+    }
+    ++w;
+  };
+  if constexpr (MERGED) {
 #pragma unroll
-  for (int d = 2 * KT - 2; d >= 0; --d) {
+    for (int d = 2 * KT - 2; d >= 0; --d) {
 #pragma unroll
-    for (int ss = (d - KT + 1 > 0 ? d - KT + 1 : 0); ss <= (KT - 1 < d ? KT - 1 : d); ++ss) {
-      const int tt = d - ss;
-      if (ss < kA && tt < kB) {
-        mac_acc(acc, xv[ss], wv[tt], qv[tt], p);
-        if ((gend >> w) & 1) {
-          if (g >= g0 && g < g1) put_acc(lds0 + (g - g0) * rstride, acc);
-          zero_acc(acc);
-          ++g;
+      for (int ss = (d - KT + 1 > 0 ? d - KT + 1 : 0); ss <= (KT - 1 < d ? KT - 1 : d); ++ss)
+        if (ss < kAa && d - ss < kBa) {
+          walk_step<NEGB>(acc, 0, xa[ss], wa[d - ss], qa[d - ss], p);
+          close();
         }
-        ++w;
-      }
+#pragma unroll
+      for (int ss = (d - KT + 1 > 0 ? d - KT + 1 : 0); ss <= (KT - 1 < d ? KT - 1 : d); ++ss)
+        if (ss < kAb && d - ss < kBb) {
+          walk_step<NEGB>(acc, 1, xb[ss], wb[d - ss], qb[d - ss], p);
+          close();
+        }
+    }
+  } else {
+#pragma unroll
+    for (int d = 2 * KT - 2; d >= 0; --d) {
+#pragma unroll
+      for (int ss = (d - KT + 1 > 0 ? d - KT + 1 : 0); ss <= (KT - 1 < d ? KT - 1 : d); ++ss)
+        if (ss < kAa && d - ss < kBa) {
+          walk_step<NEGB>(acc, 0, xa[ss], wa[d - ss], qa[d - ss], p);
+          close();
+        }
+    }
+#pragma unroll
+    for (int d = 2 * KT - 2; d >= 0; --d) {
+#pragma unroll
+      for (int ss = (d - KT + 1 > 0 ? d - KT + 1 : 0); ss <= (KT - 1 < d ? KT - 1 : d); ++ss)
+        if (ss < kAb && d - ss < kBb) {
+          walk_step<NEGB>(acc, 1, xb[ss], wb[d - ss], qb[d - ss], p);
+          close();
+        }
     }
   }
 }
 
-// one convolution with operands read per pair (any slice counts)
-__device__ void walk_mem(const MacArgs& a, const TState& s, int c, int gbase, int g0, int g1, size_t e, u32* lds0,
+// One output component with operands read per walk position (any slice
+// counts): the members (convolution, s, t) recorded by the schedule.
+__device__ void walk_mem(const MacArgs& a, const TState& s, int tg, int gbase, int g0, int g1, size_t e, u32* lds0,
                          int rstride) {
-  const int pa = c_conv_pa[c], pb = c_conv_pb[c];
   const size_t N = (size_t)1 << a.logN, sstride = 2 * N;
-  const u32* xb = a.X + (size_t)((pa * a.K) * 2 + a.prime) * N + e;
-  const u32* wb = a.W + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
-  const u32* qb = a.Wq + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
-  const u64 gend = s.gend[c];
   int g = gbase;
   uint2 acc = make_uint2(0, 0);
-  for (int w = 0; w < s.npairs[c]; ++w) {
-    const int ss = s.ps[c][w], tt = s.pt[c][w];
-    mac_acc(acc, ld2(xb + ss * sstride), ld2(wb + tt * sstride), ld2(qb + tt * sstride), a.p);
-    if ((gend >> w) & 1) {
+  for (int w = 0; w < s.nmem[tg]; ++w) {
+    const int c = s.mc[tg][w], ss = s.ms[tg][w], tt = s.mt[tg][w];
+    const int pa = c_conv_pa[c], pb = c_conv_pb[c];
+    const u32* xb = a.X + (size_t)((pa * a.K) * 2 + a.prime) * N + e;
+    const u32* wb = a.W + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
+    const u32* qb = a.Wq + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
+    if (c == 1) mac_sub(acc, ld2(xb + ss * sstride), ld2(wb + tt * sstride), ld2(qb + tt * sstride), a.p);
+    else mac_acc(acc, ld2(xb + ss * sstride), ld2(wb + tt * sstride), ld2(qb + tt * sstride), a.p);
+    if ((s.gend[tg][w >> 6] >> (w & 63)) & 1) {
       if (g >= g0 && g < g1) *reinterpret_cast<uint2*>(lds0 + (g - g0) * rstride) = acc;
       acc = make_uint2(0, 0);
       ++g;
@@ -745,28 +791,41 @@ __device__ __forceinline__ void load_xregs(V (&xr)[KT], V (&xi)[KT], const u32* 
     if (k < kx1) ldv(xi[k], at_byte(xb + part + k * sstride, eb));
   }
 }
-// All four convolutions from register operands; groups [g0, g1) go to LDS.
-// Re x' feeds ReRe (0) and ReIm (3); Im x' feeds ImIm (1) and ImRe (2).
+// Both output components from register operands (Re y': ReRe - ImIm, then
+// Im y': ImRe + ReIm); groups [g0, g1) go to LDS.
+template <bool MERGED, typename V>
+__device__ __forceinline__ void mac_regs_t(const V (&xr)[KT], const V (&xi)[KT], const V (&w0)[KT], const V (&q0)[KT],
+                                           const V (&w1)[KT], const V (&q1)[KT], const TState& s, int kw0, int kw1,
+                                           int tg_lo, int tg_hi, const int (&gofs)[2], int g0, int g1, u32* lds0,
+                                           int rstride, u32 p) {
+  const int kx0 = s.kx[0], kx1 = s.kx[1];
+  if (tg_lo <= 0)
+    walk_target<MERGED, true>(xr, w0, q0, kx0, kw0, xi, w1, q1, kx1, kw1, s.gend[0][0], gofs[0], g0, g1, lds0,
+                              rstride, p);
+  if (tg_hi >= 1)
+    walk_target<MERGED, false>(xi, w0, q0, kx1, kw0, xr, w1, q1, kx0, kw1, s.gend[1][0], gofs[1], g0, g1, lds0,
+                               rstride, p);
+}
 template <typename V>
 __device__ __forceinline__ void mac_regs(const V (&xr)[KT], const V (&xi)[KT], const WRegs<V>& r,
-                                         const TState& s, int kw0, int kw1, const int (&gofs)[4], int g0, int g1,
-                                         u32* lds0, int rstride, u32 p) {
-  const int kx0 = s.kx[0], kx1 = s.kx[1];
-  walk_regs(xr, r.w0, r.q0, kx0, kw0, s.gend[0], gofs[0], g0, g1, lds0, rstride, p);
-  walk_regs(xr, r.w1, r.q1, kx0, kw1, s.gend[3], gofs[3], g0, g1, lds0, rstride, p);
-  walk_regs(xi, r.w1, r.q1, kx1, kw1, s.gend[1], gofs[1], g0, g1, lds0, rstride, p);
-  walk_regs(xi, r.w0, r.q0, kx1, kw0, s.gend[2], gofs[2], g0, g1, lds0, rstride, p);
+                                         const TState& s, bool merged, int kw0, int kw1, const int (&gofs)[2], int g0,
+                                         int g1, u32* lds0, int rstride, u32 p) {
+  if (merged)
+    mac_regs_t<true>(xr, xi, r.w0, r.q0, r.w1, r.q1, s, kw0, kw1, 0, 1, gofs, g0, g1, lds0, rstride, p);
+  else
+    mac_regs_t<false>(xr, xi, r.w0, r.q0, r.w1, r.q1, s, kw0, kw1, 0, 1, gofs, g0, g1, lds0, rstride, p);
 }
 
-// Convolutions [c_lo, c_hi] at positions e, e+1 (e even).
-__device__ void mac_pair(const MacArgs& a, const TState& s, int c_lo, int c_hi, const int (&gofs)[4], int g0, int g1,
-                         size_t e, u32* lds0, int rstride) {
+// Output components [tg_lo, tg_hi] at positions e, e+1 (e even).
+__device__ void mac_pair(const MacArgs& a, const TState& s, bool merged, int tg_lo, int tg_hi, const int (&gofs)[2],
+                         int g0, int g1, size_t e, u32* lds0, int rstride) {
   const size_t N = (size_t)1 << a.logN, sstride = 2 * N;
   const int kx0 = s.kx[0], kx1 = s.kx[1];
   if (kx0 <= KT && kx1 <= KT && a.kw0 <= KT && a.kw1 <= KT) {
-    uint2 w0[KT], q0[KT], w1[KT], q1[KT], xv[KT];
+    uint2 w0[KT], q0[KT], w1[KT], q1[KT], xr[KT], xi[KT];
     const u32* wb = a.W + (size_t)a.prime * N + e;
     const u32* qb = a.Wq + (size_t)a.prime * N + e;
+    const u32* xb = a.X + (size_t)a.prime * N + e;
     const size_t part = (size_t)a.K * sstride;
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
@@ -778,44 +837,34 @@ __device__ void mac_pair(const MacArgs& a, const TState& s, int c_lo, int c_hi, 
         w1[k] = ld2(wb + part + k * sstride);
         q1[k] = ld2(qb + part + k * sstride);
       }
+      if (k < kx0) xr[k] = ld2(xb + k * sstride);
+      if (k < kx1) xi[k] = ld2(xb + part + k * sstride);
     }
-    const u32* xb = a.X + (size_t)a.prime * N + e;
-    // Re x' feeds ReRe (0) and ReIm (3); Im x' feeds ImIm (1) and ImRe (2)
-    if (c_lo <= 0 || c_hi >= 3) {
-#pragma unroll
-      for (int k = 0; k < KT; ++k)
-        if (k < kx0) xv[k] = ld2(xb + k * sstride);
-      if (c_lo <= 0 && 0 <= c_hi) walk_regs(xv, w0, q0, kx0, a.kw0, s.gend[0], gofs[0], g0, g1, lds0, rstride, a.p);
-      if (c_lo <= 3 && 3 <= c_hi) walk_regs(xv, w1, q1, kx0, a.kw1, s.gend[3], gofs[3], g0, g1, lds0, rstride, a.p);
-    }
-    if (c_lo <= 2 && c_hi >= 1) {
-#pragma unroll
-      for (int k = 0; k < KT; ++k)
-        if (k < kx1) xv[k] = ld2(xb + part + k * sstride);
-      if (c_lo <= 1 && 1 <= c_hi) walk_regs(xv, w1, q1, kx1, a.kw1, s.gend[1], gofs[1], g0, g1, lds0, rstride, a.p);
-      if (c_lo <= 2 && 2 <= c_hi) walk_regs(xv, w0, q0, kx1, a.kw0, s.gend[2], gofs[2], g0, g1, lds0, rstride, a.p);
-    }
+    if (merged)
+      mac_regs_t<true>(xr, xi, w0, q0, w1, q1, s, a.kw0, a.kw1, tg_lo, tg_hi, gofs, g0, g1, lds0, rstride, a.p);
+    else
+      mac_regs_t<false>(xr, xi, w0, q0, w1, q1, s, a.kw0, a.kw1, tg_lo, tg_hi, gofs, g0, g1, lds0, rstride, a.p);
     return;
   }
-  for (int c = c_lo; c <= c_hi; ++c) walk_mem(a, s, c, gofs[c], g0, g1, e, lds0, rstride);
+  for (int tg = tg_lo; tg <= tg_hi; ++tg) walk_mem(a, s, tg, gofs[tg], g0, g1, e, lds0, rstride);
 }
 
 // Scalar variant for vectors of length 1.
-__device__ void mac_single(const MacArgs& a, const TState& s, int c_lo, int c_hi, const int (&gofs)[4], int g0, int g1,
-                           size_t e, u32* lds0, int rstride) {
+__device__ void mac_single(const MacArgs& a, const TState& s, int tg_lo, int tg_hi, const int (&gofs)[2], int g0,
+                           int g1, size_t e, u32* lds0, int rstride) {
   const size_t N = (size_t)1 << a.logN;
-  for (int c = c_lo; c <= c_hi; ++c) {
-    const int pa = c_conv_pa[c], pb = c_conv_pb[c];
-    const u32* xb = a.X + (size_t)((pa * a.K) * 2 + a.prime) * N + e;
-    const u32* wb = a.W + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
-    const u32* qb = a.Wq + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
-    const u64 gend = s.gend[c];
+  for (int tg = tg_lo; tg <= tg_hi; ++tg) {
     u32 acc = 0;
-    int g = gofs[c];
-    for (int w = 0; w < s.npairs[c]; ++w) {
-      const int ss = s.ps[c][w], tt = s.pt[c][w];
-      acc = add_mod(acc, shoup_mul(xb[ss * 2 * N], wb[tt * 2 * N], qb[tt * 2 * N], a.p), a.p);
-      if ((gend >> w) & 1) {
+    int g = gofs[tg];
+    for (int w = 0; w < s.nmem[tg]; ++w) {
+      const int c = s.mc[tg][w], ss = s.ms[tg][w], tt = s.mt[tg][w];
+      const int pa = c_conv_pa[c], pb = c_conv_pb[c];
+      const u32* xb = a.X + (size_t)((pa * a.K) * 2 + a.prime) * N + e;
+      const u32* wb = a.W + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
+      const u32* qb = a.Wq + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
+      if (c == 1) mac_sub(acc, xb[ss * 2 * N], wb[tt * 2 * N], qb[tt * 2 * N], a.p);
+      else mac_acc(acc, xb[ss * 2 * N], wb[tt * 2 * N], qb[tt * 2 * N], a.p);
+      if ((s.gend[tg][w >> 6] >> (w & 63)) & 1) {
         if (g >= g0 && g < g1) lds0[(g - g0) * rstride] = acc;
         acc = 0;
         ++g;
@@ -848,7 +897,7 @@ __device__ __forceinline__ void decode_tile(int L, int pairs, int count, int& pa
 }
 
 // Single-workgroup inverse (N <= 4096): one workgroup per (transform, prime,
-// convolution).  For each chunk of groups: multiply-accumulate into LDS
+// output component).  For each chunk of groups: multiply-accumulate into LDS
 // rows, inverse block NTTs, first n outputs to the compact buffer.
 template <int M>
 __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z, const TDesc* td, const TState* ts,
@@ -857,35 +906,36 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
   constexpr int logN = M;
   extern __shared__ u32 smem[];
   int pair, b;
-  decode_tile(blockIdx.x, 8, count, pair, b);
+  decode_tile(blockIdx.x, 4, count, pair, b);
   const int t = tlist[b];
   const TDesc& d = td[t];
   const TState& s = ts[t];
   if (s.status) return;
-  const int c = pair >> 1, prime = pair & 1;
-  const int ng = s.ngroups[c];
+  const int tg = pair >> 1, prime = pair & 1;
+  const int ng = s.ngroups[tg];
   if (ng == 0) return;
   const u32 p = prime_of(prime);
   const KernelDesc& kk = kd[d.kd];
-  const int N = 1 << logN, ldr = row_ld(N), SL = K * K, vmax = inv_vmax(logN);
+  const int N = 1 << logN, ldr = row_ld(N), SL = 2 * K * K, vmax = inv_vmax(logN);
+  const bool merged = d.acc_mode == ACC_COMPLEX;
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + N;
   load_block_tw(tw, tb.inv[prime], logN);
   const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, logN, prime, p, kk.kw[0], kk.kw[1]};
-  const int gofs[4] = {0, 0, 0, 0};
+  const int gofs[2] = {0, 0};
   for (int g0 = 0; g0 < ng; g0 += vmax) {
     const int g1 = min(ng, g0 + vmax);
-    if (c * SL + g1 <= slot_lo || c * SL + g0 >= slot_hi) continue;
+    if (tg * SL + g1 <= slot_lo || tg * SL + g0 >= slot_hi) continue;
     if (logN >= 1) {
       for (int q = threadIdx.x; q < (N >> 1); q += blockDim.x)
-        mac_pair(ma, s, c, c, gofs, g0, g1, (size_t)q << 1, tile + pad8(q << 1), ldr);
+        mac_pair(ma, s, merged, tg, tg, gofs, g0, g1, (size_t)q << 1, tile + pad8(q << 1), ldr);
     } else {
-      for (int i = threadIdx.x; i < N; i += blockDim.x) mac_single(ma, s, c, c, gofs, g0, g1, i, tile + pad8(i), ldr);
+      for (int i = threadIdx.x; i < N; i += blockDim.x) mac_single(ma, s, tg, tg, gofs, g0, g1, i, tile + pad8(i), ldr);
     }
     __syncthreads();
     block_ntt<M, true, false>(tile, g1 - g0, ldr, tw, p);
     for (int gi = g0; gi < g1; ++gi) {
-      const int slot = c * SL + gi;
+      const int slot = tg * SL + gi;
       if (slot < slot_lo || slot >= slot_hi) continue;
       u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.zs;
       const u32* row = tile + (gi - g0) * ldr;
@@ -900,7 +950,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
 // when blockDim is a multiple of the quads per group row, a thread always
 // handles the same quad, so its four twiddles are loaded once.
 __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u32* tile, const u32* rtw,
-                                                 const int (&gofs)[4], int g0, int g1, int SL, int slot_lo,
+                                                 const int (&gofs)[2], int g0, int g1, int SL, int slot_lo,
                                                  int slot_hi, int prime, int logN, size_t base, int m2, int nr,
                                                  int ldr, u32 p) {
   const int quads = (nr << m2) >> 2, N2 = 1 << m2;
@@ -914,9 +964,7 @@ __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u
   }
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
     const int gi = g0 + it / quads, q = it % quads;
-    const int c = gi >= gofs[3] ? 3 : gi >= gofs[2] ? 2 : gi >= gofs[1] ? 1 : 0;
-    const int co = gi >= gofs[3] ? gofs[3] : gi >= gofs[2] ? gofs[2] : gi >= gofs[1] ? gofs[1] : 0;
-    const int slot = c * SL + gi - co;
+    const int slot = gi < gofs[1] ? gi : SL + gi - gofs[1];   // SL: slots per output component
     if (slot < slot_lo || slot >= slot_hi) continue;
     const int e = q << 2, r = e >> m2, j2 = e & (N2 - 1);
     uint4 v = *reinterpret_cast<const uint4*>(tile + ((gi - g0) * nr + r) * ldr + pad8(j2));
@@ -968,7 +1016,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   const int prime = pair & 1;
   const u32 p = prime_of(prime);
   constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
-  const int nr = 1 << g.lrows_inv, SL = K * K;
+  const int nr = 1 << g.lrows_inv, SL = 2 * K * K;           // slots per output component
   const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);                // inverse roots, entries 0 .. N2/2
@@ -1031,8 +1079,8 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
       }
       wkd = d.kd;
     }
-    const int gofs[4] = {0, s.ngroups[0], s.ngroups[0] + s.ngroups[1], s.ngroups[0] + s.ngroups[1] + s.ngroups[2]};
-    const int gtot = gofs[3] + s.ngroups[3];
+    const int gofs[2] = {0, s.ngroups[0]};
+    const int gtot = s.ngroups[0] + s.ngroups[1];
     int b2 = bn + 1;
     while (b2 < b_hi && ts[tlist[b2]].status) ++b2;
     const int kx0 = s.kx[0], kx1 = s.kx[1];
@@ -1056,7 +1104,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
     }
     for (int g0 = 0; g0 < gtot; g0 += gch) {
       const int g1 = min(gtot, g0 + gch);
-      mac_regs(xr, xi, wr, s, kk.kw[0], kk.kw[1], gofs, g0, g1, lds_me, nr * ldr, p);
+      mac_regs(xr, xi, wr, s, d.acc_mode == ACC_COMPLEX, kk.kw[0], kk.kw[1], gofs, g0, g1, lds_me, nr * ldr, p);
       if (g1 == gtot && b2 < b_hi) {                          // slices consumed: fetch the next transform's
         const int t2 = tlist[b2];
         load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], pos);
@@ -1089,7 +1137,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
   const int prime = pair & 1;
   const u32 p = prime_of(prime);
   constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
-  const int nr = 1 << g.lrows_inv, SL = K * K;
+  const int nr = 1 << g.lrows_inv, SL = 2 * K * K;           // slots per output component
   const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);
@@ -1111,15 +1159,15 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
     const TState& s = ts[t];
     if (s.status) continue;
     const KernelDesc& kk = kd[d.kd];
-    const int gofs[4] = {0, s.ngroups[0], s.ngroups[0] + s.ngroups[1], s.ngroups[0] + s.ngroups[1] + s.ngroups[2]};
-    const int gtot = gofs[3] + s.ngroups[3];
+    const int gofs[2] = {0, s.ngroups[0]};
+    const int gtot = s.ngroups[0] + s.ngroups[1];
     const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, g.logN, prime, p, kk.kw[0], kk.kw[1]};
     for (int g0 = 0; g0 < gtot; g0 += gch) {
       const int g1 = min(gtot, g0 + gch);
       // tile vector (number - g0) * nr + r holds row r of that group
       for (int q = threadIdx.x; q < 2 * quads; q += blockDim.x) {
         const int e = q << 1, r = e >> m2, i = e & (N2 - 1);
-        mac_pair(ma, s, 0, 3, gofs, g0, g1, base + e, tile + r * ldr + pad8(i), nr * ldr);
+        mac_pair(ma, s, d.acc_mode == ACC_COMPLEX, 0, 1, gofs, g0, g1, base + e, tile + r * ldr + pad8(i), nr * ldr);
       }
       __syncthreads();
       block_ntt<M2, true, false>(tile, (g1 - g0) * nr, ldr, tw, p);
@@ -1138,13 +1186,10 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
 constexpr int COL_PF = 8;        // 16-byte registers per thread staging the next tile (tile <= 16K words)
 
 struct ColVecs {                 // group vectors of one transform (numbering j = 2 gi + prime)
-  int gofs[4], SL, slot_lo, slot_hi, j_hi;
+  int ng0, SL, slot_lo, slot_hi, j_hi;   // ng0: groups of Re y'; SL: slots per output component
   __device__ __forceinline__ int slot_of(int j) const {
     const int gi = j >> 1;
-    // selects rather than an indexed lookup (keeps gofs in registers)
-    const int c = gi >= gofs[3] ? 3 : gi >= gofs[2] ? 2 : gi >= gofs[1] ? 1 : 0;
-    const int o = gi >= gofs[3] ? gofs[3] : gi >= gofs[2] ? gofs[2] : gi >= gofs[1] ? gofs[1] : 0;
-    return c * SL + gi - o;
+    return gi < ng0 ? gi : SL + gi - ng0;
   }
   // first vector >= j whose slot lies in [slot_lo, slot_hi), or j_hi
   __device__ __forceinline__ int next(int j) const {
@@ -1210,14 +1255,11 @@ __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, 
   if (s.status) return;
   if (only_wide && !span_wide(s, 0) && !span_wide(s, 1)) return;   // done by the fused pass
   ColVecs cv;
-  cv.gofs[0] = 0;
-  cv.gofs[1] = s.ngroups[0];
-  cv.gofs[2] = cv.gofs[1] + s.ngroups[1];
-  cv.gofs[3] = cv.gofs[2] + s.ngroups[2];
-  cv.SL = K * K;
+  cv.ng0 = s.ngroups[0];
+  cv.SL = 2 * K * K;
   cv.slot_lo = slot_lo;
   cv.slot_hi = slot_hi;
-  const int gtot = cv.gofs[3] + s.ngroups[3];
+  const int gtot = cv.ng0 + s.ngroups[1];
   const int j_lo = blockIdx.y * vpw;
   cv.j_hi = min(2 * gtot, j_lo + vpw);
   if (j_lo >= cv.j_hi) return;
@@ -1346,12 +1388,9 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, doub
   load_block_tw(tw0, tb.inv[0], M1);
   load_block_tw(tw1, tb.inv[1], M1);
   ColVecs cv;                                                 // group numbering (slot_of)
-  cv.gofs[0] = 0;
-  cv.gofs[1] = s.ngroups[0];
-  cv.gofs[2] = cv.gofs[1] + s.ngroups[1];
-  cv.gofs[3] = cv.gofs[2] + s.ngroups[2];
-  cv.SL = K * K;
-  const int V = cv.gofs[3] + s.ngroups[3];                    // groups; Re y' groups are [0, gofs[2])
+  cv.ng0 = s.ngroups[0];
+  cv.SL = 2 * K * K;
+  const int V = cv.ng0 + s.ngroups[1];                        // groups; Re y' groups are [0, ng0)
   const u32* gb = G + d.G_off;
   // this thread's quad of the tile: row i, columns c4 .. c4 + 3
   const int qi = threadIdx.x >> LQ, qc = (threadIdx.x & ((1 << LQ) - 1)) << 2;
@@ -1373,7 +1412,7 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, doub
   if (V > 0) fetch(0);
   __syncthreads();                                            // root tables
   for (int v = 0; v < V; ++v) {
-    if (v == cv.gofs[2] && v > 0) {                           // Re y' complete
+    if (v == cv.ng0 && v > 0) {                               // Re y' complete
 #pragma unroll
       for (int k = 0; k < REC_OUT; ++k) {
         u64 a64[W_FAST];
@@ -1389,20 +1428,17 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, doub
     __syncthreads();
     if (v + 1 < V) fetch(v + 1);
     rounds_dual<M1, 0>(tile0, tile1, LC, tw0, tw1);
-    const int c = v >= cv.gofs[3] ? 3 : v >= cv.gofs[2] ? 2 : v >= cv.gofs[1] ? 1 : 0;
-    const int gidx = v - (v >= cv.gofs[3] ? cv.gofs[3] : v >= cv.gofs[2] ? cv.gofs[2] : v >= cv.gofs[1] ? cv.gofs[1] : 0);
-    const int sh = s.groups[c][gidx].e - (c >= 2 ? s.emin[1] : s.emin[0]);
+    const int tg = v >= cv.ng0 ? 1 : 0;                       // the signs are applied in the NTT domain
+    const int sh = s.groups[tg][v - (tg ? cv.ng0 : 0)].e - s.emin[tg];
 #pragma unroll
     for (int k = 0; k < REC_OUT; ++k) {
       const int o = threadIdx.x + k * REC_THREADS;
-      i64 z = garner(tile0[o], tile1[o]);
-      if (c == 1) z = -z;                                     // Re y' = ReRe - ImIm
-      limb_add(acc[k], z, sh);
+      limb_add(acc[k], garner(tile0[o], tile1[o]), sh);
     }
     __syncthreads();
   }
   double pi[REC_OUT];
-  const bool has_im = V > cv.gofs[2];
+  const bool has_im = V > cv.ng0;
 #pragma unroll
   for (int k = 0; k < REC_OUT; ++k) {
     u64 a64[W_FAST];
@@ -1616,7 +1652,7 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
     if (!with_m<0, LOG2_BLOCK_MAX>(g.logN, [&](auto mc) {
           constexpr int M = decltype(mc)::value;
           if ((e = big_lds((const void*)k_inv_single<M>)) != hipSuccess) return;
-          hipLaunchKernelGGL(k_inv_single<M>, dim3(8 * count), dim3(NTT_THREADS), smem_inv_single(g.logN), s, X, Z, td,
+          hipLaunchKernelGGL(k_inv_single<M>, dim3(4 * count), dim3(NTT_THREADS), smem_inv_single(g.logN), s, X, Z, td,
                              ts, kd, tlist, count, K, slot_lo, slot_hi, tb);
         }))
       return hipErrorInvalidValue;

@@ -55,6 +55,17 @@ static int alpha_for(i64 n, int L) {
   return a;
 }
 
+// Products per group of the complex accumulation: the most c with
+// c n 4^alpha <= (p0 p1 - 1) / 2, so that the signed sum of c products, each
+// at most n 4^alpha in magnitude (n terms of two alpha-bit integers), is
+// recovered exactly by the symmetric CRT (Sec. 3.3, Sec. 4.4).  At least L
+// by the choice of alpha.
+static int acc_limit_for(i64 n, int alpha) {
+  const unsigned __int128 unit = (unsigned __int128)(u64)n << (2 * alpha);
+  const unsigned __int128 lim = (unsigned __int128)PP_HALF / unit;
+  return lim > (unsigned __int128)MAX_MEMBERS ? MAX_MEMBERS : (int)lim;
+}
+
 // Bluestein convolution length: N = 2^ceil(log2(2n - 1)) (Sec. 3.2), or
 // N = n for a power-of-two n with the cyclic embedding (Sec. 3.2).
 static int conv_log2(i64 n, bool cyclic) {
@@ -101,6 +112,7 @@ struct fft_ozaki_plan_s {
   int K = 3, L = 3, mode = FFT_OZAKI_MODE_BATCHED;
   int autotune = 0;
   bool cyclic = true;               // FFT_OZAKI_EMBED_AUTO
+  int accumulation = FFT_OZAKI_ACCUM_COMPLEX;
   std::string tune_cache;
   std::vector<fo::i64> lengths;
   fo::i64 total = 0;
@@ -379,6 +391,8 @@ static int build_plan(fft_ozaki_plan_s* p) {
     d.logN = conv_log2(n, p->cyclic);
     d.N = 1 << d.logN;
     d.alpha = alpha_for(n, p->L);
+    d.acc_mode = p->accumulation == FFT_OZAKI_ACCUM_COMPLEX ? ACC_COMPLEX : ACC_PER_CONV;
+    d.acc_limit = d.acc_mode == ACC_COMPLEX ? acc_limit_for(n, d.alpha) : p->L;
     d.kd = kidx[n];
     d.zs = (int)((n + 3) & ~(i64)3);
     d.io_off = io;
@@ -515,7 +529,7 @@ static int run_batched(fft_ozaki_plan_s* p, const double2* in, double2* out, int
 }
 
 static int run_plain(fft_ozaki_plan_s* p, const double2* in, double2* out, int dir, hipStream_t s) {
-  const int K = p->K, SL = K * K;
+  const int K = p->K, SL = 2 * K * K;   // slots per output component
   for (int t = 0; t < (int)p->td.size(); ++t) {
     const TDesc& d = p->td[t];
     const int* tl = p->d_tall + t;
@@ -547,9 +561,9 @@ static int run_plain(fft_ozaki_plan_s* p, const double2* in, double2* out, int d
             const int vi = (part * K + k) * 2 + prime;
             HIPCHK(launch_fwd_pipeline(p->X, p->d_td, p->d_ts, tl, 1, K, false, vi, vi + 1, g, p->tb, st, s));
           }
-      for (int c = 0; c < 4; ++c)
-        for (int gi = 0; gi < hs.ngroups[c]; ++gi) {
-          const int slot = c * SL + gi;
+      for (int tg = 0; tg < 2; ++tg)
+        for (int gi = 0; gi < hs.ngroups[tg]; ++gi) {
+          const int slot = tg * SL + gi;
           HIPCHK(launch_inv_pipeline(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, tl, 1, K, slot, slot + 1, g, p->tb,
                                      st, s));
         }
@@ -649,6 +663,7 @@ int fft_ozaki_default_options(fft_ozaki_options* opt) {
   opt->autotune = 0;
   opt->tune_cache = nullptr;
   opt->embedding = FFT_OZAKI_EMBED_AUTO;
+  opt->accumulation = FFT_OZAKI_ACCUM_COMPLEX;
   return FFT_OZAKI_OK;
 }
 
@@ -668,6 +683,8 @@ int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t co
   if (o.embedding != FFT_OZAKI_EMBED_PADDED && o.embedding != FFT_OZAKI_EMBED_AUTO)
     return fail(FFT_OZAKI_ERR_INVALID, "embedding must be 0 (padded) or 1 (auto)");
   const bool cyclic = o.embedding == FFT_OZAKI_EMBED_AUTO;
+  if (o.accumulation != FFT_OZAKI_ACCUM_PER_CONV && o.accumulation != FFT_OZAKI_ACCUM_COMPLEX)
+    return fail(FFT_OZAKI_ERR_INVALID, "accumulation must be 0 (per convolution) or 1 (complex)");
   i64 total = 0;
   for (int64_t i = 0; i < count; ++i) {
     const i64 n = lengths[i];
@@ -685,6 +702,7 @@ int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t co
   p->mode = o.mode;
   p->autotune = o.autotune;
   p->cyclic = cyclic;
+  p->accumulation = o.accumulation;
   p->tune_cache = o.tune_cache ? o.tune_cache : "";
   p->lengths.assign(lengths, lengths + count);
   int rc = build_plan(p);
@@ -743,6 +761,7 @@ int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info) {
   info->num_length_classes = (int)plan->classes.size();
   info->workspace_bytes = plan->bytes;
   info->embedding = plan->cyclic ? FFT_OZAKI_EMBED_AUTO : FFT_OZAKI_EMBED_PADDED;
+  info->accumulation = plan->accumulation;
   return FFT_OZAKI_OK;
 }
 
@@ -774,10 +793,11 @@ int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_tr
     fr += 2 * hs.kx[part];
     fo_ += 2 * kh.kw[part];
   }
-  for (int c = 0; c < 4; ++c) {
-    info->ngroups[c] = hs.ngroups[c];
-    iv += 2 * hs.ngroups[c];
+  for (int tg = 0; tg < 2; ++tg) {
+    info->ngroups[tg] = hs.ngroups[tg];
+    iv += 2 * hs.ngroups[tg];
   }
+  info->acc_limit = d.acc_limit;
   info->forward_runtime = fr;
   info->forward_offline = fo_;
   info->inverse = iv;

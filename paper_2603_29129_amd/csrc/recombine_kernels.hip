@@ -1,11 +1,13 @@
 // Garner CRT, exact recombination to binary64 and chirp postmultiply.
 //
-// For each output index k < n and each group g of the Alg. 8 schedule the two
-// inverse-NTT residues are combined by Garner's formula (Sec. 3.3)
+// For each output index k < n and each group g of the accumulation schedule
+// the two inverse-NTT residues are combined by Garner's formula (Sec. 3.3)
 //     z = z0 + ((z1 - z0) p0^{-1} mod p1) p0,  mapped to [-(P-1)/2, (P-1)/2],
-// which is the exact integer convolution value because |z| <= L n 4^alpha
-// <= (P-1)/2 (Sec. 4.2 / 4.4).  Each component of y' is then the exact sum
-//     Re y' = sum_{ReRe} z 2^e - sum_{ImIm} z 2^e,  Im y' = sum_{ImRe} + sum_{ReIm},
+// which is the exact signed integer value of the group's sum because at most
+// acc_limit products of magnitude <= n 4^alpha enter it and
+// acc_limit n 4^alpha <= (P-1)/2 (Sec. 4.2 / 4.4; the ImIm products enter Re y'
+// with a minus sign, already applied in the NTT domain).  Each component of
+// y' is then the exact sum of z 2^e over its groups,
 // accumulated in a two's-complement fixed-point integer (4 x 64 bits when the
 // exponents of the transform span <= 185 bits, 50 x 64 bits otherwise) and
 // rounded once to binary64, round to nearest even, subnormals and overflow
@@ -15,9 +17,6 @@
 
 namespace fo {
 
-__device__ __constant__ int c_tconv[2][2] = {{0, 1}, {2, 3}};
-__device__ __constant__ int c_tsign[2][2] = {{1, -1}, {1, 1}};
-
 // Both outputs j, j + 1 of one component (j even; the compact rows are
 // padded to a multiple of four, so j + 1 is always a readable position).
 __device__ void recombine_fast2(const u32* Zb, const TState& s, int tg, int SL, int zs, int j, double& r0,
@@ -26,22 +25,13 @@ __device__ void recombine_fast2(const u32* Zb, const TState& s, int tg, int SL, 
 #pragma unroll
   for (int k = 0; k < NL_FAST; ++k) a[k] = b[k] = 0;
   const int emin = s.emin[tg];
-  for (int ci = 0; ci < 2; ++ci) {
-    const int c = c_tconv[tg][ci];
-    const int sg = c_tsign[tg][ci];
-    for (int g = 0; g < s.ngroups[c]; ++g) {
-      const int slot = c * SL + g;
-      const uint2 v0 = *reinterpret_cast<const uint2*>(Zb + (size_t)(slot * 2) * zs + j);
-      const uint2 v1 = *reinterpret_cast<const uint2*>(Zb + (size_t)(slot * 2 + 1) * zs + j);
-      i64 za = garner(v0.x, v1.x), zb = garner(v0.y, v1.y);
-      if (sg < 0) {
-        za = -za;
-        zb = -zb;
-      }
-      const int sh = s.groups[c][g].e - emin;
-      limb_add(a, za, sh);
-      limb_add(b, zb, sh);
-    }
+  for (int g = 0; g < s.ngroups[tg]; ++g) {
+    const int slot = tg * SL + g;
+    const uint2 v0 = *reinterpret_cast<const uint2*>(Zb + (size_t)(slot * 2) * zs + j);
+    const uint2 v1 = *reinterpret_cast<const uint2*>(Zb + (size_t)(slot * 2 + 1) * zs + j);
+    const int sh = s.groups[tg][g].e - emin;
+    limb_add(a, garner(v0.x, v1.x), sh);
+    limb_add(b, garner(v0.y, v1.y), sh);
   }
   u64 a64[W_FAST], b64[W_FAST];
 #pragma unroll
@@ -59,17 +49,11 @@ __device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, 
 #pragma unroll
   for (int w = 0; w < W; ++w) acc[w] = 0;
   const int emin = s.emin[tg];
-  for (int ci = 0; ci < 2; ++ci) {
-    const int c = c_tconv[tg][ci];
-    const int sg = c_tsign[tg][ci];
-    for (int g = 0; g < s.ngroups[c]; ++g) {
-      const int slot = c * SL + g;
-      const u32 z0 = Zb[(size_t)(slot * 2) * zs + j];
-      const u32 z1 = Zb[(size_t)(slot * 2 + 1) * zs + j];
-      i64 z = garner(z0, z1);
-      if (sg < 0) z = -z;
-      acc_add<W>(acc, z, s.groups[c][g].e - emin);
-    }
+  for (int g = 0; g < s.ngroups[tg]; ++g) {
+    const int slot = tg * SL + g;
+    const u32 z0 = Zb[(size_t)(slot * 2) * zs + j];
+    const u32 z1 = Zb[(size_t)(slot * 2 + 1) * zs + j];
+    acc_add<W>(acc, garner(z0, z1), s.groups[tg][g].e - emin);
   }
   return acc_round<W>(acc, emin);
 }
@@ -86,7 +70,7 @@ __global__ void k_recombine(const u32* Z, double2* out, const TDesc* td, const T
   const bool wide0 = span_wide(s, 0), wide1 = span_wide(s, 1);
   if (WIDE != (!s.status && (wide0 || wide1))) return;
   const double2* ch = kd[d.kd].chirp;
-  const int SL = K * K;
+  const int SL = 2 * K * K;                                   // slots per output component
   const u32* Zb = Z + d.Z_off;
   if (!WIDE) {
     for (int j = 2 * (blockIdx.x * blockDim.x + threadIdx.x); j < d.n; j += 2 * gridDim.x * blockDim.x) {

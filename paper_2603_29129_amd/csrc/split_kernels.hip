@@ -403,15 +403,19 @@ hipError_t launch_split_check(const TDesc* td, TState* ts, const int* tlist, int
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 8 schedule for the four real convolutions of Sec. 4.5.  Walk the
-// anti-diagonals d = kA + kB - 2 .. 0, s = max(0, d - kB + 1) .. min(kA - 1, d),
-// t = d - s; a new group starts when L products are accumulated or the
-// product scale (here the exponent sum E_A^s + E_B^t) changes.
+// Alg. 8 schedule for the four real convolutions of Sec. 4.5.  Per
+// convolution the walk takes the anti-diagonals d = kA + kB - 2 .. 0,
+// s = max(0, d - kB + 1) .. min(kA - 1, d), t = d - s; a new group starts
+// when the group is full or the product scale (here the exponent sum
+// E_A^s + E_B^t) changes.  The two convolutions of one output component are
+// walked one after the other (the paper's schedule) or, anti-diagonal by
+// anti-diagonal, together, so that equal scales of the two share a group.
 
-__device__ __constant__ int c_pa[4] = {0, 1, 1, 0};
-__device__ __constant__ int c_pb[4] = {0, 1, 0, 1};
-__device__ __constant__ int c_tgt[4] = {0, 0, 1, 1};
+__device__ __constant__ int c_pa[4] = {0, 1, 1, 0};   // x' part of convolution c
+__device__ __constant__ int c_pb[4] = {0, 1, 0, 1};   // w* part of convolution c
 
+// The accumulation schedule of every transform (the walk orders and group
+// rules are described with TState).  One thread per transform.
 __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist, int count, int K, int L) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -429,55 +433,61 @@ __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
       E[part][k] = s.E[part][k];
       Ew[part][k] = kk.Ew[part][k];
     }
-  int emin[2] = {0x7FFFFFFF, 0x7FFFFFFF}, emax[2] = {-0x7FFFFFFF, -0x7FFFFFFF};
-  for (int c = 0; c < 4; ++c) {
-    const int pa = c_pa[c], pb = c_pb[c];
-    const int kA = s.status ? 0 : s.kx[pa], kB = kk.kw[pb];
-    int np = 0, ng = 0;
-    if (kA > 0 && kB > 0) {
-      int key = E[pa][kA - 1] + Ew[pb][kB - 1];
-      int cnt = 0, gstart = 0;
-      for (int dg = kA + kB - 2; dg >= 0; --dg) {
-        const int s0 = dg - kB + 1 > 0 ? dg - kB + 1 : 0;
-        const int s1 = kA - 1 < dg ? kA - 1 : dg;
-        for (int ss = s0; ss <= s1; ++ss) {
-          const int tt = dg - ss;
-          const int k2 = E[pa][ss] + Ew[pb][tt];
-          if (cnt >= L || k2 != key) {
-            s.groups[c][ng].start = gstart;
-            s.groups[c][ng].count = cnt;
-            s.groups[c][ng].e = key - 2 * d.alpha;
-            ++ng;
-            gstart = np;
-            cnt = 0;
-            key = k2;
-          }
-          s.ps[c][np] = (unsigned char)ss;
-          s.pt[c][np] = (unsigned char)tt;
-          ++np;
-          ++cnt;
-        }
-      }
-      s.groups[c][ng].start = gstart;
-      s.groups[c][ng].count = cnt;
-      s.groups[c][ng].e = key - 2 * d.alpha;
-      ++ng;
-    }
-    s.npairs[c] = np;
-    s.ngroups[c] = ng;
-    u64 gend = 0;
-    for (int g = 0; g < ng; ++g) gend |= 1ull << (s.groups[c][g].start + s.groups[c][g].count - 1);
-    s.gend[c] = gend;
-    const int tg = c_tgt[c];
-    for (int g = 0; g < ng; ++g) {
-      const int e = s.groups[c][g].e;
-      if (e < emin[tg]) emin[tg] = e;
-      if (e > emax[tg]) emax[tg] = e;
-    }
-  }
+  const bool merged = d.acc_mode == ACC_COMPLEX;
+  const int lim = merged ? d.acc_limit : L;
   for (int tg = 0; tg < 2; ++tg) {
-    s.emin[tg] = emin[tg] == 0x7FFFFFFF ? 0 : emin[tg];
-    s.span[tg] = emin[tg] == 0x7FFFFFFF ? 0 : emax[tg] - emin[tg];
+    int np = 0, ng = 0, cnt = 0, gstart = 0, key = 0, cur = -1;
+    int emin = 0x7FFFFFFF, emax = -0x7FFFFFFF;
+    auto close = [&]() {
+      s.groups[tg][ng].start = gstart;
+      s.groups[tg][ng].count = cnt;
+      s.groups[tg][ng].e = key - 2 * d.alpha;
+      emin = min(emin, key - 2 * d.alpha);
+      emax = max(emax, key - 2 * d.alpha);
+      ++ng;
+      gstart = np;
+      cnt = 0;
+    };
+    auto visit = [&](int c, int ss, int tt) {
+      const int k2 = E[c_pa[c]][ss] + Ew[c_pb[c]][tt];
+      if (cnt > 0 && (cnt >= lim || k2 != key || (!merged && c != cur))) close();
+      key = k2;
+      cur = c;
+      s.mc[tg][np] = (unsigned char)c;
+      s.ms[tg][np] = (unsigned char)ss;
+      s.mt[tg][np] = (unsigned char)tt;
+      ++np;
+      ++cnt;
+    };
+    int kA[2], kB[2];
+    for (int h = 0; h < 2; ++h) {
+      const int c = 2 * tg + h;
+      kA[h] = s.status ? 0 : s.kx[c_pa[c]];
+      kB[h] = kk.kw[c_pb[c]];
+      if (kA[h] == 0 || kB[h] == 0) kA[h] = kB[h] = 0;
+    }
+    if (merged) {
+      const int dmax = max(kA[0] + kB[0], kA[1] + kB[1]) - 2;
+      for (int dg = dmax; dg >= 0; --dg)
+        for (int h = 0; h < 2; ++h)
+          for (int ss = max(0, dg - kB[h] + 1); ss <= min(kA[h] - 1, dg); ++ss) visit(2 * tg + h, ss, dg - ss);
+    } else {
+      for (int h = 0; h < 2; ++h)
+        for (int dg = kA[h] + kB[h] - 2; dg >= 0; --dg)
+          for (int ss = max(0, dg - kB[h] + 1); ss <= min(kA[h] - 1, dg); ++ss) visit(2 * tg + h, ss, dg - ss);
+    }
+    if (cnt > 0) close();
+    s.nmem[tg] = np;
+    s.ngroups[tg] = ng;
+    u64 ge[2] = {0, 0};
+    for (int g = 0; g < ng; ++g) {
+      const int w = s.groups[tg][g].start + s.groups[tg][g].count - 1;
+      ge[w >> 6] |= 1ull << (w & 63);
+    }
+    s.gend[tg][0] = ge[0];
+    s.gend[tg][1] = ge[1];
+    s.emin[tg] = ng ? emin : 0;
+    s.span[tg] = ng ? emax - emin : 0;
   }
 }
 

@@ -2,7 +2,7 @@
 
 Every intermediate the library exposes is compared bit for bit with the
 oracle's (chirp, x', slice counts and exponents, forward NTTs of the slices,
-kernel NTTs, inverse-NTT residues of every Alg. 8 group); the binary64
+kernel NTTs, inverse-NTT residues of every accumulation group); the binary64
 outputs must agree within 2 ulp per component (the method is deterministic
 and the expected distance is 0)."""
 
@@ -14,6 +14,7 @@ from oracle import bluestein as bl
 from oracle import ntt as nt
 from oracle import ozaki as oz_or
 from oracle import reference as ref
+from tests.accum_schedule import acc_limit, component_schedule, group_residues
 from tests.gpu_helpers import max_ulp, ntt_domain_index
 
 pytestmark = pytest.mark.gpu
@@ -66,7 +67,17 @@ def check_stages(plan, idx, tr, kp, K):
         assert info["Ex"][part] == [E for _, E in tr["slices"][part]]
         assert info["kw"][part] == len(kp.slices[part])
         assert info["Ew"][part] == [E for _, E in kp.slices[part]]
-    assert info["ngroups"] == [len(g) for g in tr["groups"]]
+    # accumulation schedule: group counts per output component
+    complex_acc = plan.info()["accumulation"] == 1
+    limit = acc_limit(n, tr["alpha"]) if complex_acc else tr["L"]
+    assert info["acc_limit"] == limit
+    EX = [[E for _, E in tr["slices"][v]] for v in range(2)]
+    EW = [kp.exps(v) for v in range(2)]
+    sched = component_schedule(EX, EW, tr["L"], "complex" if complex_acc else "per_conv", limit)
+    if not complex_acc:       # the paper's schedule: the oracle's Alg. 8 groups, convolution by convolution
+        assert [[(s, t) for _, s, t in g] for g in sched[0] + sched[1]] == [
+            list(g) for c in range(4) for g in tr["groups"][c]]
+    assert info["ngroups"] == [len(g) for g in sched]
     logN = N.bit_length() - 1
     perm = ntt_domain_index(logN, info["ntt_log2N1"])
     # forward NTTs of the slices
@@ -82,13 +93,20 @@ def check_stages(plan, idx, tr, kp, K):
             for ip, p in enumerate(nt.PRIMES):
                 want = (kp.ntts[part][t][ip] * np.uint64(pow(N, -1, p))) % np.uint64(p)
                 assert np.array_equal(W[part, t, ip].astype(np.uint64), want[perm]), (part, t, ip)
-    # inverse NTT residues of every group
+    # inverse NTT residues of every group (signed sums: ImIm enters Re y' negated)
     Z = plan.debug_dump(3, idx).reshape(4 * K * K, 2, (n + 3) // 4 * 4)[:, :, :n]
-    for c in range(4):
-        for g, (z, _e) in enumerate(tr["group_z"][c]):
-            for ip, p in enumerate(nt.PRIMES):
-                want = np.mod(z, p).astype(np.uint64)
-                assert np.array_equal(Z[c * K * K + g, ip].astype(np.uint64), want), (c, g, ip)
+    for tg in range(2):
+        for g, grp in enumerate(sched[tg]):
+            slot = tg * 2 * K * K + g
+            if complex_acc:
+                want = group_residues(tr, kp, grp)
+            else:             # the oracle's group integers, convolution by convolution
+                c = grp[0][0]
+                j = sum(1 for h in sched[tg][:g] if h[0][0] == c)
+                z = tr["group_z"][c][j][0] * bl.CONVS[c][3]
+                want = [np.mod(z, p).astype(np.uint64) for p in nt.PRIMES]
+            for ip in range(2):
+                assert np.array_equal(Z[slot, ip].astype(np.uint64), want[ip]), (tg, g, ip)
 
 
 @pytest.mark.parametrize("cyclic", [True, False])

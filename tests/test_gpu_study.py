@@ -31,6 +31,8 @@ def test_study_counts_match_oracle(phi):
         if (K, L) == (3, 1):
             assert r["ntt_total"] == 96
         assert r["status"] == 0
+        assert r["complex_identical"], (K, L)
+        assert r["ntt_runtime_complex"] <= r["ntt_runtime"], (K, L)
 
 
 def test_study_error_levels():

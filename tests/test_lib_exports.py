@@ -56,9 +56,13 @@ def test_host_only_calls():
     assert L.fft_ozaki_plan_ex(ctypes.byref(h), arr, 1, ctypes.byref(opts)) == -1
     opts = oz._Options(3, 3, 1, 0, None, 2)                               # no such embedding
     assert L.fft_ozaki_plan_ex(ctypes.byref(h), arr, 1, ctypes.byref(opts)) == -1
+    opts = oz._Options(3, 3, 1, 0, None, 1, 2)                            # no such accumulation
+    assert L.fft_ozaki_plan_ex(ctypes.byref(h), arr, 1, ctypes.byref(opts)) == -1
+    assert b"accumulation" in L.fft_ozaki_last_error_message()
     d = oz._Options()
     assert L.fft_ozaki_default_options(ctypes.byref(d)) == 0
     assert (d.K, d.L, d.mode, d.autotune, d.embedding) == (3, 3, 1, 0, oz.EMBED_AUTO)
+    assert d.accumulation == oz.ACCUM_COMPLEX
     assert L.fft_ozaki_execute(None, None, None, 0, None) == -1
     assert L.fft_ozaki_destroy(None) == -1
     m = ctypes.c_int()
