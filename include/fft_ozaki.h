@@ -192,13 +192,14 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
  * schedule for all transforms of the plan, on `stream`, reusing the buffers
  * and the in/out pointers of the plan's last execution (they must still be
  * valid).  Stages: 1 split (premultiply, maxima, extraction passes),
- * 2 Alg. 8 group tables, 3 forward NTTs (both passes), 4 forward column
- * pass, 5 forward row pass, 6 inverse row pass with the fused NTT-domain
- * multiply-accumulate (for N <= 4096: the whole inverse), 7 inverse column
- * pass (for 2^13 <= N <= 2^18 fused with the CRT, recombination and
- * postmultiply), 8 CRT/recombination/postmultiply (for the fused lengths:
- * only the unfused fallback of transforms whose exponent span needs the wide
- * accumulator).  Stages 3-5 transform the slice
+ * 2 the accumulation schedule, 3 forward NTTs (both passes), 4 forward
+ * column pass, 5 forward row pass, 6 inverse row pass with the fused
+ * NTT-domain multiply-accumulate (for N <= 4096: the whole inverse),
+ * 7 inverse column pass (for 2^13 <= N <= 2^18 fused with the CRT,
+ * recombination and postmultiply; transforms whose exponent span needs the
+ * wide accumulator only get their columns, written to the compact buffer),
+ * 8 CRT/recombination/postmultiply (for the fused lengths: only those wide
+ * transforms).  Stages 3-5 transform the slice
  * buffers again in place, so intermediates read with fft_ozaki_debug_dump
  * afterwards are not those of the last execution.  Batched plans only. */
 int fft_ozaki_profile_stage(fft_ozaki_plan_t plan, int stage, int reps, void* stream);

@@ -61,13 +61,11 @@ hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, co
 hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K,
                             bool valid_full, int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb,
                             const TwStep& st, int which, hipStream_t s);
-// only_wide: the column pass skips transforms the fused column pass handles.
 // fused_fwd: the row pass also does the forward row NTTs of the slices (X
 // holds the forward column pass's output); needs fused_rows_ok.
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
-                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s, bool only_wide = false,
-                            bool fused_fwd = false);
+                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s, bool fused_fwd = false);
 // The register form of the inverse row pass applies (K <= 3, 512-position
 // row tiles) and its group tile holds the 2K forward slice rows, so the
 // forward row pass can be folded into it.
@@ -75,12 +73,12 @@ bool fused_rows_ok(const NttGeom& g, int K);
 
 // Fused inverse column pass + CRT + recombination + postmultiply for the
 // two-pass lengths with 2^7 <= N1 <= 2^9 (fused_cols_ok); transforms whose
-// exponent span needs the wide accumulator are left out (they take the
-// column pass with only_wide and launch_recombine_wide).
+// exponent span needs the wide accumulator only get their column pass,
+// written to the compact buffer Z for launch_recombine_wide.
 bool fused_cols_ok(const NttGeom& g);
-hipError_t launch_inv_cols_rec(const u32* G, double2* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                               const int* tlist, int count, int K, const NttGeom& g, const TwBlock& tb, int dir,
-                               hipStream_t s);
+hipError_t launch_inv_cols_rec(const u32* G, u32* Z, double2* out, const TDesc* td, const TState* ts,
+                               const KernelDesc* kd, const int* tlist, int count, int K, const NttGeom& g,
+                               const TwBlock& tb, int dir, hipStream_t s);
 
 // Kernel slices: multiply by N^{-1} and build Shoup companions.
 hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s);

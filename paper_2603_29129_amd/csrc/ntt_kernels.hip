@@ -138,13 +138,13 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
   };
   auto load = [&](u32 (&a)[R], const u32* p0) {
     if (!COLS && ST == 1 && R >= 4) {
+      // 8-byte accesses: a wave's 16-byte accesses to groups 8 words apart
+      // meet half the banks (measured slower)
 #pragma unroll
-      for (int j = 0; j < R; j += 4) {
-        const uint4 t = *reinterpret_cast<const uint4*>(p0 + j);
+      for (int j = 0; j < R; j += 2) {
+        const uint2 t = *reinterpret_cast<const uint2*>(p0 + j);
         a[j] = t.x;
         a[j + 1] = t.y;
-        a[j + 2] = t.z;
-        a[j + 3] = t.w;
       }
     } else {
 #pragma unroll
@@ -154,7 +154,7 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
   auto store = [&](const u32 (&a)[R], u32* p0) {
     if (!COLS && ST == 1 && R >= 4) {
 #pragma unroll
-      for (int j = 0; j < R; j += 4) *reinterpret_cast<uint4*>(p0 + j) = make_uint4(a[j], a[j + 1], a[j + 2], a[j + 3]);
+      for (int j = 0; j < R; j += 2) *reinterpret_cast<uint2*>(p0 + j) = make_uint2(a[j], a[j + 1]);
     } else {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
@@ -1020,8 +1020,9 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);                // inverse roots, entries 0 .. N2/2
-  u32* rtw = smem + N2 + 4;                                   // w_N^{-j2 k1} per tile element, then companions
-  u32* tile = rtw + 2 * (nr << m2);
+  u32* rtw = smem + N2 + 4;                                   // w_N^{-j2 k1} per tile element, then companions,
+                                                              // then T(N2) per row (nr values, nr companions)
+  u32* tile = rtw + 2 * (nr << m2) + 2 * nr;
   load_block_tw(tw, tb.inv[prime], m2);
   if (threadIdx.x == 0) tw[N2 >> 1] = make_uint2(p - 1, shoup_companion(p - 1, p));   // w^(-N2/2) = -1
   const int i1_0 = (pair >> 1) << g.lrows_inv;
@@ -1038,17 +1039,17 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   WRegs<u32> wr;
   int wkd = -1;
   u32 xr[KT], xi[KT];
-  // forward row twiddle T(N2 - j2) of this position (the factor c is formed
+  // forward row twiddle T(N2 - j2) of this position: an entry of rtw, or
+  // for j2 = 0 the row's T(N2), stored after rtw (the factor c is formed
   // where the kernel-slice operands are loaded)
-  uint2 ftw = make_uint2(0, 0);
   const u32 e_c = FWD ? ((u32)N2 * bitrev(i1_0 + (e_loc >> m2), g.m1)) & Nmask : 0u;   // N2 k1 mod N
   if (FWD) {
+    if ((e_loc & (N2 - 1)) == 0) {
+      const uint2 t = step_root(e_c, st.lo[1][prime], st.hi[1][prime], p);
+      rtw[2 * (nr << m2) + (e_loc >> m2)] = t.x;
+      rtw[2 * (nr << m2) + nr + (e_loc >> m2)] = t.y;
+    }
     __syncthreads();                                          // rtw complete
-    const int r = e_loc >> m2, j2 = e_loc & (N2 - 1);
-    if (j2)
-      ftw = make_uint2(rtw[r * N2 + N2 - j2], rtw[(nr << m2) + r * N2 + N2 - j2]);
-    else
-      ftw = step_root(e_c, st.lo[1][prime], st.hi[1][prime], p);
   }
   int bn = b_lo;                                              // transform whose slices are in xr, xi
   while (bn < b_hi && ts[tlist[bn]].status) ++bn;
@@ -1086,13 +1087,14 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
     const int kx0 = s.kx[0], kx1 = s.kx[1];
     if (FWD && kx0 + kx1 > 0) {
       // forward rows: slice k of Re x' in tile vector k, of Im x' in kx0 + k
-      const int r = e_loc >> m2;
+      const int r = e_loc >> m2, j2 = e_loc & (N2 - 1);
+      const int fi = j2 ? r * N2 + N2 - j2 : 2 * (nr << m2) + r;
+      const u32 fx = rtw[fi], fy = rtw[fi + (j2 ? (nr << m2) : nr)];
 #pragma unroll
       for (int k = 0; k < KT; ++k) {
-        if (k < kx0) lds_me[(k * nr) * ldr] = shoup_mul(xr[k], ftw.x, ftw.y, p);
-        if (k < kx1) lds_me[((kx0 + k) * nr) * ldr] = shoup_mul(xi[k], ftw.x, ftw.y, p);
+        if (k < kx0) lds_me[(k * nr) * ldr] = shoup_mul(xr[k], fx, fy, p);
+        if (k < kx1) lds_me[((kx0 + k) * nr) * ldr] = shoup_mul(xi[k], fx, fy, p);
       }
-      (void)r;
       __syncthreads();
       rounds_t<M2, 0, false, false, true>(tile, (kx0 + kx1) * nr, ldr, tw, p);
 #pragma unroll
@@ -1247,13 +1249,12 @@ __device__ __forceinline__ void put_col_tile(ColStage& b, u32* tile, int tot4, i
 template <int M1>
 __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, const TDesc* td, const TState* ts,
                                                           const int* tlist, int K, int slot_lo, int slot_hi,
-                                                          NttGeom g, TwBlock tb, int vpw, int only_wide) {
+                                                          NttGeom g, TwBlock tb, int vpw) {
   extern __shared__ u32 smem[];
   const int t = tlist[blockIdx.z];
   const TDesc& d = td[t];
   const TState& s = ts[t];
   if (s.status) return;
-  if (only_wide && !span_wide(s, 0) && !span_wide(s, 1)) return;   // done by the fused pass
   ColVecs cv;
   cv.ng0 = s.ngroups[0];
   cv.SL = 2 * K * K;
@@ -1358,7 +1359,7 @@ __device__ __forceinline__ void rounds_dual(u32* tile0, u32* tile1, int nv, cons
 
 constexpr int REC_THREADS = 1024, REC_OUT = 4;   // 4096-position tiles
 template <int M1>
-__global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, double2* out, const TDesc* td,
+__global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32* Z, double2* out, const TDesc* td,
                                                               const TState* ts, const KernelDesc* kd,
                                                               const int* tlist, int K, int m2, TwBlock tb, int dir) {
   constexpr int LC = 12 - M1, LQ = LC - 2, TILE = 1 << 12;
@@ -1367,7 +1368,10 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, doub
   const int t = tlist[blockIdx.z];
   const TDesc& d = td[t];
   const TState& s = ts[t];
-  if (!s.status && (span_wide(s, 0) || span_wide(s, 1))) return;    // unfused path
+  // a transform whose exponent span needs the wide accumulator only gets
+  // its column pass here: the residues go to the compact buffer Z for the
+  // wide recombination
+  const bool wide = !s.status && (span_wide(s, 0) || span_wide(s, 1));
   const int n = d.n, N2 = 1 << m2;
   const int j2_0 = col_tile(blockIdx.x, m2 - LC) << LC;
   const double2* ch = kd[d.kd].chirp;
@@ -1401,6 +1405,29 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, doub
     st0 = *reinterpret_cast<const u32x4*>(vec + goff);
     st1 = *reinterpret_cast<const u32x4*>(vec + ((size_t)1 << d.logN) + goff);
   };
+  if (wide) {
+    if (V > 0) fetch(0);
+    __syncthreads();                                          // root tables
+    for (int v = 0; v < V; ++v) {
+      *reinterpret_cast<u32x4*>(tile0 + (qi << LC) + qc) = st0;
+      *reinterpret_cast<u32x4*>(tile1 + (qi << LC) + qc) = st1;
+      __syncthreads();
+      if (v + 1 < V) fetch(v + 1);
+      rounds_dual<M1, 0>(tile0, tile1, LC, tw0, tw1);
+      u32* z0 = Z + d.Z_off + (size_t)(cv.slot_of(2 * v) * 2) * d.zs;
+#pragma unroll
+      for (int k = 0; k < REC_OUT; ++k) {
+        const int o = threadIdx.x + k * REC_THREADS;
+        const int j = (o >> LC) * N2 + j2_0 + (o & ((1 << LC) - 1));
+        if (j < n) {
+          z0[j] = tile0[o];
+          z0[d.zs + j] = tile1[o];
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
   u32 acc[REC_OUT][NL_FAST];
   double pr[REC_OUT];
 #pragma unroll
@@ -1510,7 +1537,7 @@ static size_t smem_rows(const NttGeom& g) {
 static size_t smem_single(int logN) { return ((size_t)(1 << logN) + row_ld(1 << logN)) * 4; }
 static size_t smem_inv_rows(const NttGeom& g) {
   const int gch = std::max(1, inv_vmax(g.m2) >> g.lrows_inv);
-  return ((size_t)(1 << g.m2) + 4 + ((size_t)2 << (g.m2 + g.lrows_inv)) +
+  return ((size_t)(1 << g.m2) + 4 + ((size_t)2 << (g.m2 + g.lrows_inv)) + ((size_t)2 << g.lrows_inv) +
           (size_t)row_ld(1 << g.m2) * (size_t)(gch << g.lrows_inv)) * 4;
 }
 static size_t smem_inv_single(int logN) {
@@ -1642,7 +1669,7 @@ bool fused_rows_ok(const NttGeom& g, int K) {
 
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
-                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s, bool only_wide,
+                            const TwBlock& tb, const TwStep& st, int which, hipStream_t s,
                             bool fused_fwd) {
   if (fused_fwd && !fused_rows_ok(g, K)) return hipErrorInvalidValue;   // also keeps the forward rows inside the tile
   if (count <= 0 || slot_hi <= slot_lo) return hipSuccess;
@@ -1697,7 +1724,7 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
           constexpr int M1 = decltype(mc)::value;
           if ((e = big_lds((const void*)k_inv_cols<M1>)) != hipSuccess) return;
           hipLaunchKernelGGL(k_inv_cols<M1>, grid, dim3(COL_THREADS), smem_inv_cols(g), s, G, Z, td, ts, tlist, K,
-                             slot_lo, slot_hi, g, tb, vpw, only_wide ? 1 : 0);
+                             slot_lo, slot_hi, g, tb, vpw);
         }))
       return hipErrorInvalidValue;
   }
@@ -1708,9 +1735,9 @@ bool fused_cols_ok(const NttGeom& g) {
   return g.two_pass() && g.m1 >= 7 && g.m1 <= 9 && 12 - g.m1 <= g.m2;
 }
 
-hipError_t launch_inv_cols_rec(const u32* G, double2* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                               const int* tlist, int count, int K, const NttGeom& g, const TwBlock& tb, int dir,
-                               hipStream_t s) {
+hipError_t launch_inv_cols_rec(const u32* G, u32* Z, double2* out, const TDesc* td, const TState* ts,
+                               const KernelDesc* kd, const int* tlist, int count, int K, const NttGeom& g,
+                               const TwBlock& tb, int dir, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (!fused_cols_ok(g)) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
@@ -1719,8 +1746,8 @@ hipError_t launch_inv_cols_rec(const u32* G, double2* out, const TDesc* td, cons
     constexpr int LC = 12 - M1;
     const size_t smem = ((size_t)(2 << M1) + 2 * 4096) * 4;
     if ((e = big_lds((const void*)k_inv_cols_rec<M1>)) != hipSuccess) return;
-    hipLaunchKernelGGL(k_inv_cols_rec<M1>, dim3(1u << (g.m2 - LC), 1, count), dim3(REC_THREADS), smem, s, G, out, td,
-                       ts, kd, tlist, K, g.m2, tb, dir);
+    hipLaunchKernelGGL(k_inv_cols_rec<M1>, dim3(1u << (g.m2 - LC), 1, count), dim3(REC_THREADS), smem, s, G, Z, out,
+                       td, ts, kd, tlist, K, g.m2, tb, dir);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -1728,7 +1755,7 @@ hipError_t launch_inv_cols_rec(const u32* G, double2* out, const TDesc* td, cons
 hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts,
                                const KernelDesc* kd, const int* tlist, int count, int K, int slot_lo, int slot_hi,
                                const NttGeom& g, const TwBlock& tb, const TwStep& st, hipStream_t s) {
-  return launch_inv_stage(X, G, Z, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, 0, s, false);
+  return launch_inv_stage(X, G, Z, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, 0, s);
 }
 
 hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s) {

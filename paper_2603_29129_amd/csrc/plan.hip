@@ -476,17 +476,16 @@ static int enqueue_batched(fft_ozaki_plan_s* p, const double2* in, double2* out,
     const int cnt = (int)lc.tids.size();
     if (fused_cols_ok(lc.geom)) {
       // rows (with the forward rows where possible); fused columns + CRT +
-      // recombination; the unfused path for the transforms that need the
-      // wide accumulator
+      // recombination (for transforms that need the wide accumulator: the
+      // columns to the compact buffer, then the wide recombination)
       HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
-                              p->tb, step_for(p, lc.logN), 1, s, false, fused_rows_ok(lc.geom, K)));
-      HIPCHK(launch_inv_cols_rec(p->G, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir, s));
-      HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
-                              p->tb, step_for(p, lc.logN), 2, s, true));
+                              p->tb, step_for(p, lc.logN), 1, s, fused_rows_ok(lc.geom, K)));
+      HIPCHK(launch_inv_cols_rec(p->G, p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir,
+                                 s));
       HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
     } else {
       HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
-                              p->tb, step_for(p, lc.logN), 0, s, false, fused_rows_ok(lc.geom, K)));
+                              p->tb, step_for(p, lc.logN), 0, s, fused_rows_ok(lc.geom, K)));
       HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
     }
   }
@@ -611,14 +610,14 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
     case 6:
       for (auto& lc : p->classes)
         HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), K, 0,
-                                4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), 1, s, false,
-                                fused_rows_ok(lc.geom, K)));
+                                4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), 1, s, fused_rows_ok(lc.geom, K)));
       return FFT_OZAKI_OK;
     case 7:   // column pass (fused with CRT and recombination where the length allows)
       for (auto& lc : p->classes) {
         const int cnt = (int)lc.tids.size();
         if (fused_cols_ok(lc.geom))
-          HIPCHK(launch_inv_cols_rec(p->G, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir, s));
+          HIPCHK(launch_inv_cols_rec(p->G, p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb,
+                                     dir, s));
         else
           HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K,
                                   lc.geom, p->tb, step_for(p, lc.logN), 2, s));
@@ -628,8 +627,6 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
       for (auto& lc : p->classes) {
         const int cnt = (int)lc.tids.size();
         if (fused_cols_ok(lc.geom)) {
-          HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K,
-                                  lc.geom, p->tb, step_for(p, lc.logN), 2, s, true));
           HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
         } else {
           HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));

@@ -411,8 +411,10 @@ hipError_t launch_split_check(const TDesc* td, TState* ts, const int* tlist, int
 // walked one after the other (the paper's schedule) or, anti-diagonal by
 // anti-diagonal, together, so that equal scales of the two share a group.
 
-__device__ __constant__ int c_pa[4] = {0, 1, 1, 0};   // x' part of convolution c
-__device__ __constant__ int c_pb[4] = {0, 1, 0, 1};   // w* part of convolution c
+// Convolution c uses x' part (c + 1) / 2 % 2 and w* part c % 2 (computed, not
+// looked up: the walk is one serial chain per transform).
+__device__ __forceinline__ int conv_pa(int c) { return ((c + 1) >> 1) & 1; }
+__device__ __forceinline__ int conv_pb(int c) { return c & 1; }
 
 // The accumulation schedule of every transform (the walk orders and group
 // rules are described with TState).  One thread per transform.
@@ -449,7 +451,7 @@ __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
       cnt = 0;
     };
     auto visit = [&](int c, int ss, int tt) {
-      const int k2 = E[c_pa[c]][ss] + Ew[c_pb[c]][tt];
+      const int k2 = E[conv_pa(c)][ss] + Ew[conv_pb(c)][tt];
       if (cnt > 0 && (cnt >= lim || k2 != key || (!merged && c != cur))) close();
       key = k2;
       cur = c;
@@ -462,8 +464,8 @@ __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
     int kA[2], kB[2];
     for (int h = 0; h < 2; ++h) {
       const int c = 2 * tg + h;
-      kA[h] = s.status ? 0 : s.kx[c_pa[c]];
-      kB[h] = kk.kw[c_pb[c]];
+      kA[h] = s.status ? 0 : s.kx[conv_pa(c)];
+      kB[h] = kk.kw[conv_pb(c)];
       if (kA[h] == 0 || kB[h] == 0) kA[h] = kB[h] = 0;
     }
     if (merged) {
