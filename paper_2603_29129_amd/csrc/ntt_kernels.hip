@@ -52,6 +52,17 @@ __host__ __device__ constexpr int pad8(int i) { return i + ((i >> 6) << 3); }
 // Row stride: rows shorter than 512 words are offset by four banks (a wave's
 // radix groups then span several rows); longer rows need no offset.
 __host__ __device__ constexpr int row_ld(int M) { return pad8(M) + (M >= 512 ? 0 : 4); }
+// Second row layout, for kernels that touch rows only element by element: one
+// pad word per eight, element i at pad9(i) = i + i / 8, rows M + M/8 apart.
+// The eight elements of a unit-stride radix group then start at 9q, so the
+// 64 lanes of a wave reach 64 different banks in every round (with pad8 the
+// unit-stride round puts eight lanes on each bank); 16-byte chunks stay
+// contiguous but not aligned.  PL selects the layout (8 or 9).
+__host__ __device__ constexpr int pad9(int i) { return i + (i >> 3); }
+template <int PL>
+__host__ __device__ constexpr int padl(int i) { return PL == 9 ? pad9(i) : pad8(i); }
+template <int PL>
+__host__ __device__ constexpr int row_ldl(int M) { return PL == 9 ? pad9(M) : row_ld(M); }
 
 constexpr int UNR = 4;           // 16-byte global loads in flight per thread
 constexpr int INV_TILE_ROWS = 20;        // group rows per inverse chunk: the 20 groups of K = L = 3 fit, 3 workgroups per CU
@@ -117,7 +128,7 @@ __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const 
 // dependent product chains (at the tail the second group repeats the first
 // and is not stored).  The row kernels keep one group per iteration: there
 // the extra registers cost a wave per SIMD, which is worth more.
-template <int M, int S0, int RL, bool INV, bool COLS, bool HOIST, bool MIRROR = false>
+template <int M, int S0, int RL, bool INV, bool COLS, bool HOIST, bool MIRROR = false, int PL = 8>
 __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const uint2* __restrict__ tw,
                                              const uint2 (&twr)[1 << RL], u32 p) {
   constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
@@ -134,10 +145,10 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
     }
     off = q & (ST - 1);
     const int base = ((q >> LST) << LBK) + off;
-    return COLS ? lds + (base << nv) + v : lds + v * ldr + pad8(base);
+    return COLS ? lds + (base << nv) + v : lds + v * ldr + padl<PL>(base);
   };
   auto load = [&](u32 (&a)[R], const u32* p0) {
-    if (!COLS && ST == 1 && R >= 4) {
+    if (!COLS && ST == 1 && R >= 4 && PL == 8) {
       // 8-byte accesses: a wave's 16-byte accesses to groups 8 words apart
       // meet half the banks (measured slower)
 #pragma unroll
@@ -148,18 +159,18 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < R; ++j) a[j] = COLS ? p0[j * sst] : p0[pad8(j * ST)];
+      for (int j = 0; j < R; ++j) a[j] = COLS ? p0[j * sst] : p0[padl<PL>(j * ST)];
     }
   };
   auto store = [&](const u32 (&a)[R], u32* p0) {
-    if (!COLS && ST == 1 && R >= 4) {
+    if (!COLS && ST == 1 && R >= 4 && PL == 8) {
 #pragma unroll
       for (int j = 0; j < R; j += 2) *reinterpret_cast<uint2*>(p0 + j) = make_uint2(a[j], a[j + 1]);
     } else {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         if (COLS) p0[j * sst] = a[j];
-        else p0[pad8(j * ST)] = a[j];
+        else p0[padl<PL>(j * ST)] = a[j];
       }
     }
   };
@@ -197,7 +208,7 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
 // always when ST = 1, and in the row layout when blockDim is a multiple of
 // the groups per vector (then the lanes of a stage would otherwise read the
 // strided table w^((off + jj ST) 2^s) once per group, on few LDS banks).
-template <int M, int S0, int RL, bool INV, bool COLS, bool MIRROR = false>
+template <int M, int S0, int RL, bool INV, bool COLS, bool MIRROR = false, int PL = 8>
 __device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* __restrict__ tw, u32 p) {
   constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
   constexpr int MM = 1 << M;
@@ -209,7 +220,7 @@ __device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* 
 #pragma unroll
       for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = block_root<MM, MIRROR>(tw, jj << (S0 + ss), p);
     }
-    round_groups<M, S0, RL, INV, COLS, false, MIRROR>(lds, nv, ldr, tw, twr, p);
+    round_groups<M, S0, RL, INV, COLS, false, MIRROR, PL>(lds, nv, ldr, tw, twr, p);
     return;
   }
   if (!COLS && (blockDim.x & ((1u << LGPV) - 1)) == 0) {
@@ -220,25 +231,25 @@ __device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* 
 #pragma unroll
       for (int jj = 0; jj < hd; ++jj) twr[hd + jj] = block_root<MM, MIRROR>(tw, (off + jj * ST) << (S0 + ss), p);
     }
-    round_groups<M, S0, RL, INV, COLS, true, MIRROR>(lds, nv, ldr, tw, twr, p);
+    round_groups<M, S0, RL, INV, COLS, true, MIRROR, PL>(lds, nv, ldr, tw, twr, p);
     return;
   }
-  round_groups<M, S0, RL, INV, COLS, false, MIRROR>(lds, nv, ldr, tw, twr, p);
+  round_groups<M, S0, RL, INV, COLS, false, MIRROR, PL>(lds, nv, ldr, tw, twr, p);
 }
 
 // Rounds I.. of a length-2^M block NTT: ceil(M/3) rounds, the M stages spread
 // evenly (the first M mod nr rounds take one stage more); the inverse runs
 // the mirrored rounds in reverse order.
-template <int M, int I, bool INV, bool COLS, bool MIRROR = false>
+template <int M, int I, bool INV, bool COLS, bool MIRROR = false, int PL = 8>
 __device__ __forceinline__ void rounds_t(u32* lds, int nv, int ldr, const uint2* tw, u32 p) {
   constexpr int NR = (M + 2) / 3, RB = NR ? M / NR : 0, RX = NR ? M % NR : 0;
   if constexpr (I < NR) {
     constexpr int IDX = INV ? NR - 1 - I : I;
     constexpr int S0 = IDX * RB + (IDX < RX ? IDX : RX);
     constexpr int RL = RB + (IDX < RX ? 1 : 0);
-    round_t<M, S0, RL, INV, COLS, MIRROR>(lds, nv, ldr, tw, p);
+    round_t<M, S0, RL, INV, COLS, MIRROR, PL>(lds, nv, ldr, tw, p);
     __syncthreads();
-    rounds_t<M, I + 1, INV, COLS, MIRROR>(lds, nv, ldr, tw, p);
+    rounds_t<M, I + 1, INV, COLS, MIRROR, PL>(lds, nv, ldr, tw, p);
   }
 }
 
@@ -246,9 +257,9 @@ __device__ __forceinline__ void rounds_t(u32* lds, int nv, int ldr, const uint2*
 // caller synchronises after filling the tile; this routine ends
 // synchronised.  Every kernel is instantiated per block length, so the
 // rounds inline with compile-time geometry.
-template <int M, bool INV, bool COLS>
+template <int M, bool INV, bool COLS, int PL = 8>
 __device__ __forceinline__ void block_ntt(u32* lds, int nv, int ldr, const uint2* tw, u32 p) {
-  rounds_t<M, 0, INV, COLS>(lds, nv, ldr, tw, p);
+  rounds_t<M, 0, INV, COLS, false, PL>(lds, nv, ldr, tw, p);
 }
 
 // Copies the roots w_M^e (e < M/2) of a length-2^m block NTT into LDS from the
@@ -949,6 +960,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
 // The (row, quad) items of all groups are spread over the whole workgroup;
 // when blockDim is a multiple of the quads per group row, a thread always
 // handles the same quad, so its four twiddles are loaded once.
+template <int PL = 8>
 __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u32* tile, const u32* rtw,
                                                  const int (&gofs)[2], int g0, int g1, int SL, int slot_lo,
                                                  int slot_hi, int prime, int logN, size_t base, int m2, int nr,
@@ -967,7 +979,13 @@ __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u
     const int slot = gi < gofs[1] ? gi : SL + gi - gofs[1];   // SL: slots per output component
     if (slot < slot_lo || slot >= slot_hi) continue;
     const int e = q << 2, r = e >> m2, j2 = e & (N2 - 1);
-    uint4 v = *reinterpret_cast<const uint4*>(tile + ((gi - g0) * nr + r) * ldr + pad8(j2));
+    uint4 v;
+    if constexpr (PL == 8) {
+      v = *reinterpret_cast<const uint4*>(tile + ((gi - g0) * nr + r) * ldr + pad8(j2));
+    } else {                                  // j2..j2+3 share one eight-element block: contiguous
+      const u32* q = tile + ((gi - g0) * nr + r) * ldr + padl<PL>(j2);
+      v = make_uint4(q[0], q[1], q[2], q[3]);
+    }
     if (!fixed) {
       w = *reinterpret_cast<const uint4*>(rtw + e);
       wq = *reinterpret_cast<const uint4*>(rtw + (nr << m2) + e);
@@ -1015,7 +1033,8 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   const int b_lo = run * tpw, b_hi = min(count, b_lo + tpw);
   const int prime = pair & 1;
   const u32 p = prime_of(prime);
-  constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
+  constexpr int PL = 9;                                       // row layout pad9: conflict-free rounds
+  constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ldl<PL>(N2);
   const int nr = 1 << g.lrows_inv, SL = 2 * K * K;           // slots per output component
   const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
@@ -1035,7 +1054,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   const size_t base = (size_t)i1_0 << m2;
   const int e_loc = threadIdx.x;                              // this thread's position in the tile
   const u32 pos = (u32)base + (u32)e_loc;                     // its position in the N2 x N1 matrix (< N)
-  u32* lds_me = tile + (e_loc >> m2) * ldr + pad8(e_loc & (N2 - 1));
+  u32* lds_me = tile + (e_loc >> m2) * ldr + padl<PL>(e_loc & (N2 - 1));
   WRegs<u32> wr;
   int wkd = -1;
   u32 xr[KT], xi[KT];
@@ -1096,7 +1115,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
         if (k < kx1) lds_me[((kx0 + k) * nr) * ldr] = shoup_mul(xi[k], fx, fy, p);
       }
       __syncthreads();
-      rounds_t<M2, 0, false, false, true>(tile, (kx0 + kx1) * nr, ldr, tw, p);
+      rounds_t<M2, 0, false, false, true, PL>(tile, (kx0 + kx1) * nr, ldr, tw, p);
 #pragma unroll
       for (int k = 0; k < KT; ++k) {
         if (k < kx0) xr[k] = lds_me[(k * nr) * ldr];
@@ -1112,8 +1131,8 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
         load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], pos);
       }
       __syncthreads();
-      block_ntt<M2, true, false>(tile, (g1 - g0) * nr, ldr, tw, p);
-      store_group_rows(G, d, tile, rtw, gofs, g0, g1, SL, slot_lo, slot_hi, prime, g.logN, base, m2, nr, ldr, p);
+      block_ntt<M2, true, false, PL>(tile, (g1 - g0) * nr, ldr, tw, p);
+      store_group_rows<PL>(G, d, tile, rtw, gofs, g0, g1, SL, slot_lo, slot_hi, prime, g.logN, base, m2, nr, ldr, p);
       __syncthreads();
     }
     if (gtot == 0 && b2 < b_hi) {                             // no groups (all-zero input): still advance
