@@ -15,7 +15,9 @@ give the same bits.
 Prints one JSON line.  Besides the headline (batched form, HIP graph replay)
 it reports the plain form on the same input, the relative l2 error against
 a long-double DFT, per-stage device times, the roofline of the dominant
-kernel and the CPU oracle timed on a bounded sample.
+kernel, the binary32 target precision (complex64 in and out, K = 2) on the
+same input rounded to binary32, and the CPU oracle timed on a bounded
+sample.
 """
 
 import argparse
@@ -262,6 +264,30 @@ def main():
     del out_pad
     print(f"# padded embedding: {ms_pad:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # binary32 target precision (complex64 in and out, K = 2) on the same
+    # input rounded to binary32; its error against the long-double DFT of
+    # that input and the error of the exact DFT rounded to binary32
+    x32 = x.astype(np.complex64)
+    x32d = torch.from_numpy(x32).cuda()
+    out32 = torch.empty_like(x32d)
+    plan32 = oz.Plan(n, B, mode="batched", precision="fp32")
+    for _ in range(args.warmup):
+        plan32.forward(x32d, out32)
+    torch.cuda.synchronize()
+    ms32 = time_events(torch, lambda k: [plan32.forward(x32d, out32) for _ in range(k)], args.steps)
+    i32 = plan32.transform_info(0)
+    ref32 = np.fft.fft(x32[0].astype(np.clongdouble))
+    rel32 = lambda v: float(np.sqrt(np.sum(np.abs(np.asarray(v).astype(np.clongdouble) - ref32) ** 2))
+                            / np.sqrt(np.sum(np.abs(ref32) ** 2)))
+    binary32 = {"K": plan32.K, "ms_per_step": round(ms32, 4), "value": round(flops / (ms32 * 1e-3) / 1e9, 2),
+                "rel_l2_error": rel32(out32[0].cpu().numpy()),
+                "rel_l2_error_of_rounded_exact_dft": rel32(ref32.astype(np.complex128).astype(np.complex64)),
+                "ntt_counts": {"forward_runtime": i32["forward_runtime"], "inverse": i32["inverse"],
+                               "forward_offline": i32["forward_offline"]}}
+    plan32.close()
+    del x32d, out32
+    print(f"# binary32 target (K=2): {ms32:.3f} ms/step", file=sys.stderr, flush=True)
+
     y = out.cpu().numpy()
     infos = [plan.transform_info(b) for b in range(B)]
     rel, maxrel = longdouble_errors(np, y[0], x[0])
@@ -347,6 +373,7 @@ def main():
                    "embedding": "cyclic N=n for power-of-two n (Sec. 3.2)" if infos[0]["N"] == n else "padded",
                    "parallelism": "single GPU"},
         "padded_embedding": padded,
+        "binary32_target": binary32,
         "rel_l2_error": rel,
         "max_rel_error": maxrel,
         "ntt_counts": {"forward_runtime": counts["forward_runtime"], "inverse": counts["inverse"],

@@ -24,8 +24,9 @@
  *    fft_ozaki_last_error_message() gives the detail of the last failure on
  *    the calling thread.
  *  * Complex data are arrays of interleaved binary64 pairs (re, im), i.e.
- *    double2 / complex128, 16-byte aligned, in DEVICE memory of the device
- *    that was current when the plan was created.  Transform i occupies
+ *    double2 / complex128, 16-byte aligned (for an FFT_OZAKI_PREC_FP32
+ *    plan: binary32 pairs, complex64, 8-byte aligned), in DEVICE memory of
+ *    the device that was current when the plan was created.  Transform i occupies
  *    elements [off_i, off_i + n_i) where off_i is the sum of the preceding
  *    lengths; a uniform batch is therefore a row-major [batch][n] array.
  *    in == out is allowed.
@@ -101,13 +102,25 @@ enum {
   FFT_OZAKI_ACCUM_COMPLEX = 1
 };
 
+/* Target precision (the method reaches a precision through the number of
+ * splits, Sec. 6).  FP64: in / out are complex128 (interleaved binary64).
+ * FP32: in / out are complex64; the input is widened exactly to binary64,
+ * the transform runs as for FP64 with the plan's K, and each output
+ * component is the binary64 result rounded once to binary32 (nearest even).
+ * K = 2 (about 40 bits per part) suffices for binary32 targets. */
+enum {
+  FFT_OZAKI_PREC_FP64 = 0,
+  FFT_OZAKI_PREC_FP32 = 1
+};
+
 /* Plan options.  K: cap on slices per vector (Sec. 4.4), 1..8, default 3.
  * L: NTT-domain accumulation bound (Sec. 4.4, Alg. 8), >= 1, default 3.
  * mode: FFT_OZAKI_MODE_*, default batched.  autotune: 1 = time the NTT tile
  * shapes at plan time and keep the fastest (results are identical for every
  * shape); tune_cache: optional file path where tuned shapes are stored and
  * looked up (NULL = none).  embedding: FFT_OZAKI_EMBED_*, default AUTO.
- * accumulation: FFT_OZAKI_ACCUM_*, default COMPLEX. */
+ * accumulation: FFT_OZAKI_ACCUM_*, default COMPLEX.  precision:
+ * FFT_OZAKI_PREC_*, default FP64. */
 typedef struct {
   int K;
   int L;
@@ -116,10 +129,11 @@ typedef struct {
   const char* tune_cache;
   int embedding;
   int accumulation;
+  int precision;
 } fft_ozaki_options;
 
 /* Fills *opt with the defaults (K = 3, L = 3, batched, no autotune, AUTO
- * embedding, COMPLEX accumulation). */
+ * embedding, COMPLEX accumulation, FP64). */
 int fft_ozaki_default_options(fft_ozaki_options* opt);
 
 /* Plan `batch` transforms of length n (uniform batch) with default options.
@@ -150,6 +164,7 @@ typedef struct {
   int64_t workspace_bytes;         /* device memory held by the plan */
   int embedding;                   /* FFT_OZAKI_EMBED_* */
   int accumulation;                /* FFT_OZAKI_ACCUM_* */
+  int precision;                   /* FFT_OZAKI_PREC_* */
 } fft_ozaki_info;
 int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info);
 

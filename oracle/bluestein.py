@@ -35,6 +35,11 @@ Pipeline for y = DFT(x), x in (F64 + i F64)^n, parameters (K, L):
 
 Inverse: DFT^{-1}(y) = conj(DFT(conj y)) / n, componentwise division
 (Sec. 3.2, Eq. idft).  Adjoint: DFT^H(g) = conj(DFT(conj g)).
+
+Binary32 target precision (the paper reaches a target precision through the
+number of splits, Sec. 6): a complex64 input is widened exactly to binary64,
+the transform above runs with the cap K (2 slices of about 20 bits per part
+cover binary32's 24), and each output component is rounded once to binary32.
 """
 
 from __future__ import annotations
@@ -301,6 +306,29 @@ def ifft(y, K: int | None = DEFAULT_K, L: int = DEFAULT_L, plan: KernelPlan | No
     out.real = a.real / n
     out.imag = a.imag / n
     return out
+
+
+def _to32(v):
+    """Each component rounded once to binary32 (round to nearest even)."""
+    return np.asarray(v, dtype=np.complex128).astype(np.complex64)
+
+
+def _from32(x32):
+    """complex64 widened exactly to complex128."""
+    return np.asarray(x32, dtype=np.complex64).astype(np.complex128)
+
+
+def fft_binary32(x32, K: int | None = 2, L: int = DEFAULT_L, plan: KernelPlan | None = None):
+    """Forward DFT at the binary32 target (module docstring): complex64 in and out."""
+    return _to32(fft(_from32(x32), K, L, plan))
+
+
+def adjoint_binary32(g32, K: int | None = 2, L: int = DEFAULT_L, plan: KernelPlan | None = None):
+    return _to32(adjoint(_from32(g32), K, L, plan))
+
+
+def ifft_binary32(y32, K: int | None = 2, L: int = DEFAULT_L, plan: KernelPlan | None = None):
+    return _to32(ifft(_from32(y32), K, L, plan))
 
 
 def ntt_counts(tr, plan: KernelPlan):

@@ -31,6 +31,8 @@ MODE_PLAIN, MODE_BATCHED = 0, 1
 EMBED_PADDED, EMBED_AUTO = 0, 1
 ACCUM_PER_CONV, ACCUM_COMPLEX = 0, 1
 _ACCUMS = {"per_conv": ACCUM_PER_CONV, "complex": ACCUM_COMPLEX}
+PREC_FP64, PREC_FP32 = 0, 1
+_PRECS = {"fp64": PREC_FP64, "fp32": PREC_FP32}
 _MODES = {"plain": MODE_PLAIN, "batched": MODE_BATCHED}
 
 
@@ -41,13 +43,14 @@ class FftOzakiError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("L", ctypes.c_int), ("mode", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p), ("embedding", ctypes.c_int),
-                ("accumulation", ctypes.c_int)]
+                ("accumulation", ctypes.c_int), ("precision", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64), ("total_length", ctypes.c_int64), ("K", ctypes.c_int),
                 ("L", ctypes.c_int), ("mode", ctypes.c_int), ("num_length_classes", ctypes.c_int),
-                ("workspace_bytes", ctypes.c_int64), ("embedding", ctypes.c_int), ("accumulation", ctypes.c_int)]
+                ("workspace_bytes", ctypes.c_int64), ("embedding", ctypes.c_int), ("accumulation", ctypes.c_int),
+                ("precision", ctypes.c_int)]
 
 
 class _TInfo(ctypes.Structure):
@@ -119,19 +122,26 @@ class Plan:
     accumulation: "complex" (default) walks the two real convolutions of each
     output component together so that products of equal scale share an
     inverse NTT (ReRe - ImIm, ImRe + ReIm); "per_conv" is Alg. 8 applied to
-    each real convolution on its own.  Outputs are bit-identical."""
+    each real convolution on its own.  Outputs are bit-identical.
 
-    def __init__(self, n: int | None = None, batch: int = 1, *, lengths=None, K: int = 3, L: int = 3,
+    precision: "fp64" (complex128 in and out) or "fp32" (complex64 in and
+    out: inputs widened exactly, the transform computed as for fp64 with this
+    plan's K, each output component rounded once to binary32).  K defaults to
+    3 for fp64 and 2 (about 40 bits per part) for fp32."""
+
+    def __init__(self, n: int | None = None, batch: int = 1, *, lengths=None, K: int | None = None, L: int = 3,
                  mode: str = "batched", autotune: bool = False, tune_cache: str | None = None,
-                 cyclic: bool = True, accumulation: str = "complex"):
+                 cyclic: bool = True, accumulation: str = "complex", precision: str = "fp64"):
         if lengths is None:
             if n is None:
                 raise ValueError("give n (and batch) or lengths")
             lengths = [int(n)] * int(batch)
         self.lengths = [int(v) for v in lengths]
-        self.K, self.L, self.mode = K, L, mode
+        if K is None:
+            K = 2 if precision == "fp32" else 3
+        self.K, self.L, self.mode, self.precision = K, L, mode, precision
         opts = _Options(K, L, _MODES[mode], int(bool(autotune)), tune_cache.encode() if tune_cache else None,
-                        EMBED_AUTO if cyclic else EMBED_PADDED, _ACCUMS[accumulation])
+                        EMBED_AUTO if cyclic else EMBED_PADDED, _ACCUMS[accumulation], _PRECS[precision])
         arr = (ctypes.c_int64 * len(self.lengths))(*self.lengths)
         h = ctypes.c_void_p()
         _check(lib().fft_ozaki_plan_ex(ctypes.byref(h), arr, len(self.lengths), ctypes.byref(opts)))
@@ -150,11 +160,16 @@ class Plan:
             pass
 
     def execute(self, x, direction: int = FORWARD, out=None, stream=None):
-        """Run on a contiguous complex128 CUDA tensor holding the transforms
-        back to back (e.g. shape (batch, n)); returns `out`."""
+        """Run on a contiguous CUDA tensor (complex128, or complex64 for an
+        fp32 plan) holding the transforms back to back (e.g. shape
+        (batch, n)); returns `out`."""
         import torch
-        if x.dtype != torch.complex128 or not x.is_cuda:
-            raise TypeError("x must be a complex128 CUDA tensor")
+        want = torch.complex64 if self.precision == "fp32" else torch.complex128
+        if x.dtype != want or not x.is_cuda:
+            raise TypeError(f"x must be a {want} CUDA tensor")
+        if out is not None and (out.dtype != want or not out.is_cuda or out.numel() != self.total
+                                or not out.is_contiguous()):
+            raise TypeError(f"out must be a contiguous {want} CUDA tensor of {self.total} elements")
         if x.numel() != self.total:
             raise ValueError(f"x has {x.numel()} elements, the plan needs {self.total}")
         x = x.contiguous()

@@ -128,6 +128,13 @@ __device__ __forceinline__ double2 finish(double pr, double pi, double2 w, int d
   return make_double2(yr, yi);
 }
 
+// Output element idx: complex128, or for a binary32 target complex64, each
+// component rounded once (to nearest even) from the binary64 result.
+__device__ __forceinline__ void put_out(void* out, i64 idx, double2 v, int io32) {
+  if (io32) reinterpret_cast<float2*>(out)[idx] = make_float2((float)v.x, (float)v.y);
+  else reinterpret_cast<double2*>(out)[idx] = v;
+}
+
 // A transform's exponent span needs the wide accumulator (output component tg).
 __device__ __forceinline__ bool span_wide(const TState& s, int tg) { return s.span[tg] > 64 * W_FAST - 71; }
 

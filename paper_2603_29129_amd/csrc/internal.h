@@ -76,9 +76,9 @@ bool fused_rows_ok(const NttGeom& g, int K);
 // exponent span needs the wide accumulator only get their column pass,
 // written to the compact buffer Z for launch_recombine_wide.
 bool fused_cols_ok(const NttGeom& g);
-hipError_t launch_inv_cols_rec(const u32* G, u32* Z, double2* out, const TDesc* td, const TState* ts,
+hipError_t launch_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td, const TState* ts,
                                const KernelDesc* kd, const int* tlist, int count, int K, const NttGeom& g,
-                               const TwBlock& tb, int dir, hipStream_t s);
+                               const TwBlock& tb, int dir, int io32, hipStream_t s);
 
 // Kernel slices: multiply by N^{-1} and build Shoup companions.
 hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s);
@@ -86,9 +86,11 @@ hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s)
 // --- split / chirp / groups / recombination --------------------------------
 hipError_t launch_chirp(double2* chirp, int n, int* flag, hipStream_t s);
 hipError_t launch_reset(TState* ts, const int* tlist, int count, hipStream_t s);
-hipError_t launch_premul(const double2* in, double2* xp, const TDesc* td, const KernelDesc* kd,
+// in / out of the transforms: complex128, or complex64 when io32 (binary32
+// target precision: inputs widened exactly, outputs rounded once).
+hipError_t launch_premul(const void* in, double2* xp, const TDesc* td, const KernelDesc* kd,
                          TState* ts, const int* tlist, int count, int nmax, int dir, bool kernel_mode,
-                         hipStream_t s);
+                         int io32, hipStream_t s);
 hipError_t launch_split_plan(const TDesc* td, TState* ts, const int* tlist, int count, int K,
                              hipStream_t s);
 hipError_t launch_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts,
@@ -98,12 +100,12 @@ hipError_t launch_split_check(const TDesc* td, TState* ts, const int* tlist, int
                               hipStream_t s);
 hipError_t launch_groups(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist,
                          int count, int K, int L, hipStream_t s);
-hipError_t launch_recombine(const u32* Z, double2* out, const TDesc* td, const TState* ts,
+hipError_t launch_recombine(const u32* Z, void* out, const TDesc* td, const TState* ts,
                             const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
-                            int dir, hipStream_t s);
+                            int dir, int io32, hipStream_t s);
 // Only the transforms whose exponent span needs the wide accumulator.
-hipError_t launch_recombine_wide(const u32* Z, double2* out, const TDesc* td, const TState* ts,
+hipError_t launch_recombine_wide(const u32* Z, void* out, const TDesc* td, const TState* ts,
                                  const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
-                                 int dir, hipStream_t s);
+                                 int dir, int io32, hipStream_t s);
 
 }  // namespace fo

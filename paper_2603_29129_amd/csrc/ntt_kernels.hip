@@ -1378,9 +1378,10 @@ __device__ __forceinline__ void rounds_dual(u32* tile0, u32* tile1, int nv, cons
 
 constexpr int REC_THREADS = 1024, REC_OUT = 4;   // 4096-position tiles
 template <int M1>
-__global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32* Z, double2* out, const TDesc* td,
+__global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td,
                                                               const TState* ts, const KernelDesc* kd,
-                                                              const int* tlist, int K, int m2, TwBlock tb, int dir) {
+                                                              const int* tlist, int K, int m2, TwBlock tb, int dir,
+                                                              int io32) {
   constexpr int LC = 12 - M1, LQ = LC - 2, TILE = 1 << 12;
   static_assert(LC >= 2 && TILE == REC_THREADS * REC_OUT, "tile shape");
   extern __shared__ u32 smem[];
@@ -1394,13 +1395,12 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
   const int n = d.n, N2 = 1 << m2;
   const int j2_0 = col_tile(blockIdx.x, m2 - LC) << LC;
   const double2* ch = kd[d.kd].chirp;
-  double2* yo = out + d.io_off;
   if (s.status) {
 #pragma unroll
     for (int k = 0; k < REC_OUT; ++k) {
       const int o = threadIdx.x + k * REC_THREADS;
       const int j = (o >> LC) * N2 + j2_0 + (o & ((1 << LC) - 1));
-      if (j < n) yo[j] = make_double2(__builtin_nan(""), __builtin_nan(""));
+      if (j < n) put_out(out, d.io_off + j, make_double2(__builtin_nan(""), __builtin_nan("")), io32);
     }
     return;
   }
@@ -1498,7 +1498,7 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
   for (int k = 0; k < REC_OUT; ++k) {
     const int o = threadIdx.x + k * REC_THREADS;
     const int j = (o >> LC) * N2 + j2_0 + (o & ((1 << LC) - 1));
-    if (j < n) yo[j] = finish(pr[k], pi[k], ch[j], dir, n);
+    if (j < n) put_out(out, d.io_off + j, finish(pr[k], pi[k], ch[j], dir, n), io32);
   }
 }
 
@@ -1754,9 +1754,9 @@ bool fused_cols_ok(const NttGeom& g) {
   return g.two_pass() && g.m1 >= 7 && g.m1 <= 9 && 12 - g.m1 <= g.m2;
 }
 
-hipError_t launch_inv_cols_rec(const u32* G, u32* Z, double2* out, const TDesc* td, const TState* ts,
+hipError_t launch_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td, const TState* ts,
                                const KernelDesc* kd, const int* tlist, int count, int K, const NttGeom& g,
-                               const TwBlock& tb, int dir, hipStream_t s) {
+                               const TwBlock& tb, int dir, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (!fused_cols_ok(g)) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
@@ -1766,7 +1766,7 @@ hipError_t launch_inv_cols_rec(const u32* G, u32* Z, double2* out, const TDesc* 
     const size_t smem = ((size_t)(2 << M1) + 2 * 4096) * 4;
     if ((e = big_lds((const void*)k_inv_cols_rec<M1>)) != hipSuccess) return;
     hipLaunchKernelGGL(k_inv_cols_rec<M1>, dim3(1u << (g.m2 - LC), 1, count), dim3(REC_THREADS), smem, s, G, Z, out,
-                       td, ts, kd, tlist, K, g.m2, tb, dir);
+                       td, ts, kd, tlist, K, g.m2, tb, dir, io32);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }

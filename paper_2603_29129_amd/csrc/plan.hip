@@ -113,6 +113,7 @@ struct fft_ozaki_plan_s {
   int autotune = 0;
   bool cyclic = true;               // FFT_OZAKI_EMBED_AUTO
   int accumulation = FFT_OZAKI_ACCUM_COMPLEX;
+  int precision = FFT_OZAKI_PREC_FP64;  // FP32: complex64 in / out
   std::string tune_cache;
   std::vector<fo::i64> lengths;
   fo::i64 total = 0;
@@ -305,7 +306,7 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   HIPCHK(hipMemcpy(tl, &zero, sizeof zero, hipMemcpyHostToDevice));
   HIPCHK(launch_chirp(kh.chirp, (int)n, flag, nullptr));
   HIPCHK(launch_reset(ts, tl, 1, nullptr));
-  HIPCHK(launch_premul(nullptr, xp, td, kd, ts, tl, 1, (int)n, 0, true, nullptr));
+  HIPCHK(launch_premul(nullptr, xp, td, kd, ts, tl, 1, (int)n, 0, true, 0, nullptr));
   HIPCHK(launch_split_plan(td, ts, tl, 1, K, nullptr));
   for (int r = 0; r < K; ++r) {
     HIPCHK(launch_split_extract(xp, kh.W, td, ts, tl, 1, (int)n, K, true, nullptr));
@@ -452,12 +453,16 @@ static int build_plan(fft_ozaki_plan_s* p) {
   return FFT_OZAKI_OK;
 }
 
+// 1 when the plan's transforms read and write complex64 (binary32 target).
+static inline int io32_of(const fft_ozaki_plan_s* p) { return p->precision == FFT_OZAKI_PREC_FP32 ? 1 : 0; }
+
 // The batched launch sequence (also what gets captured into the graph).
-static int enqueue_batched(fft_ozaki_plan_s* p, const double2* in, double2* out, int dir, hipStream_t s) {
+static int enqueue_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
   const int K = p->K, count = (int)p->td.size();
   HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
   for (auto& lc : p->classes)
-    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false, s));
+    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
+                         io32_of(p), s));
   HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_tall, count, K, s));
   for (int r = 0; r < K; ++r) {
     for (auto& lc : p->classes)
@@ -481,18 +486,18 @@ static int enqueue_batched(fft_ozaki_plan_s* p, const double2* in, double2* out,
       HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
                               p->tb, step_for(p, lc.logN), 1, s, fused_rows_ok(lc.geom, K)));
       HIPCHK(launch_inv_cols_rec(p->G, p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir,
-                                 s));
-      HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
+                                 io32_of(p), s));
+      HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s));
     } else {
       HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
                               p->tb, step_for(p, lc.logN), 0, s, fused_rows_ok(lc.geom, K)));
-      HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
+      HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s));
     }
   }
   return FFT_OZAKI_OK;
 }
 
-static int run_batched(fft_ozaki_plan_s* p, const double2* in, double2* out, int dir, hipStream_t s) {
+static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
   for (auto& lc : p->classes)
     if (fused_rows_ok(lc.geom, p->K)) p->x_rows_pending = true;
   for (auto& g : p->graphs) {
@@ -527,7 +532,7 @@ static int run_batched(fft_ozaki_plan_s* p, const double2* in, double2* out, int
   return FFT_OZAKI_OK;
 }
 
-static int run_plain(fft_ozaki_plan_s* p, const double2* in, double2* out, int dir, hipStream_t s) {
+static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
   const int K = p->K, SL = 2 * K * K;   // slots per output component
   for (int t = 0; t < (int)p->td.size(); ++t) {
     const TDesc& d = p->td[t];
@@ -539,7 +544,7 @@ static int run_plain(fft_ozaki_plan_s* p, const double2* in, double2* out, int d
     }();
     const TwStep& st = step_for(p, d.logN);
     HIPCHK(launch_reset(p->d_ts, tl, 1, s));
-    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, s));
+    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, io32_of(p), s));
     HIPCHK(launch_split_plan(p->d_td, p->d_ts, tl, 1, K, s));
     for (int r = 0; r < K; ++r) {
       HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, tl, 1, d.n, K, false, s));
@@ -567,7 +572,7 @@ static int run_plain(fft_ozaki_plan_s* p, const double2* in, double2* out, int d
                                      st, s));
         }
     }
-    HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, tl, 1, d.n, K, dir, s));
+    HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, tl, 1, d.n, K, dir, io32_of(p), s));
   }
   HIPCHK(hipStreamSynchronize(s));
   return FFT_OZAKI_OK;
@@ -576,14 +581,15 @@ static int run_plain(fft_ozaki_plan_s* p, const double2* in, double2* out, int d
 // One stage of the batched sequence for all transforms (measurement hook).
 static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
   const int K = p->K, count = (int)p->td.size();
-  const double2* in = (const double2*)p->last_in;
-  double2* out = (double2*)p->last_out;
+  const void* in = p->last_in;
+  void* out = p->last_out;
   const int dir = p->last_dir;
   switch (stage) {
     case 1:   // split: premultiply, maxima and the K extraction/check passes
       HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
       for (auto& lc : p->classes)
-        HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false, s));
+        HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
+                         io32_of(p), s));
       HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_tall, count, K, s));
       for (int r = 0; r < K; ++r) {
         for (auto& lc : p->classes)
@@ -617,7 +623,7 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
         const int cnt = (int)lc.tids.size();
         if (fused_cols_ok(lc.geom))
           HIPCHK(launch_inv_cols_rec(p->G, p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb,
-                                     dir, s));
+                                     dir, io32_of(p), s));
         else
           HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K,
                                   lc.geom, p->tb, step_for(p, lc.logN), 2, s));
@@ -627,9 +633,11 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
       for (auto& lc : p->classes) {
         const int cnt = (int)lc.tids.size();
         if (fused_cols_ok(lc.geom)) {
-          HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
+          HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir,
+                                       io32_of(p), s));
         } else {
-          HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, s));
+          HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p),
+                                  s));
         }
       }
       return FFT_OZAKI_OK;
@@ -661,6 +669,7 @@ int fft_ozaki_default_options(fft_ozaki_options* opt) {
   opt->tune_cache = nullptr;
   opt->embedding = FFT_OZAKI_EMBED_AUTO;
   opt->accumulation = FFT_OZAKI_ACCUM_COMPLEX;
+  opt->precision = FFT_OZAKI_PREC_FP64;
   return FFT_OZAKI_OK;
 }
 
@@ -682,6 +691,8 @@ int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t co
   const bool cyclic = o.embedding == FFT_OZAKI_EMBED_AUTO;
   if (o.accumulation != FFT_OZAKI_ACCUM_PER_CONV && o.accumulation != FFT_OZAKI_ACCUM_COMPLEX)
     return fail(FFT_OZAKI_ERR_INVALID, "accumulation must be 0 (per convolution) or 1 (complex)");
+  if (o.precision != FFT_OZAKI_PREC_FP64 && o.precision != FFT_OZAKI_PREC_FP32)
+    return fail(FFT_OZAKI_ERR_INVALID, "precision must be 0 (binary64) or 1 (binary32)");
   i64 total = 0;
   for (int64_t i = 0; i < count; ++i) {
     const i64 n = lengths[i];
@@ -700,6 +711,7 @@ int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t co
   p->autotune = o.autotune;
   p->cyclic = cyclic;
   p->accumulation = o.accumulation;
+  p->precision = o.precision;
   p->tune_cache = o.tune_cache ? o.tune_cache : "";
   p->lengths.assign(lengths, lengths + count);
   int rc = build_plan(p);
@@ -725,7 +737,8 @@ int fft_ozaki_execute(fft_ozaki_plan_t plan, const void* in, void* out, int dire
   if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
   if (!in || !out) return fail(FFT_OZAKI_ERR_INVALID, "in/out is NULL");
   if (direction < 0 || direction > 2) return fail(FFT_OZAKI_ERR_INVALID, "direction must be 0, 1 or 2");
-  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(FFT_OZAKI_ERR_INVALID, "in/out must be 16-byte aligned");
+  if (((uintptr_t)in | (uintptr_t)out) & (plan->precision == FFT_OZAKI_PREC_FP32 ? 7 : 15))
+    return fail(FFT_OZAKI_ERR_INVALID, "in/out must be aligned to their element size");
   int cur = 0;
   HIPCHK(hipGetDevice(&cur));
   if (cur != plan->device) HIPCHK(hipSetDevice(plan->device));
@@ -733,9 +746,8 @@ int fft_ozaki_execute(fft_ozaki_plan_t plan, const void* in, void* out, int dire
   plan->last_in = in;
   plan->last_out = out;
   plan->last_dir = direction;
-  int rc = plan->mode == FFT_OZAKI_MODE_PLAIN
-               ? run_plain(plan, (const double2*)in, (double2*)out, direction, s)
-               : run_batched(plan, (const double2*)in, (double2*)out, direction, s);
+  int rc = plan->mode == FFT_OZAKI_MODE_PLAIN ? run_plain(plan, in, out, direction, s)
+                                              : run_batched(plan, in, out, direction, s);
   if (cur != plan->device) (void)hipSetDevice(cur);
   return rc;
 }
@@ -759,6 +771,7 @@ int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info) {
   info->workspace_bytes = plan->bytes;
   info->embedding = plan->cyclic ? FFT_OZAKI_EMBED_AUTO : FFT_OZAKI_EMBED_PADDED;
   info->accumulation = plan->accumulation;
+  info->precision = plan->precision;
   return FFT_OZAKI_OK;
 }
 

@@ -62,8 +62,8 @@ __device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, 
 // those with a status, which get NaN), two outputs per thread;
 // WIDE = true: the others, one output per thread.
 template <bool WIDE>
-__global__ void k_recombine(const u32* Z, double2* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                            const int* tlist, int K, int dir) {
+__global__ void k_recombine(const u32* Z, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                            const int* tlist, int K, int dir, int io32) {
   const int t = tlist[blockIdx.z];
   const TDesc& d = td[t];
   const TState& s = ts[t];
@@ -84,40 +84,40 @@ __global__ void k_recombine(const u32* Z, double2* out, const TDesc* td, const T
         o0 = finish(pr0, pi0, ch[j], dir, d.n);
         o1 = j + 1 < d.n ? finish(pr1, pi1, ch[j + 1], dir, d.n) : o0;
       }
-      out[d.io_off + j] = o0;
-      if (j + 1 < d.n) out[d.io_off + j + 1] = o1;
+      put_out(out, d.io_off + j, o0, io32);
+      if (j + 1 < d.n) put_out(out, d.io_off + j + 1, o1, io32);
     }
     return;
   }
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
     const double pr = wide0 ? recombine_one<W_WIDE>(Zb, s, 0, SL, d.zs, j) : recombine_one<W_FAST>(Zb, s, 0, SL, d.zs, j);
     const double pi = wide1 ? recombine_one<W_WIDE>(Zb, s, 1, SL, d.zs, j) : recombine_one<W_FAST>(Zb, s, 1, SL, d.zs, j);
-    out[d.io_off + j] = finish(pr, pi, ch[j], dir, d.n);
+    put_out(out, d.io_off + j, finish(pr, pi, ch[j], dir, d.n), io32);
   }
 }
 
-hipError_t launch_recombine(const u32* Z, double2* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                            const int* tlist, int count, int nmax, int K, int dir, hipStream_t s) {
+hipError_t launch_recombine(const u32* Z, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                            const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   int b = (nmax + 255) / 256;
   if (b > 2048) b = 2048;
   if (b < 1) b = 1;
   const int b2 = (b + 1) / 2;      // two outputs per thread
-  hipLaunchKernelGGL(k_recombine<false>, dim3(b2, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir);
-  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir);
+  hipLaunchKernelGGL(k_recombine<false>, dim3(b2, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir, io32);
+  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir, io32);
   return hipGetLastError();
 }
 
 }  // namespace fo
 
 namespace fo {
-hipError_t launch_recombine_wide(const u32* Z, double2* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                                 const int* tlist, int count, int nmax, int K, int dir, hipStream_t s) {
+hipError_t launch_recombine_wide(const u32* Z, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                                 const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   int b = (nmax + 255) / 256;
   if (b > 2048) b = 2048;
   if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir);
+  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir, io32);
   return hipGetLastError();
 }
 }  // namespace fo

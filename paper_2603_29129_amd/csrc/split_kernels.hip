@@ -194,8 +194,8 @@ __device__ __forceinline__ u64 block_max_u64(u64 v) {
   return m;
 }
 
-__global__ void k_premul(const double2* in, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
-                         const int* tlist, int dir, bool kernel_mode) {
+__global__ void k_premul(const void* in, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
+                         const int* tlist, int dir, bool kernel_mode, int io32) {
   const int t = tlist[blockIdx.z];
   const TDesc& d = td[t];
   const double2* ch = kd[d.kd].chirp;
@@ -208,7 +208,13 @@ __global__ void k_premul(const double2* in, double2* xp, const TDesc* td, const 
       re = w.x;
       im = w.y;
     } else {
-      const double2 x = in[d.io_off + j];
+      double2 x;
+      if (io32) {                     // binary32 input: widened exactly
+        const float2 f = reinterpret_cast<const float2*>(in)[d.io_off + j];
+        x = make_double2((double)f.x, (double)f.y);
+      } else {
+        x = reinterpret_cast<const double2*>(in)[d.io_off + j];
+      }
       const double xr = x.x, xi = dir ? -x.y : x.y;
       re = xr * w.x + xi * w.y;       // RN(RN(xr c) + RN(xi s))
       im = xi * w.x - xr * w.y;       // RN(RN(xi c) - RN(xr s))
@@ -234,11 +240,11 @@ static int chunks_for(int nmax) {
   return b;
 }
 
-hipError_t launch_premul(const double2* in, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
-                         const int* tlist, int count, int nmax, int dir, bool kernel_mode, hipStream_t s) {
+hipError_t launch_premul(const void* in, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
+                         const int* tlist, int count, int nmax, int dir, bool kernel_mode, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_premul, dim3(chunks_for(nmax), 1, count), dim3(256), 0, s, in, xp, td, kd, ts, tlist, dir,
-                     kernel_mode);
+                     kernel_mode, io32);
   return hipGetLastError();
 }
 
