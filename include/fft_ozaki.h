@@ -182,6 +182,8 @@ typedef struct {
   int Ew[2][8];
   int ngroups[2];                  /* accumulation groups of Re y', Im y' */
   int acc_limit;                   /* products per group: L (PER_CONV) or the CRT-range bound (COMPLEX) */
+  int xsh[2];                      /* COMPLEX: slices of Re x', Im x' are taken times 2^xsh[part] (0, 1 or 2)
+                                      and their products weigh 2^xsh[part] in a group; see debug stage 2 */
   int forward_runtime, forward_offline, inverse;
   int ntt_log2N1;                  /* NTT-domain layout: see fft_ozaki_ntt */
 } fft_ozaki_transform_info;
@@ -190,7 +192,8 @@ int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_tr
 /* Test hook: copy an intermediate buffer of transform `index` of the last
  * execution to host memory (synchronises the device).  Stages:
  *   1  x' = x (.) w                          double2[n]
- *   2  forward NTTs of the x' slices         uint32[2][K][2][N]  (part, slice, prime; NTT-domain order)
+ *   2  forward NTTs of the x' slices         uint32[2][K][2][N]  (part, slice, prime; NTT-domain order;
+ *                                            part p's slices times 2^xsh[p], see fft_ozaki_transform_info)
  *   3  inverse NTT outputs per group         uint32[4*K*K][2][n4] (slot = component*2*K*K + group,
  *                                            component 0 = Re y', 1 = Im y'; prime;
  *                                            n4 = n rounded up to a multiple of 4, first n valid; where

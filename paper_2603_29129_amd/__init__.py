@@ -57,6 +57,7 @@ class _TInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("N", ctypes.c_int64), ("alpha", ctypes.c_int), ("status", ctypes.c_int),
                 ("kx", ctypes.c_int * 2), ("Ex", (ctypes.c_int * 8) * 2), ("kw", ctypes.c_int * 2),
                 ("Ew", (ctypes.c_int * 8) * 2), ("ngroups", ctypes.c_int * 2), ("acc_limit", ctypes.c_int),
+                ("xsh", ctypes.c_int * 2),
                 ("forward_runtime", ctypes.c_int),
                 ("forward_offline", ctypes.c_int), ("inverse", ctypes.c_int), ("ntt_log2N1", ctypes.c_int)]
 
@@ -210,6 +211,7 @@ class Plan:
         d["Ex"] = [list(i.Ex[p])[: i.kx[p]] for p in range(2)]
         d["Ew"] = [list(i.Ew[p])[: i.kw[p]] for p in range(2)]
         d["ngroups"] = list(i.ngroups)
+        d["xsh"] = list(i.xsh)
         return d
 
     def debug_dump(self, stage: int, index: int) -> np.ndarray:

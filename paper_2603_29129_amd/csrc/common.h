@@ -121,11 +121,18 @@ struct KernelDesc {
 //                 scale and at the change of convolution.
 //   ACC_COMPLEX   anti-diagonals descending, on each the pairs of
 //                 convolution 2 tg and then of 2 tg + 1 (s ascending); a
-//                 group closes at a change of scale or when it holds
-//                 acc_limit products, the most whose signed sum stays within
-//                 the CRT range: acc_limit n 4^alpha <= (p0 p1 - 1) / 2.
-//                 Re y' = ReRe - ImIm and Im y' = ImRe + ReIm are then formed
-//                 in the NTT domain wherever the scales agree.
+//                 group closes at a change of scale or when its products'
+//                 weights would exceed acc_limit, the most products whose
+//                 signed sum stays within the CRT range:
+//                 acc_limit n 4^alpha <= (p0 p1 - 1) / 2.  Re y' = ReRe - ImIm
+//                 and Im y' = ImRe + ReIm are then formed in the NTT domain
+//                 wherever the scales agree.  When the top exponents of
+//                 Re x' and Im x' differ by d = 1 or 2, the larger part's
+//                 slice spectra enter the products times 2^d (xsh) and its
+//                 exponents count d lower, so the two parts' scales line up;
+//                 its products then weigh 2^d.  This is done when a full
+//                 anti-diagonal of that part's products still fits
+//                 acc_limit.
 constexpr int ACC_PER_CONV = 0;
 constexpr int ACC_COMPLEX = 1;
 constexpr int MAX_MEMBERS = 2 * MAX_PAIRS;      // walk positions per output component
@@ -150,6 +157,7 @@ struct TState {
   int ngroups[2];
   Group groups[2][MAX_MEMBERS];
   u64 gend[2][2];          // bit w of the 128: walk position w closes its group
+  int xsh[2];              // x' part p's slice spectra enter the products times 2^xsh[p]
   int emin[2];             // per output component: smallest group exponent
   int span[2];             // per output component: largest shift above emin
 };

@@ -91,7 +91,7 @@ hipError_t launch_reset(TState* ts, const int* tlist, int count, hipStream_t s);
 hipError_t launch_premul(const void* in, double2* xp, const TDesc* td, const KernelDesc* kd,
                          TState* ts, const int* tlist, int count, int nmax, int dir, bool kernel_mode,
                          int io32, hipStream_t s);
-hipError_t launch_split_plan(const TDesc* td, TState* ts, const int* tlist, int count, int K,
+hipError_t launch_split_plan(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist, int count, int K,
                              hipStream_t s);
 hipError_t launch_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts,
                                 const int* tlist, int count, int nmax, int K, bool kernel_mode,

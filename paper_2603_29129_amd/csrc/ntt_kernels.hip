@@ -1325,8 +1325,9 @@ __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, 
 // to exact per-output accumulators held in registers (REC_OUT outputs per
 // thread); the Re y' groups come first, then the Im y' groups, so one set of
 // accumulators serves both components.  The group residues never go to
-// memory.  Transforms whose exponent span needs the wide accumulator are
-// left to the unfused column pass and recombination.
+// memory.  Transforms whose exponent span needs the wide accumulator only
+// get their column pass here, written to the compact buffer for the wide
+// recombination.
 
 // One round of the inverse column transforms of two tiles (prime 0 and 1):
 // the groups of tile 1 follow those of tile 0, so every wave works on one

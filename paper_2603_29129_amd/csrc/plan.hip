@@ -307,7 +307,7 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   HIPCHK(launch_chirp(kh.chirp, (int)n, flag, nullptr));
   HIPCHK(launch_reset(ts, tl, 1, nullptr));
   HIPCHK(launch_premul(nullptr, xp, td, kd, ts, tl, 1, (int)n, 0, true, 0, nullptr));
-  HIPCHK(launch_split_plan(td, ts, tl, 1, K, nullptr));
+  HIPCHK(launch_split_plan(td, ts, kd, tl, 1, K, nullptr));
   for (int r = 0; r < K; ++r) {
     HIPCHK(launch_split_extract(xp, kh.W, td, ts, tl, 1, (int)n, K, true, nullptr));
     HIPCHK(launch_split_check(td, ts, tl, 1, K, nullptr));
@@ -463,7 +463,7 @@ static int enqueue_batched(fft_ozaki_plan_s* p, const void* in, void* out, int d
   for (auto& lc : p->classes)
     HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
                          io32_of(p), s));
-  HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_tall, count, K, s));
+  HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
   for (int r = 0; r < K; ++r) {
     for (auto& lc : p->classes)
       HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s));
@@ -545,7 +545,7 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
     const TwStep& st = step_for(p, d.logN);
     HIPCHK(launch_reset(p->d_ts, tl, 1, s));
     HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, io32_of(p), s));
-    HIPCHK(launch_split_plan(p->d_td, p->d_ts, tl, 1, K, s));
+    HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, tl, 1, K, s));
     for (int r = 0; r < K; ++r) {
       HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, tl, 1, d.n, K, false, s));
       HIPCHK(launch_split_check(p->d_td, p->d_ts, tl, 1, K, s));
@@ -590,7 +590,7 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
       for (auto& lc : p->classes)
         HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
                          io32_of(p), s));
-      HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_tall, count, K, s));
+      HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
       for (int r = 0; r < K; ++r) {
         for (auto& lc : p->classes)
           HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s));
@@ -808,6 +808,8 @@ int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_tr
     iv += 2 * hs.ngroups[tg];
   }
   info->acc_limit = d.acc_limit;
+  info->xsh[0] = hs.xsh[0];
+  info->xsh[1] = hs.xsh[1];
   info->forward_runtime = fr;
   info->forward_offline = fo_;
   info->inverse = iv;

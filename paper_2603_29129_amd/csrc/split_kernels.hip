@@ -273,12 +273,13 @@ __device__ __forceinline__ int ceil_log2_bits(u64 bits) {
   return ex - 1023 + (man ? 1 : 0);
 }
 
-__global__ void k_split_plan(const TDesc* td, TState* ts, const int* tlist, int count, int K) {
+__global__ void k_split_plan(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist, int count, int K) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const int t = tlist[i];
   const TDesc& d = td[t];
   TState& s = ts[t];
+  s.xsh[0] = s.xsh[1] = 0;
   const int alpha = d.alpha;
   int status = 0;
   for (int part = 0; part < 2; ++part) {
@@ -304,17 +305,29 @@ __global__ void k_split_plan(const TDesc* td, TState* ts, const int* tlist, int 
   if (status) {
     s.active[0] = s.active[1] = 0;
     s.kx[0] = s.kx[1] = 0;
+  } else if (d.acc_mode == ACC_COMPLEX && s.active[0] && s.active[1]) {
+    // scale alignment for the complex accumulation: the part whose top
+    // exponent lies sh = 1 or 2 binades above the other's is extracted
+    // times 2^sh with exponents sh lower, when an anti-diagonal of its
+    // products (each then weighing 2^sh) fits the group limit and the
+    // scaled slice integers (at most 2^(alpha + sh)) stay below 2^30
+    const int dl = s.E[0][0] - s.E[1][0], part = dl > 0 ? 0 : 1, sh = dl > 0 ? dl : -dl;
+    const KernelDesc& kk = kd[d.kd];
+    const int diag = max(kk.kw[0], kk.kw[1]);              // kernel slices, at most K
+    if (sh >= 1 && sh <= 2 && (diag << sh) <= d.acc_limit && alpha + sh <= 30) s.xsh[part] = sh;
   }
 }
 
-hipError_t launch_split_plan(const TDesc* td, TState* ts, const int* tlist, int count, int K, hipStream_t s) {
+hipError_t launch_split_plan(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist, int count, int K,
+                             hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_split_plan, dim3((count + 63) / 64), dim3(64), 0, s, td, ts, tlist, count, K);
+  hipLaunchKernelGGL(k_split_plan, dim3((count + 63) / 64), dim3(64), 0, s, td, ts, kd, tlist, count, K);
   return hipGetLastError();
 }
 
-// blockIdx.y = part.  Slices k >= start are written as residues mod p0, p1
-// into X[(part*K + k)*2 + prime][.]; input slices go to positions j < n (the
+// blockIdx.y = part.  Slices k >= start are written, times 2^xsh[part], as
+// residues mod p0, p1 into X[(part*K + k)*2 + prime][.]; input slices go to
+// positions j < n (the
 // NTT treats the rest as zero), kernel slices are placed by ZeroPad+-
 // (positions j and N - j), or at j alone when N = n (cyclic embedding).
 __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts, const int* tlist, int K,
@@ -324,7 +337,7 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
   TState& s = ts[t];
   if (!s.active[part]) return;
   const TDesc& d = td[t];
-  const int alpha = d.alpha, start = s.start[part];
+  const int alpha = d.alpha, start = s.start[part], sh = s.xsh[part];
   int Ek[KMAX];
   int kend = K;
   for (int k = 0; k < K; ++k) {
@@ -345,7 +358,7 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
       const double x = (r + sigma) - sigma;
       r = r - x;
       if (k >= start) {
-        const int a = (int)(x * ldexp(1.0, alpha - E));
+        const int a = (int)(x * ldexp(1.0, alpha - E + sh));   // |a| <= 2^(alpha + sh) <= 2^30 < p0, p1
         const u32 r0 = a < 0 ? (u32)(a + (int)P0) : (u32)a;
         const u32 r1 = a < 0 ? (u32)(a + (int)P1) : (u32)a;
         u32* v0 = Xb + (((size_t)((part * K + k) * 2)) << d.logN);
@@ -443,8 +456,9 @@ __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
     }
   const bool merged = d.acc_mode == ACC_COMPLEX;
   const int lim = merged ? d.acc_limit : L;
+  const int xsh[2] = {merged ? s.xsh[0] : 0, merged ? s.xsh[1] : 0};
   for (int tg = 0; tg < 2; ++tg) {
-    int np = 0, ng = 0, cnt = 0, gstart = 0, key = 0, cur = -1;
+    int np = 0, ng = 0, cnt = 0, gstart = 0, key = 0, cur = -1, load = 0;
     int emin = 0x7FFFFFFF, emax = -0x7FFFFFFF;
     auto close = [&]() {
       s.groups[tg][ng].start = gstart;
@@ -455,12 +469,15 @@ __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
       ++ng;
       gstart = np;
       cnt = 0;
+      load = 0;
     };
     auto visit = [&](int c, int ss, int tt) {
-      const int k2 = E[conv_pa(c)][ss] + Ew[conv_pb(c)][tt];
-      if (cnt > 0 && (cnt >= lim || k2 != key || (!merged && c != cur))) close();
+      const int pa = conv_pa(c), wgt = 1 << xsh[pa];
+      const int k2 = E[pa][ss] - xsh[pa] + Ew[conv_pb(c)][tt];
+      if (cnt > 0 && (load + wgt > lim || k2 != key || (!merged && c != cur))) close();
       key = k2;
       cur = c;
+      load += wgt;
       s.mc[tg][np] = (unsigned char)c;
       s.ms[tg][np] = (unsigned char)ss;
       s.mt[tg][np] = (unsigned char)tt;

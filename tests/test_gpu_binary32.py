@@ -64,7 +64,8 @@ def test_binary32_forward(torch_mod, n, mode):
         info = plan.transform_info(b)
         tr = bl.forward_trace(x[b].astype(np.complex128), 2, 3, kp)
         EX = [[E for _, E in tr["slices"][v]] for v in range(2)]
-        sched = component_schedule(EX, [kp.exps(0), kp.exps(1)], 3, "complex", acc_limit(n, tr["alpha"]))
+        sched = component_schedule(EX, [kp.exps(0), kp.exps(1)], 3, "complex", acc_limit(n, tr["alpha"]),
+                                    alpha=tr["alpha"])
         assert info["ngroups"] == [len(g) for g in sched]
         assert info["forward_runtime"] == 2 * sum(info["kx"]) and max(info["kx"]) <= 2
 

@@ -14,7 +14,7 @@ from oracle import bluestein as bl
 from oracle import ntt as nt
 from oracle import ozaki as oz_or
 from oracle import reference as ref
-from tests.accum_schedule import acc_limit, component_schedule, group_residues
+from tests.accum_schedule import acc_limit, component_schedule, group_residues, part_shift
 from tests.gpu_helpers import max_ulp, ntt_domain_index
 
 pytestmark = pytest.mark.gpu
@@ -73,19 +73,23 @@ def check_stages(plan, idx, tr, kp, K):
     assert info["acc_limit"] == limit
     EX = [[E for _, E in tr["slices"][v]] for v in range(2)]
     EW = [kp.exps(v) for v in range(2)]
-    sched = component_schedule(EX, EW, tr["L"], "complex" if complex_acc else "per_conv", limit)
+    sched = component_schedule(EX, EW, tr["L"], "complex" if complex_acc else "per_conv", limit, weights=True,
+                                alpha=tr["alpha"])
     if not complex_acc:       # the paper's schedule: the oracle's Alg. 8 groups, convolution by convolution
-        assert [[(s, t) for _, s, t in g] for g in sched[0] + sched[1]] == [
+        assert [[(s, t) for _, s, t, _ in g] for g in sched[0] + sched[1]] == [
             list(g) for c in range(4) for g in tr["groups"][c]]
     assert info["ngroups"] == [len(g) for g in sched]
+    xsh = part_shift(EX, EW, limit, tr["alpha"]) if complex_acc else [0, 0]
+    assert info["xsh"] == xsh
     logN = N.bit_length() - 1
     perm = ntt_domain_index(logN, info["ntt_log2N1"])
-    # forward NTTs of the slices
+    # forward NTTs of the slices (part p's times 2^xsh[p])
     X = plan.debug_dump(2, idx).reshape(2, K, 2, N)
     for part in range(2):
         for k in range(len(tr["slices"][part])):
-            for ip in range(2):
-                assert np.array_equal(X[part, k, ip].astype(np.uint64), tr["X"][part][k][ip][perm]), (part, k, ip)
+            for ip, p in enumerate(nt.PRIMES):
+                want = (tr["X"][part][k][ip] * np.uint64(1 << xsh[part])) % np.uint64(p)
+                assert np.array_equal(X[part, k, ip].astype(np.uint64), want[perm]), (part, k, ip)
     # kernel NTTs (times N^-1)
     W = plan.debug_dump(4, idx).reshape(2, K, 2, N)
     for part in range(2):
@@ -168,6 +172,54 @@ def test_cyclic_embedding_two_pass(torch_mod, n):
                 check_stages(plan, 1, tr, kp, 3)
                 assert max_ulp(outs[-1][1], tr["y"]) == 0
     assert all(np.array_equal(v.view(np.uint64), outs[0].view(np.uint64)) for v in outs)
+
+
+def _spiked(n, spikes, seed=0):
+    """Small noise with x_0 set per transform: x'_0 = x_0 (the chirp is 1
+    there), so the spike fixes the top exponents of Re x' and Im x'."""
+    x = wl.paper_phi(n, 0.0, seed=seed, batch=len(spikes)) * 2.0 ** -6
+    x[:, 0] = spikes
+    return x
+
+
+@pytest.mark.parametrize("n,xsh", [(12, [[1, 0], [0, 1], [0, 0], [2, 0]]),
+                                   (1 << 16, [[1, 0], [0, 1], [0, 0], [0, 0]])])
+def test_part_shift(torch_mod, n, xsh):
+    """Re x' and Im x' with top exponents 1 or 2 binades apart: the larger
+    part is taken times 2^xsh (when an anti-diagonal of its products still
+    fits the group bound) and its products share groups with the other
+    part's.  Intermediates bit-exact, outputs 0 ulp from the oracle; at
+    n = 2^16 (bound 7, three kernel slices) a shift of 2 would not fit."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = _spiked(n, [1 + 0.4j, 0.4 + 1j, 1 + 1j, 1 + 0.2j])
+    plan = oz.Plan(n, 4)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan(n, 3, 3)
+    for b in range(4):
+        tr = bl.forward_trace(x[b], 3, 3, kp)
+        check_stages(plan, b, tr, kp, 3)
+        assert plan.transform_info(b)["xsh"] == xsh[b], b
+        assert max_ulp(y[b], tr["y"]) == 0, b
+    if n > 12:                # 10 groups per component unshifted, 6 shifted, 5 with equal exponents
+        assert [plan.transform_info(b)["ngroups"] for b in range(4)] == [[6, 6], [6, 6], [5, 5], [10, 10]]
+
+
+def test_part_shift_headline_length(torch_mod):
+    """n = 2^18 (folded forward rows, fused column pass): a transform with
+    the Re x' top exponent one above Im x' next to one with them equal, in
+    one launch; full outputs 0 ulp from the oracle."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 1 << 18
+    x = _spiked(n, [1 + 0.4j, 1 + 1j], seed=3)
+    plan = oz.Plan(n, 2)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan(n, 3, 3)
+    for b, (xs, ng) in enumerate((([1, 0], [6, 6]), ([0, 0], [5, 5]))):
+        info = plan.transform_info(b)
+        assert info["xsh"] == xs and info["ngroups"] == ng, b
+        assert max_ulp(y[b], bl.fft(x[b], plan=kp)) == 0, b
 
 
 @pytest.mark.parametrize("K,L", [(1, 1), (2, 1), (3, 1), (2, 2), (4, 3), (6, 1), (8, 8)])
