@@ -36,6 +36,12 @@ Pipeline for y = DFT(x), x in (F64 + i F64)^n, parameters (K, L):
 Inverse: DFT^{-1}(y) = conj(DFT(conj y)) / n, componentwise division
 (Sec. 3.2, Eq. idft).  Adjoint: DFT^H(g) = conj(DFT(conj g)).
 
+Three moduli (d = 3, Sec. 3.3's CRT with d moduli; ``primes=3``): residues
+mod p0, p1, p2, the split width from Sec. 4.2's formula with the product of
+the three moduli (alpha = 36 at n = 2^18, L = 3), Garner's algorithm with
+d = 3 in step 6; everything else as above.  With slices that wide K = 2
+reaches the binary64 accuracy of K = 3 with two moduli.
+
 Binary32 target precision (the paper reaches a target precision through the
 number of splits, Sec. 6): a complex64 input is widened exactly to binary64,
 the transform above runs with the cap K (2 slices of about 20 bits per part
@@ -191,10 +197,14 @@ class KernelPlan:
     """Input-independent part for one length n: chirp, splits of Re w* and
     Im w* and their forward NTTs (Sec. 4.5, precomputed offline)."""
 
-    def __init__(self, n: int, K: int | None = DEFAULT_K, L: int = DEFAULT_L, cyclic: bool = False):
+    def __init__(self, n: int, K: int | None = DEFAULT_K, L: int = DEFAULT_L, cyclic: bool = False,
+                 primes: int = 2):
+        if primes not in (2, 3):
+            raise ValueError("primes must be 2 or 3")
         self.n, self.K, self.L, self.cyclic = n, K, L, cyclic
         self.N = conv_length(n, cyclic)
-        self.alpha = oz.alpha_crt(n, L)
+        self.primes = nt.PRIMES if primes == 2 else nt.PRIMES3
+        self.alpha = oz.alpha_crt(n, L, nt.PP if primes == 2 else nt.PPP)
         self.c, self.s = chirp(n)
         self.slices = []   # per part: list of (a, E)
         self.ntts = []     # per part: list of (W0, W1)
@@ -202,7 +212,7 @@ class KernelPlan:
             sl, _, st = oz.split(v, self.alpha, K)
             assert st == oz.STATUS_OK
             self.slices.append(sl)
-            self.ntts.append([tuple(nt.ntt(pad_kernel(a, self.N), p) for p in nt.PRIMES)
+            self.ntts.append([tuple(nt.ntt(pad_kernel(a, self.N), p) for p in self.primes)
                               for a, _ in sl])
 
     def exps(self, part):
@@ -235,8 +245,8 @@ def forward_trace(x, K: int | None = DEFAULT_K, L: int = DEFAULT_L, plan: Kernel
         tr["groups"] = [[] for _ in CONVS]
         return tr
     tr["slices"] = xs
-    # forward NTTs of the input slices (zero padded), both primes
-    X = [[tuple(nt.ntt(pad_input(a, N), p) for p in nt.PRIMES) for a, _ in xs[v]] for v in range(2)]
+    # forward NTTs of the input slices (zero padded), every prime
+    X = [[tuple(nt.ntt(pad_input(a, N), p) for p in plan.primes) for a, _ in xs[v]] for v in range(2)]
     tr["X"] = X
     EX = [[E for _, E in xs[v]] for v in range(2)]
     tr["groups"] = []
@@ -248,12 +258,12 @@ def forward_trace(x, K: int | None = DEFAULT_K, L: int = DEFAULT_L, plan: Kernel
         zs = []
         for grp in groups:
             zi = []
-            for ip, p in enumerate(nt.PRIMES):
+            for ip, p in enumerate(plan.primes):
                 acc = np.zeros(N, dtype=np.uint64)
                 for (s, t) in grp:
                     acc = (acc + X[pa][s][ip] * plan.ntts[pb][t][ip]) % np.uint64(p)
                 zi.append(nt.ntt(acc, p, inverse=True)[:n])
-            z = nt.garner_crt(zi[0], zi[1])
+            z = nt.garner_crt(zi[0], zi[1]) if len(zi) == 2 else nt.garner_crt3(zi[0], zi[1], zi[2])
             s0, t0 = grp[0]
             e = EX[pa][s0] + plan.exps(pb)[t0] - 2 * alpha
             zs.append((z, e))
@@ -334,9 +344,10 @@ def ifft_binary32(y32, K: int | None = 2, L: int = DEFAULT_L, plan: KernelPlan |
 def ntt_counts(tr, plan: KernelPlan):
     """32-bit transform counts (Sec. 4.5): forward NTTs of the input splits
     (runtime), of the kernel splits (offline), inverse NTTs (runtime)."""
-    fwd_rt = 2 * sum(len(tr["slices"][v]) for v in range(2))
-    fwd_off = 2 * sum(len(plan.slices[v]) for v in range(2))
-    inv = 2 * sum(len(g) for g in tr["groups"])
+    d = len(plan.primes)
+    fwd_rt = d * sum(len(tr["slices"][v]) for v in range(2))
+    fwd_off = d * sum(len(plan.slices[v]) for v in range(2))
+    inv = d * sum(len(g) for g in tr["groups"])
     return dict(forward_runtime=fwd_rt, forward_offline=fwd_off, inverse=inv,
                 runtime=fwd_rt + inv, total=fwd_rt + fwd_off + inv)
 

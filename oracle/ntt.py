@@ -1,4 +1,5 @@
-"""Oracle: arithmetic modulo the two 32-bit primes, NTT and CRT.
+"""Oracle: arithmetic modulo the 32-bit primes, NTT and CRT (two primes, and
+three for the d = 3 variant).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -25,6 +26,15 @@ PP_HALF = (PP - 1) // 2
 P0_INV_MOD_P1 = pow(P0, -1, P1)
 # Largest power-of-two NTT length supported by both primes: gcd(p0-1, p1-1).
 MAX_LOG2_N = 24
+
+# Third modulus for the d = 3 CRT (Sec. 3.3 with d moduli; Sec. 4.2's alpha
+# formula with the product of all moduli): p2 = 15 * 2^27 + 1 < 2^31, its
+# 2-power part 2^27 covers every NTT length above.
+P2 = 2013265921
+GENERATORS[P2] = 31
+PRIMES3 = (P0, P1, P2)
+PPP = P0 * P1 * P2
+PPP_HALF = (PPP - 1) // 2
 
 
 def smod(a: int, m: int) -> int:
@@ -154,6 +164,24 @@ def garner_crt(z0, z1) -> np.ndarray:
     h = (d * np.uint64(P0_INV_MOD_P1)) % p1
     z = z0.astype(np.int64) + h.astype(np.int64) * np.int64(P0)  # in [0, P) < 2^62
     return np.where(z > PP_HALF, z - np.int64(PP), z)
+
+
+def garner_crt3(z0, z1, z2) -> np.ndarray:
+    """Three-prime CRT in Garner's mixed-radix form (Sec. 3.3, Garner's
+    algorithm with d = 3):
+        h1 = (z1 - z0) p0^{-1} mod p1,
+        h2 = (z2 - z0 - p0 h1) (p0 p1)^{-1} mod p2,
+        z  = z0 + p0 h1 + p0 p1 h2,
+    then mapped to the symmetric range [-(M-1)/2, (M-1)/2], M = p0 p1 p2.
+    Returns an object array of Python ints (|z| < 2^92)."""
+    out = []
+    for a, b, c in zip(np.asarray(z0).tolist(), np.asarray(z1).tolist(), np.asarray(z2).tolist()):
+        h1 = ((b - a) * pow(P0, -1, P1)) % P1
+        t = a + P0 * h1
+        h2 = ((c - t) * pow(P0 * P1, -1, P2)) % P2
+        z = t + P0 * P1 * h2
+        out.append(z - PPP if z > PPP_HALF else z)
+    return np.array(out, dtype=object)
 
 
 def crt_explicit(residues, moduli) -> int:
