@@ -16,8 +16,8 @@ Prints one JSON line.  Besides the headline (batched form, HIP graph replay)
 it reports the plain form on the same input, the relative l2 error against
 a long-double DFT, per-stage device times, the roofline of the dominant
 kernel, the binary32 target precision (complex64 in and out, K = 2) on the
-same input rounded to binary32, and the CPU oracle timed on a bounded
-sample.
+same input rounded to binary32, the three-modulus CRT plan (K = 2 slices of
+36 bits) on the same input, and the CPU oracle timed on a bounded sample.
 """
 
 import argparse
@@ -288,6 +288,24 @@ def main():
     del x32d, out32
     print(f"# binary32 target (K=2): {ms32:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # three CRT moduli (d = 3): K = 2 slices of alpha = 36 bits, same input
+    # and output type; the standalone NTTs run per length class and prime
+    plan3 = oz.Plan(n, B, mode="batched", primes=3)
+    out3 = torch.empty_like(xd)
+    for _ in range(args.warmup):
+        plan3.forward(xd, out3)
+    torch.cuda.synchronize()
+    ms3 = time_events(torch, lambda k: [plan3.forward(xd, out3) for _ in range(k)], args.steps)
+    i3 = plan3.transform_info(0)
+    rel3, maxrel3 = longdouble_errors(np, out3[0].cpu().numpy(), x[0])
+    three_moduli = {"K": plan3.K, "alpha": i3["alpha"], "acc_limit": i3["acc_limit"], "ms_per_step": round(ms3, 4),
+                    "value": round(flops / (ms3 * 1e-3) / 1e9, 2), "rel_l2_error": rel3, "max_rel_error": maxrel3,
+                    "ntt_counts": {"forward_runtime": i3["forward_runtime"], "inverse": i3["inverse"],
+                                   "forward_offline": i3["forward_offline"]}}
+    plan3.close()
+    del out3
+    print(f"# three moduli (K=2, alpha={i3['alpha']}): {ms3:.3f} ms/step", file=sys.stderr, flush=True)
+
     y = out.cpu().numpy()
     infos = [plan.transform_info(b) for b in range(B)]
     rel, maxrel = longdouble_errors(np, y[0], x[0])
@@ -374,6 +392,7 @@ def main():
                    "parallelism": "single GPU"},
         "padded_embedding": padded,
         "binary32_target": binary32,
+        "three_moduli": three_moduli,
         "rel_l2_error": rel,
         "max_rel_error": maxrel,
         "ntt_counts": {"forward_runtime": counts["forward_runtime"], "inverse": counts["inverse"],

@@ -120,7 +120,13 @@ enum {
  * shape); tune_cache: optional file path where tuned shapes are stored and
  * looked up (NULL = none).  embedding: FFT_OZAKI_EMBED_*, default AUTO.
  * accumulation: FFT_OZAKI_ACCUM_*, default COMPLEX.  precision:
- * FFT_OZAKI_PREC_*, default FP64. */
+ * FFT_OZAKI_PREC_*, default FP64.  primes: number of CRT moduli, 2 (p0, p1;
+ * default) or 3 (p0, p1 and p2 = 15 * 2^27 + 1, Sec. 3.3 with d = 3): the
+ * split width then follows Sec. 4.2 with the product p0 p1 p2 (alpha = 36 at
+ * n = 2^18, L = 3), so K = 2 slices of about 36 bits reach the binary64
+ * accuracy that K = 3 needs with two moduli.  Three moduli: batched mode
+ * only (FFT_OZAKI_ERR_UNSUPPORTED otherwise); group values reach 93 bits;
+ * debug stages 2-4 and fft_ozaki_profile_stage are not available. */
 typedef struct {
   int K;
   int L;
@@ -130,10 +136,11 @@ typedef struct {
   int embedding;
   int accumulation;
   int precision;
+  int primes;
 } fft_ozaki_options;
 
 /* Fills *opt with the defaults (K = 3, L = 3, batched, no autotune, AUTO
- * embedding, COMPLEX accumulation, FP64). */
+ * embedding, COMPLEX accumulation, FP64, two moduli). */
 int fft_ozaki_default_options(fft_ozaki_options* opt);
 
 /* Plan `batch` transforms of length n (uniform batch) with default options.
@@ -165,6 +172,7 @@ typedef struct {
   int embedding;                   /* FFT_OZAKI_EMBED_* */
   int accumulation;                /* FFT_OZAKI_ACCUM_* */
   int precision;                   /* FFT_OZAKI_PREC_* */
+  int primes;                      /* CRT moduli: 2 or 3 */
 } fft_ozaki_info;
 int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info);
 
@@ -231,8 +239,9 @@ const char* fft_ozaki_error_string(int status);
 const char* fft_ozaki_last_error_message(void);
 
 /* The library's 32-bit NTT (Sec. 3.3, Eq. ntt / intt) on `count` contiguous
- * device vectors of length N = 2^log2N (1 <= N <= 2^24) modulo p0 (prime 0)
- * or p1 (prime 1), in place.  The forward transform reads natural order and
+ * device vectors of length N = 2^log2N (1 <= N <= 2^24) modulo p0 (prime 0),
+ * p1 (prime 1) or p2 = 2013265921 (prime 2, the third modulus of the
+ * three-modulus plans), in place.  The forward transform reads natural order and
  * writes the NTT-domain order: position i1 * N2 + i2 holds X(br(i1) + N1 br(i2))
  * with N1 = 2^ntt_log2N1 (from fft_ozaki_ntt_layout), N2 = N / N1 and br the
  * bit reversal on log2 N1 resp. log2 N2 bits.  The inverse reads that order

@@ -43,14 +43,14 @@ class FftOzakiError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("L", ctypes.c_int), ("mode", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p), ("embedding", ctypes.c_int),
-                ("accumulation", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("accumulation", ctypes.c_int), ("precision", ctypes.c_int), ("primes", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64), ("total_length", ctypes.c_int64), ("K", ctypes.c_int),
                 ("L", ctypes.c_int), ("mode", ctypes.c_int), ("num_length_classes", ctypes.c_int),
                 ("workspace_bytes", ctypes.c_int64), ("embedding", ctypes.c_int), ("accumulation", ctypes.c_int),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("primes", ctypes.c_int)]
 
 
 class _TInfo(ctypes.Structure):
@@ -128,21 +128,25 @@ class Plan:
     precision: "fp64" (complex128 in and out) or "fp32" (complex64 in and
     out: inputs widened exactly, the transform computed as for fp64 with this
     plan's K, each output component rounded once to binary32).  K defaults to
-    3 for fp64 and 2 (about 40 bits per part) for fp32."""
+    3 for fp64 and 2 (about 40 bits per part) for fp32.
+
+    primes: 2 (p0, p1) or 3 (p0, p1, p2: the CRT with d = 3 moduli, slices
+    of about 36 bits at n = 2^18; K then defaults to 2; batched mode only)."""
 
     def __init__(self, n: int | None = None, batch: int = 1, *, lengths=None, K: int | None = None, L: int = 3,
                  mode: str = "batched", autotune: bool = False, tune_cache: str | None = None,
-                 cyclic: bool = True, accumulation: str = "complex", precision: str = "fp64"):
+                 cyclic: bool = True, accumulation: str = "complex", precision: str = "fp64", primes: int = 2):
         if lengths is None:
             if n is None:
                 raise ValueError("give n (and batch) or lengths")
             lengths = [int(n)] * int(batch)
         self.lengths = [int(v) for v in lengths]
         if K is None:
-            K = 2 if precision == "fp32" else 3
-        self.K, self.L, self.mode, self.precision = K, L, mode, precision
+            K = 2 if precision == "fp32" or primes == 3 else 3
+        self.K, self.L, self.mode, self.precision, self.primes = K, L, mode, precision, primes
         opts = _Options(K, L, _MODES[mode], int(bool(autotune)), tune_cache.encode() if tune_cache else None,
-                        EMBED_AUTO if cyclic else EMBED_PADDED, _ACCUMS[accumulation], _PRECS[precision])
+                        EMBED_AUTO if cyclic else EMBED_PADDED, _ACCUMS[accumulation], _PRECS[precision],
+                        int(primes))
         arr = (ctypes.c_int64 * len(self.lengths))(*self.lengths)
         h = ctypes.c_void_p()
         _check(lib().fft_ozaki_plan_ex(ctypes.byref(h), arr, len(self.lengths), ctypes.byref(opts)))

@@ -12,7 +12,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libfft_ozaki.so")
-SOURCES = ["ntt_kernels.hip", "split_kernels.hip", "recombine_kernels.hip", "plan.hip"]
+SOURCES = ["ntt_kernels.hip", "split_kernels.hip", "recombine_kernels.hip", "crt3_kernels.hip", "plan.hip"]
 
 FLAGS = [
     "-O3",

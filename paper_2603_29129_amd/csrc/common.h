@@ -25,6 +25,11 @@ constexpr u32 P0_INV_MOD_P1 = 2113929091u;
 constexpr u64 PP = (u64)P0 * (u64)P1;           // 4504162581568552961 < 2^62
 constexpr u64 PP_HALF = (PP - 1) / 2;
 constexpr int MAX_LOG2_N = 24;                  // 2^24 = gcd(p0-1, p1-1)
+// Third modulus of the d = 3 CRT variant (Sec. 3.3 with three moduli):
+// p2 = 15*2^27 + 1 < 2^31, smallest primitive root 31.
+constexpr u32 P2 = 2013265921u;
+constexpr u32 G2 = 31u;
+constexpr int NPRIME_MAX = 3;
 
 // Splitting limits.
 constexpr int KMAX = 8;                         // cap on slices per vector
@@ -84,14 +89,14 @@ __host__ __device__ inline u32 shoup_companion(u32 w, u32 p) {
 // Twiddles for block NTTs: w^e for e < BLOCK_MAX/2 with w a primitive
 // BLOCK_MAX-th root, value and Shoup companion interleaved.
 struct TwBlock {
-  const uint2* fwd[2];   // per prime: (w^e, companion)
-  const uint2* inv[2];   // per prime: (w^-e, companion)
+  const uint2* fwd[NPRIME_MAX];   // per prime: (w^e, companion)
+  const uint2* inv[NPRIME_MAX];   // per prime: (w^-e, companion)
 };
 
 // Twiddles between the two passes of a length-N NTT, w_N^e = lo[e & 4095] * hi[e >> 12].
 struct TwStep {
-  const uint2* lo[2][2];   // [dir][prime], 4096 entries
-  const uint2* hi[2][2];   // [dir][prime], max(1, N/4096) entries
+  const uint2* lo[2][NPRIME_MAX];   // [dir][prime], 4096 entries
+  const uint2* hi[2][NPRIME_MAX];   // [dir][prime], max(1, N/4096) entries
 };
 
 // Input-independent data for one distinct length n: the chirp and the
@@ -174,6 +179,10 @@ struct TDesc {
   i64 X_off;               // u32 offset of the slice/NTT buffer [part][k][prime][N]
   i64 G_off;               // u32 offset of the group buffer [slot][prime][N]
   i64 Z_off;               // u32 offset of the compact outputs [slot][prime][zs]
+  // three-modulus plans: X_off / G_off locate this transform's prime-0 block
+  // ([part][k][N] / [slot][N]); the blocks of primes 1, 2 follow at strides
+  // xps / gps (u32 words)
+  i64 xps, gps;
 };
 
 }  // namespace fo

@@ -33,11 +33,33 @@ int build_block_twiddles(TwBlock* out, void** allocs);
 int build_step_twiddles(int logN, TwStep* out, void** allocs);
 
 // --- NTT launches -----------------------------------------------------------
+// Which vectors of a standalone launch hold data; the others are skipped.
+// Vector v = v0 + (index in the launch) belongs to transform tlist[v / per]
+// at local index r = v % per.  kind 0: every vector; kind 1 (slice
+// residues, r = part K + k): live while k < kx[part]; kind 2 (group sums,
+// r = component 2K^2 + g): live while g < ngroups[component].  A transform
+// with a status has no live vector.
+struct VecSel {
+  const TState* ts = nullptr;
+  const int* tlist = nullptr;
+  int per = 1, K = 1, kind = 0, v0 = 0;
+};
+__device__ __forceinline__ bool vec_live(const VecSel& sel, int idx) {
+  if (sel.kind == 0) return true;
+  const int v = sel.v0 + idx, r = v % sel.per;
+  const TState& s = sel.ts[sel.tlist[v / sel.per]];
+  if (s.status) return false;
+  if (sel.kind == 1) return r % sel.K < s.kx[r / sel.K];
+  const int SL = 2 * sel.K * sel.K;
+  return r % SL < s.ngroups[r / SL];
+}
+
 // Standalone transforms of `count` contiguous vectors (natural order in for the
 // forward transform, NTT-domain order out; the inverse takes NTT-domain order
-// and returns natural order multiplied by N^{-1}).
+// and returns natural order multiplied by N^{-1}); `sel` skips vectors.
 hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool inverse,
-                                 const NttGeom& g, const TwBlock& tb, const TwStep& ts, hipStream_t s);
+                                 const NttGeom& g, const TwBlock& tb, const TwStep& ts, hipStream_t s,
+                                 const VecSel& sel = VecSel{});
 
 // Pipeline: forward NTTs of the slice residues of the listed transforms
 // (vector index vi = (part*K + k)*2 + prime; only k < kx[part] are done).
@@ -83,6 +105,17 @@ hipError_t launch_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td,
 // Kernel slices: multiply by N^{-1} and build Shoup companions.
 hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s);
 
+// --- three moduli (d = 3 CRT) -------------------------------------------------
+// Kernel-spectra companions (Shoup) for W laid out [prime][part][k][N].
+hipError_t launch_companions3(const u32* W, u32* Wq, int K, int logN, hipStream_t s);
+// NTT-domain multiply-accumulate of every group of the listed transforms,
+// all three primes: G[prime * gps + slot N + e] (slot = component 2K^2 + g).
+hipError_t launch_mac3(const u32* X, u32* G, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                       const int* tlist, int count, int K, int logN, hipStream_t s);
+// Garner CRT (d = 3), exact recombination, postmultiply, output.
+hipError_t launch_recombine3(const u32* G, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                             const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s);
+
 // --- split / chirp / groups / recombination --------------------------------
 hipError_t launch_chirp(double2* chirp, int n, int* flag, hipStream_t s);
 hipError_t launch_reset(TState* ts, const int* tlist, int count, hipStream_t s);
@@ -95,7 +128,7 @@ hipError_t launch_split_plan(const TDesc* td, TState* ts, const KernelDesc* kd, 
                              hipStream_t s);
 hipError_t launch_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts,
                                 const int* tlist, int count, int nmax, int K, bool kernel_mode,
-                                hipStream_t s);
+                                hipStream_t s, int np = 2);
 hipError_t launch_split_check(const TDesc* td, TState* ts, const int* tlist, int count, int K,
                               hipStream_t s);
 hipError_t launch_groups(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist,

@@ -40,7 +40,7 @@
 
 namespace fo {
 
-__device__ __forceinline__ u32 prime_of(int i) { return i ? P1 : P0; }
+__device__ __forceinline__ u32 prime_of(int i) { return i == 0 ? P0 : (i == 1 ? P1 : P2); }
 __device__ __forceinline__ u32 bitrev(u32 v, int bits) { return bits ? (__brev(v) >> (32 - bits)) : 0u; }
 
 // Row layout of a tile: vector v at v * ldr, element i at pad8(i) = i + 8 (i / 64)
@@ -269,13 +269,14 @@ __device__ __forceinline__ void load_block_tw(uint2* tw, const uint2* __restrict
   for (int e = threadIdx.x; e < half; e += blockDim.x) tw[e] = src[e << (LOG2_BLOCK_MAX - m)];
 }
 
-// floor(v 2^32 / p) for v < p, exactly.  p is one of the two NTT primes, so
-// 2^32 / p is a constant picked by a uniform select.  The binary64 product
+// floor(v 2^32 / p) for v < p, exactly.  p is one of the NTT primes, so
+// 2^32 / p is a constant picked by uniform selects.  The binary64 product
 // v (2^32 / p) is below 2^32 with an error under 2^-19, so its truncation is
 // off by at most one either way; one step on the sign and size of the exact
 // 64-bit remainder fixes it (a single select, no loop, no division).
 __device__ __forceinline__ u32 companion_dev(u32 v, u32 p) {
-  const double rp = p == P0 ? 4294967296.0 / (double)P0 : 4294967296.0 / (double)P1;
+  const double rp = p == P0 ? 4294967296.0 / (double)P0
+                   : (p == P1 ? 4294967296.0 / (double)P1 : 4294967296.0 / (double)P2);
   const u32 c = (u32)((double)v * rp);
   const long long r = (long long)(((u64)v << 32) - (u64)c * p);
   return r < 0 ? c - 1 : (r >= (long long)p ? c + 1 : c);
@@ -486,8 +487,10 @@ __device__ __forceinline__ void fwd_single_body(u32* vec, int valid, int prime, 
 // Standalone kernels (count contiguous vectors; blockIdx.z = vector).
 
 template <int M>
-__global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int prime, bool inverse, TwBlock tb) {
+__global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int prime, bool inverse, TwBlock tb,
+                                                             VecSel sel) {
   extern __shared__ u32 smem[];
+  if (!vec_live(sel, blockIdx.z)) return;
   constexpr int logN = M, N = 1 << logN;
   u32* vec = data + ((size_t)blockIdx.z << logN);
   if (!inverse) {
@@ -508,23 +511,29 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int prime
 }
 
 template <int M1>
-__global__ void __launch_bounds__(COL_THREADS) k_std_fwd_cols(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
+__global__ void __launch_bounds__(COL_THREADS) k_std_fwd_cols(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts,
+                                                               VecSel sel) {
   extern __shared__ u32 smem[];
+  if (!vec_live(sel, blockIdx.z)) return;
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   fwd_cols_body<M1>(vec, 1 << g.logN, prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[prime], smem);
 }
 
 template <int M2>
-__global__ void __launch_bounds__(NTT_THREADS) k_std_fwd_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
+__global__ void __launch_bounds__(NTT_THREADS) k_std_fwd_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts,
+                                                               VecSel sel) {
   extern __shared__ u32 smem[];
+  if (!vec_live(sel, blockIdx.z)) return;
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   fwd_rows_body<M2>(vec, prime, g, blockIdx.x << g.lrows, tb.fwd[prime], ts.lo[0][prime], ts.hi[0][prime], smem);
 }
 
 // Inverse row pass (standalone): DIT rows then w_N^{-j2 k1}.
 template <int M2>
-__global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
+__global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts,
+                                                               VecSel sel) {
   extern __shared__ u32 smem[];
+  if (!vec_live(sel, blockIdx.z)) return;
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   const u32 p = prime_of(prime);
   constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
@@ -549,8 +558,9 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int pri
 
 // Inverse column pass (standalone): DIT columns, times N^{-1}, natural order.
 template <int M1>
-__global__ void __launch_bounds__(COL_THREADS) k_std_inv_cols(u32* data, int prime, NttGeom g, TwBlock tb) {
+__global__ void __launch_bounds__(COL_THREADS) k_std_inv_cols(u32* data, int prime, NttGeom g, TwBlock tb, VecSel sel) {
   extern __shared__ u32 smem[];
+  if (!vec_live(sel, blockIdx.z)) return;
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   const u32 p = prime_of(prime);
   constexpr int m1 = M1;
@@ -1594,7 +1604,7 @@ static hipError_t big_lds(const void* fn) {
 }
 
 hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool inverse, const NttGeom& g,
-                                 const TwBlock& tb, const TwStep& ts, hipStream_t s) {
+                                 const TwBlock& tb, const TwStep& ts, hipStream_t s, const VecSel& sel) {
   if (count <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
   if (!g.two_pass()) {
@@ -1602,7 +1612,7 @@ hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool
           constexpr int M = decltype(mc)::value;
           if ((e = big_lds((const void*)k_std_single<M>)) != hipSuccess) return;
           hipLaunchKernelGGL(k_std_single<M>, dim3(1, 1, count), dim3(NTT_THREADS), smem_single(logN), s, data, prime,
-                             inverse, tb);
+                             inverse, tb, sel);
         }))
       return hipErrorInvalidValue;
     return e != hipSuccess ? e : hipGetLastError();
@@ -1612,20 +1622,20 @@ hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool
     constexpr int M1 = decltype(mc)::value;
     if (!inverse) {
       if ((e = big_lds((const void*)k_std_fwd_cols<M1>)) != hipSuccess) return;
-      hipLaunchKernelGGL(k_std_fwd_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, ts);
+      hipLaunchKernelGGL(k_std_fwd_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, ts, sel);
     } else {
       if ((e = big_lds((const void*)k_std_inv_cols<M1>)) != hipSuccess) return;
-      hipLaunchKernelGGL(k_std_inv_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb);
+      hipLaunchKernelGGL(k_std_inv_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, sel);
     }
   };
   auto rows = [&](auto mc) {
     constexpr int M2 = decltype(mc)::value;
     if (!inverse) {
       if ((e = big_lds((const void*)k_std_fwd_rows<M2>)) != hipSuccess) return;
-      hipLaunchKernelGGL(k_std_fwd_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
+      hipLaunchKernelGGL(k_std_fwd_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts, sel);
     } else {
       if ((e = big_lds((const void*)k_std_inv_rows<M2>)) != hipSuccess) return;
-      hipLaunchKernelGGL(k_std_inv_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
+      hipLaunchKernelGGL(k_std_inv_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts, sel);
     }
   };
   if (!inverse) {
@@ -1800,7 +1810,7 @@ static u32 powmod(u64 b, u64 e, u32 p) {
 }
 
 static u32 root_of_unity(int prime, u64 N) {
-  const u32 p = prime ? P1 : P0, gen = prime ? G1 : G0;
+  const u32 p = prime == 0 ? P0 : (prime == 1 ? P1 : P2), gen = prime == 0 ? G0 : (prime == 1 ? G1 : G2);
   return powmod(gen, (u64)(p - 1) / N, p);
 }
 
@@ -1820,8 +1830,8 @@ static hipError_t upload_powers(uint2** dst, u32 w, u32 count, u32 p) {
 }
 
 int build_block_twiddles(TwBlock* out, void** allocs) {
-  for (int prime = 0; prime < 2; ++prime) {
-    const u32 p = prime ? P1 : P0;
+  for (int prime = 0; prime < NPRIME_MAX; ++prime) {
+    const u32 p = prime == 0 ? P0 : (prime == 1 ? P1 : P2);
     const u32 w = root_of_unity(prime, BLOCK_MAX);
     const u32 wi = powmod(w, p - 2, p);
     uint2 *f = nullptr, *iv = nullptr;
@@ -1839,8 +1849,8 @@ int build_step_twiddles(int logN, TwStep* out, void** allocs) {
   const u64 N = 1ull << logN;
   const u32 nhi = N > 4096 ? (u32)(N >> 12) : 1u;
   int a = 0;
-  for (int prime = 0; prime < 2; ++prime) {
-    const u32 p = prime ? P1 : P0;
+  for (int prime = 0; prime < NPRIME_MAX; ++prime) {
+    const u32 p = prime == 0 ? P0 : (prime == 1 ? P1 : P2);
     const u32 w = root_of_unity(prime, N);
     const u32 wi = powmod(w, p - 2, p);
     for (int dir = 0; dir < 2; ++dir) {

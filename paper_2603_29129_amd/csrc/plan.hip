@@ -42,12 +42,16 @@ static int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(FFT_OZAKI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Split width of Sec. 4.4: the largest alpha with 2 L n 4^alpha <= p0 p1,
-// i.e. alpha = floor((log2(p0 p1 / 2) - log2(L n)) / 2) evaluated exactly.
-static int alpha_for(i64 n, int L) {
-  const unsigned __int128 P = (unsigned __int128)PP;
+// Split width of Sec. 4.4: the largest alpha with 2 L n 4^alpha <= P, i.e.
+// alpha = floor((log2(P / 2) - log2(L n)) / 2) evaluated exactly, with P the
+// product of the np moduli (p0 p1, or p0 p1 p2 for the d = 3 CRT).
+static unsigned __int128 modulus_product(int np) {
+  return np == 3 ? (unsigned __int128)PP * P2 : (unsigned __int128)PP;
+}
+static int alpha_for(i64 n, int L, int np = 2) {
+  const unsigned __int128 P = modulus_product(np);
   int a = -1;
-  for (int c = 0; c < 40; ++c) {
+  for (int c = 0; c < 50; ++c) {
     const unsigned __int128 v = ((unsigned __int128)2 * (unsigned)L * (u64)n) << (2 * c);
     if (v > P) break;
     a = c;
@@ -60,9 +64,9 @@ static int alpha_for(i64 n, int L) {
 // at most n 4^alpha in magnitude (n terms of two alpha-bit integers), is
 // recovered exactly by the symmetric CRT (Sec. 3.3, Sec. 4.4).  At least L
 // by the choice of alpha.
-static int acc_limit_for(i64 n, int alpha) {
+static int acc_limit_for(i64 n, int alpha, int np = 2) {
   const unsigned __int128 unit = (unsigned __int128)(u64)n << (2 * alpha);
-  const unsigned __int128 lim = (unsigned __int128)PP_HALF / unit;
+  const unsigned __int128 lim = ((modulus_product(np) - 1) / 2) / unit;
   return lim > (unsigned __int128)MAX_MEMBERS ? MAX_MEMBERS : (int)lim;
 }
 
@@ -96,6 +100,8 @@ struct LengthClass {
   std::vector<int> tids;
   int* d_tlist = nullptr;
   int nmax = 0;
+  // three moduli: the class's slice and group buffers, prime by prime
+  i64 x3_base = 0, x3_ps = 0, g3_base = 0, g3_ps = 0;
 };
 
 struct GraphEntry {
@@ -114,6 +120,7 @@ struct fft_ozaki_plan_s {
   bool cyclic = true;               // FFT_OZAKI_EMBED_AUTO
   int accumulation = FFT_OZAKI_ACCUM_COMPLEX;
   int precision = FFT_OZAKI_PREC_FP64;  // FP32: complex64 in / out
+  int primes = 2;                   // CRT moduli: 2 (p0, p1) or 3 (p0, p1, p2)
   std::string tune_cache;
   std::vector<fo::i64> lengths;
   fo::i64 total = 0;
@@ -269,12 +276,12 @@ static int autotune_geom(fft_ozaki_plan_s* p, int logN, NttGeom* out) {
 static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   const i64 n = kh.n;
   const size_t N = (size_t)1 << kh.logN;
-  const int K = p->K;
+  const int K = p->K, np = p->primes;
   int rc;
   if ((rc = dmalloc(p, (void**)&kh.chirp, sizeof(double2) * n))) return rc;
-  if ((rc = dmalloc(p, (void**)&kh.W, 4 * (size_t)(4 * K) * N))) return rc;
-  if ((rc = dmalloc(p, (void**)&kh.Wq, 4 * (size_t)(4 * K) * N))) return rc;
-  HIPCHK(hipMemset(kh.W, 0, 4 * (size_t)(4 * K) * N));
+  if ((rc = dmalloc(p, (void**)&kh.W, 4 * (size_t)(2 * np * K) * N))) return rc;
+  if ((rc = dmalloc(p, (void**)&kh.Wq, 4 * (size_t)(2 * np * K) * N))) return rc;
+  HIPCHK(hipMemset(kh.W, 0, 4 * (size_t)(2 * np * K) * N));
   int* flag = nullptr;
   double2* xp = nullptr;
   TState* ts = nullptr;
@@ -294,6 +301,7 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   h.logN = kh.logN;
   h.alpha = kh.alpha;
   h.kd = 0;
+  h.xps = (i64)(2 * K) * (i64)N;         // three moduli: W laid out [prime][part][k][N]
   KernelDesc hk{};
   hk.n = (int)n;
   hk.N = (int)N;
@@ -309,7 +317,7 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   HIPCHK(launch_premul(nullptr, xp, td, kd, ts, tl, 1, (int)n, 0, true, 0, nullptr));
   HIPCHK(launch_split_plan(td, ts, kd, tl, 1, K, nullptr));
   for (int r = 0; r < K; ++r) {
-    HIPCHK(launch_split_extract(xp, kh.W, td, ts, tl, 1, (int)n, K, true, nullptr));
+    HIPCHK(launch_split_extract(xp, kh.W, td, ts, tl, 1, (int)n, K, true, nullptr, np));
     HIPCHK(launch_split_check(td, ts, tl, 1, K, nullptr));
   }
   TState hs;
@@ -324,8 +332,16 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   }
   // forward NTTs of the kernel slices (all N positions populated)
   NttGeom g = ntt_geom(kh.logN);
-  HIPCHK(launch_fwd_pipeline(kh.W, td, ts, tl, 1, K, true, 0, 4 * K, g, p->tb, step_for(p, kh.logN), nullptr));
-  HIPCHK(launch_kernel_finish(kh.W, kh.Wq, K, kh.logN, nullptr));
+  if (np == 3) {
+    // prime by prime; the standalone inverse applies N^{-1} itself
+    for (int q = 0; q < 3; ++q)
+      HIPCHK(launch_ntt_standalone(kh.W + (size_t)q * h.xps, kh.logN, q, 2 * K, false, g, p->tb,
+                                   step_for(p, kh.logN), nullptr));
+    HIPCHK(launch_companions3(kh.W, kh.Wq, K, kh.logN, nullptr));
+  } else {
+    HIPCHK(launch_fwd_pipeline(kh.W, td, ts, tl, 1, K, true, 0, 4 * K, g, p->tb, step_for(p, kh.logN), nullptr));
+    HIPCHK(launch_kernel_finish(kh.W, kh.Wq, K, kh.logN, nullptr));
+  }
   HIPCHK(hipDeviceSynchronize());
   (void)idx;
   (void)hipFree(flag);
@@ -341,7 +357,7 @@ static int build_plan(fft_ozaki_plan_s* p) {
   const int K = p->K;
   const int count = (int)p->lengths.size();
   HIPCHK(hipGetDevice(&p->device));
-  void* tw_allocs[4];
+  void* tw_allocs[2 * NPRIME_MAX];
   if (build_block_twiddles(&p->tb, tw_allocs)) return fail(FFT_OZAKI_ERR_NOMEM, "twiddle tables");
   for (void* a : tw_allocs) p->allocs.push_back(a);
   // distinct lengths and N classes
@@ -352,7 +368,7 @@ static int build_plan(fft_ozaki_plan_s* p) {
       KernelHost kh;
       kh.n = n;
       kh.logN = conv_log2(n, p->cyclic);
-      kh.alpha = alpha_for(n, p->L);
+      kh.alpha = alpha_for(n, p->L, p->primes);
       kidx[n] = (int)p->kernels.size();
       p->kernels.push_back(kh);
     }
@@ -366,7 +382,7 @@ static int build_plan(fft_ozaki_plan_s* p) {
   }
   for (auto& lc : p->classes) {
     if (ntt_geom(lc.logN).two_pass() && !p->steps.count(lc.logN)) {
-      void* sa[8];
+      void* sa[4 * NPRIME_MAX];
       TwStep st{};
       if (build_step_twiddles(lc.logN, &st, sa)) return fail(FFT_OZAKI_ERR_NOMEM, "step twiddles");
       for (void* a : sa) p->allocs.push_back(a);
@@ -391,9 +407,9 @@ static int build_plan(fft_ozaki_plan_s* p) {
     d.n = (int)n;
     d.logN = conv_log2(n, p->cyclic);
     d.N = 1 << d.logN;
-    d.alpha = alpha_for(n, p->L);
+    d.alpha = alpha_for(n, p->L, p->primes);
     d.acc_mode = p->accumulation == FFT_OZAKI_ACCUM_COMPLEX ? ACC_COMPLEX : ACC_PER_CONV;
-    d.acc_limit = d.acc_mode == ACC_COMPLEX ? acc_limit_for(n, d.alpha) : p->L;
+    d.acc_limit = d.acc_mode == ACC_COMPLEX ? acc_limit_for(n, d.alpha, p->primes) : p->L;
     d.kd = kidx[n];
     d.zs = (int)((n + 3) & ~(i64)3);
     d.io_off = io;
@@ -402,13 +418,35 @@ static int build_plan(fft_ozaki_plan_s* p) {
     d.G_off = go;
     d.Z_off = zo;
     io += n;
-    xo += (i64)(4 * K) << d.logN;
-    if (ntt_geom(d.logN).two_pass()) go += (8 * SL) << d.logN;
-    zo += 8 * SL * (i64)d.zs;
+    if (p->primes == 2) {
+      xo += (i64)(4 * K) << d.logN;
+      if (ntt_geom(d.logN).two_pass()) go += (8 * SL) << d.logN;
+      zo += 8 * SL * (i64)d.zs;
+    }
     p->td.push_back(d);
     LengthClass& lc = p->classes[cidx[d.logN]];
     lc.tids.push_back(t);
     lc.nmax = std::max<int>(lc.nmax, (int)n);
+  }
+  if (p->primes == 3) {
+    // per class, prime by prime: slice spectra [prime][transform][part][k][N]
+    // and group sums [prime][transform][slot][N] (4 K^2 slots)
+    for (auto& lc : p->classes) {
+      const i64 N = (i64)1 << lc.logN, T = (i64)lc.tids.size();
+      lc.x3_base = xo;
+      lc.x3_ps = T * 2 * K * N;
+      lc.g3_base = go;
+      lc.g3_ps = T * 4 * SL * N;
+      for (i64 i = 0; i < T; ++i) {
+        TDesc& d = p->td[lc.tids[i]];
+        d.X_off = lc.x3_base + i * 2 * K * N;
+        d.xps = lc.x3_ps;
+        d.G_off = lc.g3_base + i * 4 * SL * N;
+        d.gps = lc.g3_ps;
+      }
+      xo += 3 * lc.x3_ps;
+      go += 3 * lc.g3_ps;
+    }
   }
   p->total = io;
   for (auto& lc : p->classes)
@@ -497,9 +535,67 @@ static int enqueue_batched(fft_ozaki_plan_s* p, const void* in, void* out, int d
   return FFT_OZAKI_OK;
 }
 
+// Standalone NTTs of `count` vectors at data, in launches of at most 65535
+// vectors (the grid's z extent); sel numbers the vectors from 0 across them.
+static int ntt_chunked(u32* data, int logN, int prime, i64 count, bool inverse, const NttGeom& g, const TwBlock& tb,
+                       const TwStep& st, hipStream_t s, VecSel sel) {
+  for (i64 v0 = 0; v0 < count; v0 += 65535) {
+    const int c = (int)std::min<i64>(65535, count - v0);
+    sel.v0 = (int)v0;
+    HIPCHK(launch_ntt_standalone(data + ((size_t)v0 << logN), logN, prime, c, inverse, g, tb, st, s, sel));
+  }
+  return FFT_OZAKI_OK;
+}
+
+// The launch sequence of a three-modulus plan (captured like the two-modulus
+// one): premultiply and split as there, then per length class and prime the
+// forward NTTs of the live slice vectors, the NTT-domain multiply-accumulate,
+// the inverse NTTs of the live group vectors, and Garner (d = 3) with the
+// exact recombination and postmultiply.
+static int enqueue_batched3(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
+  const int K = p->K, count = (int)p->td.size();
+  HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
+  for (auto& lc : p->classes)
+    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
+                         io32_of(p), s));
+  HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
+  for (int r = 0; r < K; ++r) {
+    for (auto& lc : p->classes)
+      HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s,
+                                  3));
+    HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
+  }
+  HIPCHK(launch_groups(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, p->L, s));
+  for (auto& lc : p->classes) {
+    const i64 T = (i64)lc.tids.size();
+    const TwStep& st = step_for(p, lc.logN);
+    VecSel xs;
+    xs.ts = p->d_ts;
+    xs.tlist = lc.d_tlist;
+    xs.per = 2 * K;
+    xs.K = K;
+    xs.kind = 1;
+    VecSel gs = xs;
+    gs.per = 4 * K * K;
+    gs.kind = 2;
+    int rc;
+    for (int q = 0; q < 3; ++q)
+      if ((rc = ntt_chunked(p->X + lc.x3_base + q * lc.x3_ps, lc.logN, q, T * 2 * K, false, lc.geom, p->tb, st, s, xs)))
+        return rc;
+    HIPCHK(launch_mac3(p->X, p->G, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, K, lc.logN, s));
+    for (int q = 0; q < 3; ++q)
+      if ((rc = ntt_chunked(p->G + lc.g3_base + q * lc.g3_ps, lc.logN, q, T * 4 * K * K, true, lc.geom, p->tb, st, s,
+                            gs)))
+        return rc;
+    HIPCHK(launch_recombine3(p->G, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, lc.nmax, K, dir, io32_of(p),
+                             s));
+  }
+  return FFT_OZAKI_OK;
+}
+
 static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
   for (auto& lc : p->classes)
-    if (fused_rows_ok(lc.geom, p->K)) p->x_rows_pending = true;
+    if (p->primes == 2 && fused_rows_ok(lc.geom, p->K)) p->x_rows_pending = true;
   for (auto& g : p->graphs) {
     if (g.in == in && g.out == out && g.dir == dir) {
       HIPCHK(hipGraphLaunch(g.exec, s));
@@ -515,7 +611,7 @@ static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, 
   (void)hipEventDestroy(ev);
   hipGraph_t graph;
   HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-  int rc = enqueue_batched(p, in, out, dir, p->cap);
+  int rc = p->primes == 3 ? enqueue_batched3(p, in, out, dir, p->cap) : enqueue_batched(p, in, out, dir, p->cap);
   hipError_t ce = hipStreamEndCapture(p->cap, &graph);
   if (rc) return rc;
   if (ce != hipSuccess) return fail(FFT_OZAKI_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
@@ -670,6 +766,7 @@ int fft_ozaki_default_options(fft_ozaki_options* opt) {
   opt->embedding = FFT_OZAKI_EMBED_AUTO;
   opt->accumulation = FFT_OZAKI_ACCUM_COMPLEX;
   opt->precision = FFT_OZAKI_PREC_FP64;
+  opt->primes = 2;
   return FFT_OZAKI_OK;
 }
 
@@ -693,13 +790,17 @@ int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t co
     return fail(FFT_OZAKI_ERR_INVALID, "accumulation must be 0 (per convolution) or 1 (complex)");
   if (o.precision != FFT_OZAKI_PREC_FP64 && o.precision != FFT_OZAKI_PREC_FP32)
     return fail(FFT_OZAKI_ERR_INVALID, "precision must be 0 (binary64) or 1 (binary32)");
+  if (o.primes != 2 && o.primes != 3) return fail(FFT_OZAKI_ERR_INVALID, "primes must be 2 or 3");
+  if (o.primes == 3 && o.mode != FFT_OZAKI_MODE_BATCHED)
+    return fail(FFT_OZAKI_ERR_UNSUPPORTED, "three moduli are served by the batched mode only");
   i64 total = 0;
   for (int64_t i = 0; i < count; ++i) {
     const i64 n = lengths[i];
     if (n < 1) return fail(FFT_OZAKI_ERR_INVALID, "lengths must be >= 1");
     if (conv_log2(n, cyclic) > MAX_LOG2_N) return fail(FFT_OZAKI_ERR_INVALID, "convolution length exceeds 2^24");
-    const int a = alpha_for(n, o.L);
-    if (a < 1 || a > 30) return fail(FFT_OZAKI_ERR_INVALID, "split width alpha < 1 for this n and L");
+    const int a = alpha_for(n, o.L, o.primes);
+    if (a < 1 || a > (o.primes == 3 ? 46 : 30))
+      return fail(FFT_OZAKI_ERR_INVALID, "split width alpha < 1 for this n and L");
     total += n;
   }
   if (total > ((i64)1 << 31)) return fail(FFT_OZAKI_ERR_INVALID, "total length too large");
@@ -712,6 +813,7 @@ int fft_ozaki_plan_ex(fft_ozaki_plan_t* plan, const int64_t* lengths, int64_t co
   p->cyclic = cyclic;
   p->accumulation = o.accumulation;
   p->precision = o.precision;
+  p->primes = o.primes;
   p->tune_cache = o.tune_cache ? o.tune_cache : "";
   p->lengths.assign(lengths, lengths + count);
   int rc = build_plan(p);
@@ -772,6 +874,7 @@ int fft_ozaki_query(fft_ozaki_plan_t plan, fft_ozaki_info* info) {
   info->embedding = plan->cyclic ? FFT_OZAKI_EMBED_AUTO : FFT_OZAKI_EMBED_PADDED;
   info->accumulation = plan->accumulation;
   info->precision = plan->precision;
+  info->primes = plan->primes;
   return FFT_OZAKI_OK;
 }
 
@@ -800,12 +903,12 @@ int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_tr
       info->Ex[part][k] = k < hs.kx[part] ? hs.E[part][k] : 0;
       info->Ew[part][k] = kh.Ew[part][k];
     }
-    fr += 2 * hs.kx[part];
-    fo_ += 2 * kh.kw[part];
+    fr += plan->primes * hs.kx[part];
+    fo_ += plan->primes * kh.kw[part];
   }
   for (int tg = 0; tg < 2; ++tg) {
     info->ngroups[tg] = hs.ngroups[tg];
-    iv += 2 * hs.ngroups[tg];
+    iv += plan->primes * hs.ngroups[tg];
   }
   info->acc_limit = d.acc_limit;
   info->xsh[0] = hs.xsh[0];
@@ -826,6 +929,8 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
   const int K = plan->K;
   const void* src = nullptr;
   size_t sz = 0;
+  if (plan->primes == 3 && stage >= 2 && stage <= 4)
+    return fail(FFT_OZAKI_ERR_UNSUPPORTED, "stages 2-4 are laid out for two moduli");
   switch (stage) {
     case 1: src = plan->xp + d.xp_off; sz = sizeof(double2) * (size_t)d.n; break;
     case 2: src = plan->X + d.X_off; sz = 4 * ((size_t)(4 * K) << d.logN); break;
@@ -872,6 +977,7 @@ int fft_ozaki_profile_stage(fft_ozaki_plan_t plan, int stage, int reps, void* st
   g_err.clear();
   if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
   if (plan->mode != FFT_OZAKI_MODE_BATCHED) return fail(FFT_OZAKI_ERR_INVALID, "stage profiling needs the batched mode");
+  if (plan->primes != 2) return fail(FFT_OZAKI_ERR_UNSUPPORTED, "stage profiling covers two-modulus plans");
   if (!plan->last_in) return fail(FFT_OZAKI_ERR_INVALID, "execute the plan once before profiling");
   if (reps < 1) return fail(FFT_OZAKI_ERR_INVALID, "reps must be >= 1");
   for (int r = 0; r < reps; ++r) {
@@ -908,7 +1014,7 @@ int fft_ozaki_ntt_layout(int log2N, int* log2N1) {
 
 int fft_ozaki_ntt(int prime, int log2N, int64_t count, void* data, int inverse, void* stream) {
   g_err.clear();
-  if (prime < 0 || prime > 1) return fail(FFT_OZAKI_ERR_INVALID, "prime must be 0 or 1");
+  if (prime < 0 || prime > 2) return fail(FFT_OZAKI_ERR_INVALID, "prime must be 0, 1 or 2");
   if (log2N < 0 || log2N > MAX_LOG2_N) return fail(FFT_OZAKI_ERR_INVALID, "log2N out of range");
   if (count < 0 || count > 65535) return fail(FFT_OZAKI_ERR_INVALID, "count must be in [0, 65535]");
   if (!data && count) return fail(FFT_OZAKI_ERR_INVALID, "data is NULL");
@@ -921,12 +1027,12 @@ int fft_ozaki_ntt(int prime, int log2N, int64_t count, void* data, int inverse, 
     std::lock_guard<std::mutex> lk(g_std_mu);
     StdTables& T = g_std[dev];
     if (!T.tb.fwd[0]) {
-      void* a[4];
+      void* a[2 * NPRIME_MAX];
       if (build_block_twiddles(&T.tb, a)) return fail(FFT_OZAKI_ERR_NOMEM, "twiddle tables");
     }
     NttGeom g = ntt_geom(log2N);
     if (g.two_pass() && !T.steps.count(log2N)) {
-      void* a[8];
+      void* a[4 * NPRIME_MAX];
       TwStep s{};
       if (build_step_twiddles(log2N, &s, a)) return fail(FFT_OZAKI_ERR_NOMEM, "step twiddles");
       T.steps[log2N] = s;

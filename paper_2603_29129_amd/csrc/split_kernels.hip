@@ -326,10 +326,12 @@ hipError_t launch_split_plan(const TDesc* td, TState* ts, const KernelDesc* kd, 
 }
 
 // blockIdx.y = part.  Slices k >= start are written, times 2^xsh[part], as
-// residues mod p0, p1 into X[(part*K + k)*2 + prime][.]; input slices go to
+// residues mod p0, p1 into X[(part*K + k)*2 + prime][.] (NP = 2), or mod p0,
+// p1, p2 into X[prime * xps + (part*K + k) N] (NP = 3); input slices go to
 // positions j < n (the
 // NTT treats the rest as zero), kernel slices are placed by ZeroPad+-
 // (positions j and N - j), or at j alone when N = n (cyclic embedding).
+template <int NP>
 __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts, const int* tlist, int K,
                                 bool kernel_mode) {
   const int t = tlist[blockIdx.z];
@@ -358,6 +360,7 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
       const double x = (r + sigma) - sigma;
       r = r - x;
       if (k >= start) {
+        if constexpr (NP == 2) {
         const int a = (int)(x * ldexp(1.0, alpha - E + sh));   // |a| <= 2^(alpha + sh) <= 2^30 < p0, p1
         const u32 r0 = a < 0 ? (u32)(a + (int)P0) : (u32)a;
         const u32 r1 = a < 0 ? (u32)(a + (int)P1) : (u32)a;
@@ -369,10 +372,30 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
           v0[N - j] = r0;
           v1[N - j] = r1;
         }
+        } else {
+        // three moduli: |a| <= 2^alpha with alpha up to 45, kept in 64 bits
+        const long long a = (long long)(x * ldexp(1.0, alpha - E + sh));
+        const u32 r[3] = {(u32)(((a % (long long)P0) + P0) % P0), (u32)(((a % (long long)P1) + P1) % P1),
+                          (u32)(((a % (long long)P2) + P2) % P2)};
+        u32* v0 = Xb + (((size_t)(part * K + k)) << d.logN);
+        for (int q = 0; q < 3; ++q) {
+          u32* vq = v0 + q * d.xps;
+          vq[j] = r[q];
+          if (kernel_mode && j > 0 && N != (size_t)d.n) vq[N - j] = r[q];
+        }
+        }
         const u64 rb = abs_bits(r);
         if (rb > mloc[k]) mloc[k] = rb;
       }
     }
+  }
+  if constexpr (NP == 3) {
+    // the standalone NTTs of the three-modulus path read whole vectors and
+    // transform them in place: clear the zero padding n <= j < N each time
+    if (!kernel_mode)
+      for (size_t j = (size_t)d.n + blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (size_t)gridDim.x * blockDim.x)
+        for (int k = start; k < kend; ++k)
+          for (int q = 0; q < 3; ++q) Xb[((size_t)(part * K + k) << d.logN) + q * d.xps + j] = 0u;
   }
   for (int k = start; k < kend && k + 1 < K; ++k) {
     const u64 m = block_max_u64(mloc[k]);
@@ -381,10 +404,14 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
 }
 
 hipError_t launch_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts, const int* tlist, int count,
-                                int nmax, int K, bool kernel_mode, hipStream_t s) {
+                                int nmax, int K, bool kernel_mode, hipStream_t s, int np) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_split_extract, dim3(chunks_for(nmax), 2, count), dim3(256), 0, s, xp, X, td, ts, tlist, K,
-                     kernel_mode);
+  if (np == 3)
+    hipLaunchKernelGGL(k_split_extract<3>, dim3(chunks_for(nmax), 2, count), dim3(256), 0, s, xp, X, td, ts, tlist, K,
+                       kernel_mode);
+  else
+    hipLaunchKernelGGL(k_split_extract<2>, dim3(chunks_for(nmax), 2, count), dim3(256), 0, s, xp, X, td, ts, tlist, K,
+                       kernel_mode);
   return hipGetLastError();
 }
 

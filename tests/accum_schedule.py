@@ -34,8 +34,9 @@ P = nt.P0 * nt.P1
 MAX_MEMBERS = 128
 
 
-def acc_limit(n: int, alpha: int) -> int:
-    return min(MAX_MEMBERS, ((P - 1) // 2) // (n << (2 * alpha)))
+def acc_limit(n: int, alpha: int, primes: int = 2) -> int:
+    M = P if primes == 2 else nt.PPP
+    return min(MAX_MEMBERS, ((M - 1) // 2) // (n << (2 * alpha)))
 
 
 def _pairs(kA: int, kB: int, d: int):

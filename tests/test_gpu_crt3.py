@@ -1,0 +1,169 @@
+"""GPU parity of the three-modulus plans (d = 3 CRT) against the oracle.
+
+The oracle runs the same method with p0, p1, p2 (primes=3): the split width
+of Sec. 4.2 with the product of the three moduli and Garner's algorithm with
+d = 3.  Outputs must equal the oracle's (2 ulp per component allowed, 0
+expected: the method is deterministic); slice counts, exponents, group
+counts and NTT counts must equal the oracle's schedule."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import bluestein as bl
+from oracle import ntt as nt
+from oracle import ozaki as oz_or
+from tests.accum_schedule import acc_limit, component_schedule
+from tests.gpu_helpers import max_ulp
+
+pytestmark = pytest.mark.gpu
+ULP_TOL = 2
+_KP = {}
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _gpu(torch, x, dtype=np.complex128):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).cuda()
+
+
+def kplan3(n, K=2, L=3, cyclic=None):
+    cyclic = bl.is_pow2(n) if cyclic is None else (bool(cyclic) and bl.is_pow2(n))
+    key = (n, K, L, cyclic)
+    if key not in _KP:
+        _KP[key] = bl.KernelPlan(n, K, L, cyclic=cyclic, primes=3)
+    return _KP[key]
+
+
+def check_info(plan, b, tr, kp, complex_acc=True):
+    info = plan.transform_info(b)
+    assert info["status"] == tr["status"] and info["alpha"] == tr["alpha"] == kp.alpha
+    if tr["status"]:
+        return info
+    EX = [[E for _, E in tr["slices"][v]] for v in range(2)]
+    EW = [kp.exps(v) for v in range(2)]
+    assert info["Ex"] == EX and info["Ew"] == EW
+    limit = acc_limit(tr["n"], tr["alpha"], primes=3) if complex_acc else tr["L"]
+    assert info["acc_limit"] == limit
+    sched = component_schedule(EX, EW, tr["L"], "complex" if complex_acc else "per_conv", limit, alpha=tr["alpha"])
+    assert info["ngroups"] == [len(g) for g in sched]
+    assert info["forward_runtime"] == 3 * sum(info["kx"]) and info["inverse"] == 3 * sum(info["ngroups"])
+    assert info["forward_offline"] == 3 * sum(info["kw"])
+    return info
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 64, 100, 1000, 1024, 4096, 4097, 8192, 1 << 14])
+def test_forward_three_moduli(torch_mod, n):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = wl.paper_phi(n, 1.0, seed=n, batch=2)
+    plan = oz.Plan(n, 2, primes=3)
+    assert plan.info()["primes"] == 3 and plan.K == 2
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan3(n)
+    for b in range(2):
+        tr = bl.forward_trace(x[b], 2, 3, kp)
+        check_info(plan, b, tr, kp)
+        assert max_ulp(y[b], tr["y"]) <= ULP_TOL, b
+
+
+@pytest.mark.parametrize("K,L,accumulation,cyclic", [(3, 1, "per_conv", True), (1, 1, "complex", True),
+                                                     (3, 12, "complex", False), (4, 3, "per_conv", False)])
+def test_variants_three_moduli(torch_mod, K, L, accumulation, cyclic):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 1024
+    x = wl.paper_phi(n, 4.0, seed=K + L, batch=2)
+    plan = oz.Plan(n, 2, K=K, L=L, primes=3, accumulation=accumulation, cyclic=cyclic)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan3(n, K, L, cyclic)
+    assert plan.transform_info(0)["N"] == kp.N
+    for b in range(2):
+        tr = bl.forward_trace(x[b], K, L, kp)
+        check_info(plan, b, tr, kp, complex_acc=accumulation == "complex")
+        assert max_ulp(y[b], tr["y"]) <= ULP_TOL, b
+
+
+@pytest.mark.parametrize("direction", [1, 2])
+def test_inverse_adjoint_three_moduli(torch_mod, direction):
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    for n in (100, 4096):
+        x = wl.uniform(n, batch=1, seed=n)
+        plan = oz.Plan(n, 1, primes=3)
+        y = plan.execute(_gpu(torch, x), direction).cpu().numpy()
+        kp = kplan3(n)
+        want = bl.ifft(x[0], plan=kp) if direction == 1 else bl.adjoint(x[0], plan=kp)
+        assert max_ulp(y[0], want) <= ULP_TOL
+
+
+def test_mixed_lengths_and_special_inputs(torch_mod):
+    """Several length classes in one plan; a zero transform, one with a NaN
+    and one with half its entries 2^-300 times the others (K = 8: group
+    exponents spanning several hundred bits, the wide accumulator)."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    lengths = [1000, 4096, 17, 1000, 4096]
+    xs = [wl.paper_phi(n, 1.0, seed=i, batch=1)[0] for i, n in enumerate(lengths)]
+    xs[1][:] = 0
+    xs[2][5] = np.nan
+    xs[3][::2] *= 2.0 ** -300
+    plan = oz.Plan(lengths=lengths, K=8, primes=3)
+    y = plan.forward(_gpu(torch, np.concatenate(xs))).cpu().numpy()
+    off = 0
+    for b, n in enumerate(lengths):
+        yb = y[off:off + n]
+        off += n
+        kp = kplan3(n, 8, 3)
+        tr = bl.forward_trace(xs[b], 8, 3, kp)
+        check_info(plan, b, tr, kp)
+        if b == 2:
+            assert np.all(np.isnan(yb.real)) and np.all(np.isnan(yb.imag))
+            continue
+        if b == 3:
+            es = [e for conv in tr["group_z"] for (_z, e) in conv]
+            assert max(es) - min(es) > 300
+        assert max_ulp(yb, tr["y"]) <= ULP_TOL, b
+    assert np.all(y[1000:1000 + 4096] == 0)
+
+
+def test_binary32_three_moduli(torch_mod):
+    import paper_2603_29129_amd as oz
+    from tests.test_gpu_binary32 import max_ulp32
+    torch = torch_mod
+    n = 1000
+    x = wl.paper_phi(n, 1.0, seed=3, batch=2).astype(np.complex64)
+    plan = oz.Plan(n, 2, precision="fp32", primes=3)
+    y = plan.forward(_gpu(torch, x, np.complex64)).cpu().numpy()
+    for b in range(2):
+        assert max_ulp32(y[b], bl.fft_binary32(x[b], 2, 3, kplan3(n))) <= 1
+
+
+def test_headline_length_three_moduli(torch_mod):
+    """n = 2^18, K = 2 (alpha = 36): bit-exact against the oracle, and as
+    accurate against the long-double DFT as the two-modulus K = 3 plan."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 1 << 18
+    x = wl.wide_256k(seed=1, batch=1, n=n)
+    xd = _gpu(torch, x)
+    plan = oz.Plan(n, 1, primes=3)
+    y = plan.forward(xd).cpu().numpy()[0]
+    kp = kplan3(n)
+    assert kp.alpha == oz_or.alpha_crt(n, 3, nt.PPP) == 36
+    tr = bl.forward_trace(x[0], 2, 3, kp)
+    check_info(plan, 0, tr, kp)
+    assert max_ulp(y, tr["y"]) <= ULP_TOL
+    y2 = oz.Plan(n, 1).forward(xd).cpu().numpy()[0]
+    ref = np.fft.fft(x[0].astype(np.clongdouble))
+
+    def rel(v):
+        v = np.asarray(v).astype(np.clongdouble)
+        return float(np.sqrt(np.sum(np.abs(v - ref) ** 2)) / np.sqrt(np.sum(np.abs(ref) ** 2)))
+
+    assert rel(y) <= 1.5 * rel(y2) and rel(y) < 1e-15

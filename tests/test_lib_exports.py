@@ -59,14 +59,20 @@ def test_host_only_calls():
     opts = oz._Options(3, 3, 1, 0, None, 1, 2)                            # no such accumulation
     assert L.fft_ozaki_plan_ex(ctypes.byref(h), arr, 1, ctypes.byref(opts)) == -1
     assert b"accumulation" in L.fft_ozaki_last_error_message()
+    opts = oz._Options(3, 3, 1, 0, None, 1, 1, 0, 4)                      # no such number of moduli
+    assert L.fft_ozaki_plan_ex(ctypes.byref(h), arr, 1, ctypes.byref(opts)) == -1
+    assert b"primes" in L.fft_ozaki_last_error_message()
+    opts = oz._Options(2, 3, 0, 0, None, 1, 1, 0, 3)                      # three moduli, plain mode
+    assert L.fft_ozaki_plan_ex(ctypes.byref(h), arr, 1, ctypes.byref(opts)) == -4
     d = oz._Options()
     assert L.fft_ozaki_default_options(ctypes.byref(d)) == 0
     assert (d.K, d.L, d.mode, d.autotune, d.embedding) == (3, 3, 1, 0, oz.EMBED_AUTO)
-    assert d.accumulation == oz.ACCUM_COMPLEX
+    assert d.accumulation == oz.ACCUM_COMPLEX and d.primes == 2
     assert L.fft_ozaki_execute(None, None, None, 0, None) == -1
     assert L.fft_ozaki_destroy(None) == -1
     m = ctypes.c_int()
     assert L.fft_ozaki_ntt_layout(19, ctypes.byref(m)) == 0 and m.value == 10
     assert L.fft_ozaki_ntt_layout(12, ctypes.byref(m)) == 0 and m.value == 12
     assert L.fft_ozaki_ntt_layout(25, ctypes.byref(m)) == -1
-    assert L.fft_ozaki_ntt(2, 10, 1, None, 0, None) == -1
+    assert L.fft_ozaki_ntt(2, 10, 1, None, 0, None) == -1                 # data NULL
+    assert L.fft_ozaki_ntt(3, 10, 0, None, 0, None) == -1                 # no prime 3
