@@ -75,38 +75,73 @@ __device__ __forceinline__ void acc_add128(u64 (&acc)[W], u64 lo, i64 hi, int sh
 constexpr int SPAN_FAST3 = 64 * W_FAST - 104;
 
 // ---------------------------------------------------------------------------
-// NTT-domain multiply-accumulate: for every group g of component tg of the
+// NTT-domain multiply-accumulate: for every group g of component tg of a
 // transform, G[slot] = sum over its members (c, s, t) of +- X_pa(c)^s (.)
-// W_pb(c)^t mod p, the ImIm products (c = 1) subtracted.  blockIdx.y is the
-// prime, blockIdx.z the transform; the schedule reads are uniform per block.
+// W_pb(c)^t mod p, the ImIm products (c = 1) subtracted.  A block takes 256
+// positions of one prime (blockIdx.y) for a run of up to `tpr` transforms of
+// the class (blockIdx.z), so the kernel spectra are loaded once per run
+// (again only where the kernel changes).  Each thread keeps the values of
+// its position in its own LDS column ([vector][256], conflict-free); the
+// transform's walk is staged in LDS as operand offsets and sign per member.
 // Convolution c uses x' part ((c + 1) >> 1) & 1 and w* part c & 1.
-__global__ void k_mac3(const u32* X, u32* G, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                       const int* tlist, int K) {
-  const int t = tlist[blockIdx.z];
-  const TState& s = ts[t];
-  if (s.status) return;
-  const TDesc& d = td[t];
-  const KernelDesc& kk = kd[d.kd];
-  const int q = blockIdx.y, logN = d.logN, SL = 2 * K * K;
+constexpr int MAC3_THREADS = 256;
+__global__ void __launch_bounds__(MAC3_THREADS) k_mac3(const u32* __restrict__ X, u32* __restrict__ G,
+                                                       const TDesc* td, const TState* ts, const KernelDesc* kd,
+                                                       const int* tlist, int count, int K, int tpr) {
+  extern __shared__ u32 sm[];
+  const int V = 2 * K, SL = 2 * K * K, q = blockIdx.y;
   const u32 p = prime3_of(q);
-  const size_t N = (size_t)1 << logN, wps = (size_t)(2 * K) << logN;
-  const u32* Xb = X + d.X_off + q * d.xps;
-  const u32* Wb = kk.W + q * wps;
-  const u32* Qb = kk.Wq + q * wps;
-  u32* Gb = G + d.G_off + q * d.gps;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
+  u32* cx = sm + threadIdx.x;                          // column of this thread: vector v at v * 256
+  u32* cw = cx + V * MAC3_THREADS;
+  u32* cq = cw + V * MAC3_THREADS;
+  u32* code = sm + 3 * V * MAC3_THREADS;               // [component][walk position]
+  const int b0 = blockIdx.z * tpr, b1 = min(count, b0 + tpr);
+  int wkd = -1;
+  for (int b = b0; b < b1; ++b) {
+    const int t = tlist[b];
+    const TState& s = ts[t];
+    if (s.status) continue;
+    const TDesc& d = td[t];
+    const KernelDesc& kk = kd[d.kd];
+    const int logN = d.logN;
+    const size_t N = (size_t)1 << logN, e = blockIdx.x * (size_t)MAC3_THREADS + threadIdx.x;
+    const bool live = e < N;
+    __syncthreads();                                   // the previous transform's walk is consumed
+    const int nm0 = s.nmem[0], nm = nm0 + s.nmem[1];
+    for (int i = threadIdx.x; i < nm; i += MAC3_THREADS) {
+      const int tg = i >= nm0, m = i - tg * nm0, c = s.mc[tg][m];
+      const int xo = ((((c + 1) >> 1) & 1) * K + s.ms[tg][m]) * MAC3_THREADS;
+      const int wo = ((c & 1) * K + s.mt[tg][m]) * MAC3_THREADS;
+      code[tg * MAX_MEMBERS + m] = (u32)xo | ((u32)wo << 13) | (c == 1 ? 1u << 31 : 0u);
+    }
+    __syncthreads();
+    if (!live) continue;
+    if (d.kd != wkd) {
+      const size_t wps = (size_t)V << logN;
+      const u32* Wb = kk.W + q * wps;
+      const u32* Qb = kk.Wq + q * wps;
+      for (int v = 0; v < V; ++v)
+        if (v - (v >= K) * K < kk.kw[v >= K]) {
+          cw[v * MAC3_THREADS] = Wb[((size_t)v << logN) + e];
+          cq[v * MAC3_THREADS] = Qb[((size_t)v << logN) + e];
+        }
+      wkd = d.kd;
+    }
+    const u32* Xb = X + d.X_off + q * d.xps;
+    for (int v = 0; v < V; ++v)
+      if (v - (v >= K) * K < s.kx[v >= K]) cx[v * MAC3_THREADS] = Xb[((size_t)v << logN) + e];
+    u32* Gb = G + d.G_off + q * d.gps + e;
     for (int tg = 0; tg < 2; ++tg) {
       for (int g = 0; g < s.ngroups[tg]; ++g) {
         const int m0 = s.groups[tg][g].start, m1 = m0 + s.groups[tg][g].count;
         u32 acc = 0;
         for (int m = m0; m < m1; ++m) {
-          const int c = s.mc[tg][m], pa = ((c + 1) >> 1) & 1, pb = c & 1;
-          const u32 xv = Xb[((size_t)(pa * K + s.ms[tg][m]) << logN) + e];
-          const size_t wi = ((size_t)(pb * K + s.mt[tg][m]) << logN) + e;
-          const u32 pr = shoup_mul(xv, Wb[wi], Qb[wi], p);
-          acc = c == 1 ? sub_mod(acc, pr, p) : add_mod(acc, pr, p);
+          const u32 cd = code[tg * MAX_MEMBERS + m];
+          const int wo = (cd >> 13) & 0x1FFF;
+          const u32 pr = shoup_mul(cx[cd & 0x1FFF], cw[wo], cq[wo], p);
+          acc = (cd >> 31) ? sub_mod(acc, pr, p) : add_mod(acc, pr, p);
         }
-        Gb[((size_t)(tg * SL + g) << logN) + e] = acc;
+        Gb[(size_t)(tg * SL + g) << logN] = acc;
       }
     }
   }
@@ -117,6 +152,30 @@ __global__ void k_companions3(const u32* W, u32* Wq, size_t per_prime) {
   const size_t total = 3 * per_prime;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
     Wq[i] = shoup_companion(W[i], prime3_of((int)(i / per_prime)));
+}
+
+// Fast path: the sum in NL_FAST 32-bit limbs; a group value v (|v| < 2^92)
+// enters as v mod 2^62 (non-negative) at shift sh and v >> 62 (|.| < 2^31)
+// at sh + 62, each one add-with-carry chain (sh <= SPAN_FAST3 keeps both
+// inside the limbs).
+__device__ double recombine3_fast(const u32* G, const TDesc& d, const TState& s, int tg, int SL, int j) {
+  u32 acc[NL_FAST];
+#pragma unroll
+  for (int k = 0; k < NL_FAST; ++k) acc[k] = 0;
+  const int emin = s.emin[tg];
+  for (int g = 0; g < s.ngroups[tg]; ++g) {
+    const u32* z = G + d.G_off + ((size_t)(tg * SL + g) << d.logN) + j;
+    u64 lo;
+    i64 hi;
+    garner3(z[0], z[d.gps], z[2 * d.gps], lo, hi);
+    const int sh = s.groups[tg][g].e - emin;
+    limb_add(acc, (i64)(lo & 0x3FFFFFFFFFFFFFFFull), sh);
+    limb_add(acc, (hi << 2) | (i64)(lo >> 62), sh + 62);
+  }
+  u64 a64[W_FAST];
+#pragma unroll
+  for (int w = 0; w < W_FAST; ++w) a64[w] = (u64)acc[2 * w] | ((u64)acc[2 * w + 1] << 32);
+  return acc_round<W_FAST>(a64, emin);
 }
 
 // One component of y' at output j: the exact sum of the group values
@@ -158,8 +217,7 @@ __global__ void k_recombine3(const u32* G, void* out, const TDesc* td, const TSt
       const double pi = w1 ? recombine3_one<W_WIDE>(G, d, s, 1, SL, j) : recombine3_one<W_FAST>(G, d, s, 1, SL, j);
       o = finish(pr, pi, ch[j], dir, d.n);
     } else {
-      o = finish(recombine3_one<W_FAST>(G, d, s, 0, SL, j), recombine3_one<W_FAST>(G, d, s, 1, SL, j), ch[j], dir,
-                 d.n);
+      o = finish(recombine3_fast(G, d, s, 0, SL, j), recombine3_fast(G, d, s, 1, SL, j), ch[j], dir, d.n);
     }
     put_out(out, d.io_off + j, o, io32);
   }
@@ -180,8 +238,12 @@ hipError_t launch_companions3(const u32* W, u32* Wq, int K, int logN, hipStream_
 hipError_t launch_mac3(const u32* X, u32* G, const TDesc* td, const TState* ts, const KernelDesc* kd,
                        const int* tlist, int count, int K, int logN, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mac3, dim3(grid_for((size_t)1 << logN), 3, count), dim3(256), 0, s, X, G, td, ts, kd, tlist,
-                     K);
+  constexpr int TPR = 8;                                            // transforms per block
+  // operand columns (at most 48 KiB for K <= 8) and the two walks' codes
+  const size_t lds = sizeof(u32) * (3 * (size_t)(2 * K) * MAC3_THREADS + 2 * MAX_MEMBERS);
+  const unsigned bx = (unsigned)((((size_t)1 << logN) + MAC3_THREADS - 1) / MAC3_THREADS);
+  hipLaunchKernelGGL(k_mac3, dim3(bx, 3, (count + TPR - 1) / TPR), dim3(MAC3_THREADS), lds, s, X, G, td, ts, kd,
+                     tlist, count, K, TPR);
   return hipGetLastError();
 }
 
