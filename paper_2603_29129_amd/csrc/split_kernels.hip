@@ -487,12 +487,15 @@ __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
   for (int tg = 0; tg < 2; ++tg) {
     int np = 0, ng = 0, cnt = 0, gstart = 0, key = 0, cur = -1, load = 0;
     int emin = 0x7FFFFFFF, emax = -0x7FFFFFFF;
+    u64 ge[2] = {0, 0};                                 // walk positions closing a group
     auto close = [&]() {
       s.groups[tg][ng].start = gstart;
       s.groups[tg][ng].count = cnt;
       s.groups[tg][ng].e = key - 2 * d.alpha;
       emin = min(emin, key - 2 * d.alpha);
       emax = max(emax, key - 2 * d.alpha);
+      const int w = np - 1;
+      ge[w >> 6] |= 1ull << (w & 63);
       ++ng;
       gstart = np;
       cnt = 0;
@@ -531,11 +534,6 @@ __global__ void k_groups(const TDesc* td, TState* ts, const KernelDesc* kd, cons
     if (cnt > 0) close();
     s.nmem[tg] = np;
     s.ngroups[tg] = ng;
-    u64 ge[2] = {0, 0};
-    for (int g = 0; g < ng; ++g) {
-      const int w = s.groups[tg][g].start + s.groups[tg][g].count - 1;
-      ge[w >> 6] |= 1ull << (w & 63);
-    }
     s.gend[tg][0] = ge[0];
     s.gend[tg][1] = ge[1];
     s.emin[tg] = ng ? emin : 0;
