@@ -112,6 +112,14 @@ hipError_t launch_companions3(const u32* W, u32* Wq, int K, int logN, hipStream_
 // all three primes: G[prime * gps + slot N + e] (slot = component 2K^2 + g).
 hipError_t launch_mac3(const u32* X, u32* G, const TDesc* td, const TState* ts, const KernelDesc* kd,
                        const int* tlist, int count, int K, int logN, hipStream_t s);
+// Two-pass lengths: the multiply-accumulate fused into the inverse row pass
+// (rows of every live group to G, laid out as for launch_mac3), and the
+// inverse column pass alone (standalone kernels, `sel` skips vectors).
+hipError_t launch_mac3_rows(const u32* X, u32* G, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                            const int* tlist, int count, int K, const NttGeom& g, const TwBlock& tb, const TwStep& st,
+                            hipStream_t s);
+hipError_t launch_inv_cols_standalone(u32* data, int prime, int count, const NttGeom& g, const TwBlock& tb,
+                                      hipStream_t s, const VecSel& sel);
 // Garner CRT (d = 3), exact recombination, postmultiply, output.
 hipError_t launch_recombine3(const u32* G, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
                              const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s);

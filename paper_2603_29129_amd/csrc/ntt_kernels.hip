@@ -585,6 +585,94 @@ __global__ void __launch_bounds__(COL_THREADS) k_std_inv_cols(u32* data, int pri
   }
 }
 
+// Three-modulus plans, two-pass lengths: the NTT-domain multiply-accumulate
+// fused into the inverse row pass.  A workgroup takes nr rows (N2 positions
+// each) of one prime (blockIdx.y) of one transform (blockIdx.z).  For a chunk
+// of gch groups it forms every group's signed sum of its members' products
+// at those positions directly in the LDS tile (the operands of a position
+// staged in the thread's own LDS column, the transform's walk staged as
+// operand offsets and signs), runs the inverse row NTTs and the twiddles
+// w_N^{-j2 k1}, and stores the rows to the group buffer
+// G[prime * gps + slot N + position] for the standalone inverse column pass.
+// Slice spectra X[prime * xps + (part K + k) N + e], kernel spectra and
+// companions W, Wq[prime][part][k][N] (no N^{-1}: the column pass applies it).
+template <int M2>
+__global__ void __launch_bounds__(NTT_THREADS) k_mac3_rows(const u32* __restrict__ X, u32* __restrict__ G,
+                                                          const TDesc* td, const TState* ts, const KernelDesc* kd,
+                                                          const int* tlist, int K, NttGeom g, TwBlock tb, TwStep st,
+                                                          int lr, int gch, int toff) {
+  extern __shared__ u32 smem[];
+  const int t = tlist[blockIdx.z];
+  const TState& s = ts[t];
+  if (s.status) return;
+  const TDesc& d = td[t];
+  const KernelDesc& kk = kd[d.kd];
+  const int q = blockIdx.y;
+  const u32 p = prime_of(q);
+  constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2), TH = NTT_THREADS;
+  const int nr = 1 << lr, V = 2 * K, SL = 2 * K * K, logN = d.logN;
+  const u32 Nmask = (1u << logN) - 1;
+  uint2* tw = reinterpret_cast<uint2*>(smem);                // inverse block roots (N2 words)
+  u32* twmem = smem + N2;                                    // row twiddles
+  u32* code = twmem + ((rowtw_words(m2, nr) + 3) & ~3);      // the two walks, [component][position]
+  u32* col = code + 2 * MAX_MEMBERS + threadIdx.x;           // this thread's operand column: x, w, wq
+  u32* tile = smem + toff;                                   // gch * nr rows
+  load_block_tw(tw, tb.inv[q], m2);
+  const int i1_0 = blockIdx.x << lr;
+  RowTw rt;
+  build_rowtw(rt, twmem, nr, i1_0, g.m1, m2, Nmask, st.lo[1][q], st.hi[1][q], p);
+  const int nm0 = s.nmem[0], nm = nm0 + s.nmem[1];
+  for (int i = threadIdx.x; i < nm; i += TH) {
+    const int tg = i >= nm0, m = i - tg * nm0, c = s.mc[tg][m];
+    const int xo = ((((c + 1) >> 1) & 1) * K + s.ms[tg][m]) * TH;
+    const int wo = ((c & 1) * K + s.mt[tg][m]) * TH;
+    code[tg * MAX_MEMBERS + m] = (u32)xo | ((u32)wo << 13) | (c == 1 ? 1u << 31 : 0u);
+  }
+  __syncthreads();
+  const size_t base = (size_t)i1_0 << m2, wps = (size_t)V << logN;
+  const u32* Xb = X + d.X_off + q * d.xps + base;
+  const u32* Wb = kk.W + q * wps + base;
+  const u32* Qb = kk.Wq + q * wps + base;
+  u32* Gb = G + d.G_off + q * d.gps + base;
+  const int ng0 = s.ngroups[0], gtot = ng0 + s.ngroups[1];
+  for (int g0 = 0; g0 < gtot; g0 += gch) {
+    const int g1 = min(gtot, g0 + gch);
+    for (int idx = threadIdx.x; idx < (nr << m2); idx += TH) {
+      for (int v = 0; v < V; ++v) {
+        const int part = v >= K, k = v - part * K;
+        const size_t o = ((size_t)v << logN) + idx;
+        if (k < s.kx[part]) col[v * TH] = Xb[o];
+        if (k < kk.kw[part]) {
+          col[(V + v) * TH] = Wb[o];
+          col[(2 * V + v) * TH] = Qb[o];
+        }
+      }
+      const int r = idx >> m2, j2 = idx & (N2 - 1);
+      for (int gi = g0; gi < g1; ++gi) {
+        const int tg = gi >= ng0, gl = gi - tg * ng0;
+        const int m0 = s.groups[tg][gl].start, m1 = m0 + s.groups[tg][gl].count;
+        u32 acc = 0;
+        for (int m = m0; m < m1; ++m) {
+          const u32 cd = code[tg * MAX_MEMBERS + m];
+          const int wo = (cd >> 13) & 0x1FFF;
+          const u32 pr = shoup_mul(col[cd & 0x1FFF], col[V * TH + wo], col[2 * V * TH + wo], p);
+          acc = (cd >> 31) ? sub_mod(acc, pr, p) : add_mod(acc, pr, p);
+        }
+        tile[((gi - g0) * nr + r) * ldr + pad8(j2)] = acc;
+      }
+    }
+    __syncthreads();
+    block_ntt<M2, true, false>(tile, (g1 - g0) * nr, ldr, tw, p);
+    for (int idx = threadIdx.x; idx < (((g1 - g0) * nr) << m2); idx += TH) {
+      const int row = idx >> m2, j2 = idx & (N2 - 1), gi = g0 + row / nr, r = row - (row / nr) * nr;
+      const int tg = gi >= ng0, gl = gi - tg * ng0;
+      Gb[((size_t)(tg * SL + gl) << logN) + ((size_t)r << m2) + j2] = apply_rowtw(rt, tile[row * ldr + pad8(j2)], r,
+                                                                                  j2, m2, p);
+    }
+    __syncthreads();                                         // the tile is refilled by the next chunk
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pipeline kernels.  blockIdx.z indexes the transform list.
 
@@ -1647,6 +1735,44 @@ hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool
     if (e != hipSuccess) return e;
     if (!with_m<M1_LO, M1_HI>(g.m1, cols)) return hipErrorInvalidValue;
   }
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_mac3_rows(const u32* X, u32* G, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                            const int* tlist, int count, int K, const NttGeom& g, const TwBlock& tb, const TwStep& st,
+                            hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (!g.two_pass()) return hipErrorInvalidValue;
+  // one row per workgroup: every group of the transform in one chunk (up
+  // to about 40 KiB of LDS), so the operands are staged once
+  const int lr = 0, nr = 1 << lr, N2 = 1 << g.m2, ldr = row_ld(N2);
+  const int toff = N2 + ((rowtw_words(g.m2, nr) + 3) & ~3) + 2 * MAX_MEMBERS + 3 * (2 * K) * NTT_THREADS;
+  int gch = (10240 - toff) / (nr * ldr);
+  gch = std::max(1, std::min(gch, 4 * K * K));
+  const size_t lds = 4 * ((size_t)toff + (size_t)gch * nr * ldr);
+  hipError_t e = hipSuccess;
+  if (!with_m<M2_LO, M2_HI>(g.m2, [&](auto mc) {
+        constexpr int M2 = decltype(mc)::value;
+        if ((e = big_lds((const void*)k_mac3_rows<M2>)) != hipSuccess) return;
+        hipLaunchKernelGGL(k_mac3_rows<M2>, dim3(1u << (g.m1 - lr), 3, count), dim3(NTT_THREADS), lds, s, X, G, td,
+                           ts, kd, tlist, K, g, tb, st, lr, gch, toff);
+      }))
+    return hipErrorInvalidValue;
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_inv_cols_standalone(u32* data, int prime, int count, const NttGeom& g, const TwBlock& tb,
+                                      hipStream_t s, const VecSel& sel) {
+  if (count <= 0) return hipSuccess;
+  if (!g.two_pass()) return hipErrorInvalidValue;
+  const dim3 gc(1u << (g.m2 - g.lc), 1, count);
+  hipError_t e = hipSuccess;
+  if (!with_m<M1_LO, M1_HI>(g.m1, [&](auto mc) {
+        constexpr int M1 = decltype(mc)::value;
+        if ((e = big_lds((const void*)k_std_inv_cols<M1>)) != hipSuccess) return;
+        hipLaunchKernelGGL(k_std_inv_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, sel);
+      }))
+    return hipErrorInvalidValue;
   return e != hipSuccess ? e : hipGetLastError();
 }
 

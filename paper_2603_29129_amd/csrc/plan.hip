@@ -582,11 +582,23 @@ static int enqueue_batched3(fft_ozaki_plan_s* p, const void* in, void* out, int 
     for (int q = 0; q < 3; ++q)
       if ((rc = ntt_chunked(p->X + lc.x3_base + q * lc.x3_ps, lc.logN, q, T * 2 * K, false, lc.geom, p->tb, st, s, xs)))
         return rc;
-    HIPCHK(launch_mac3(p->X, p->G, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, K, lc.logN, s));
-    for (int q = 0; q < 3; ++q)
-      if ((rc = ntt_chunked(p->G + lc.g3_base + q * lc.g3_ps, lc.logN, q, T * 4 * K * K, true, lc.geom, p->tb, st, s,
-                            gs)))
-        return rc;
+    if (lc.geom.two_pass()) {
+      // multiply-accumulate in the inverse row pass, then the column pass
+      HIPCHK(launch_mac3_rows(p->X, p->G, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, K, lc.geom, p->tb, st, s));
+      for (int q = 0; q < 3; ++q)
+        for (i64 v0 = 0; v0 < T * 4 * K * K; v0 += 65535) {
+          VecSel gsc = gs;
+          gsc.v0 = (int)v0;
+          HIPCHK(launch_inv_cols_standalone(p->G + lc.g3_base + q * lc.g3_ps + ((size_t)v0 << lc.logN), q,
+                                            (int)std::min<i64>(65535, T * 4 * K * K - v0), lc.geom, p->tb, s, gsc));
+        }
+    } else {
+      HIPCHK(launch_mac3(p->X, p->G, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, K, lc.logN, s));
+      for (int q = 0; q < 3; ++q)
+        if ((rc = ntt_chunked(p->G + lc.g3_base + q * lc.g3_ps, lc.logN, q, T * 4 * K * K, true, lc.geom, p->tb, st,
+                              s, gs)))
+          return rc;
+    }
     HIPCHK(launch_recombine3(p->G, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, lc.nmax, K, dir, io32_of(p),
                              s));
   }
