@@ -232,8 +232,8 @@ _plans: dict = {}
 _plans_lock = threading.Lock()
 
 
-def _plan_for(shape, device, K, L) -> Plan:
-    key = (tuple(shape), str(device), K, L)
+def _plan_for(shape, device, K, L, primes=2) -> Plan:
+    key = (tuple(shape), str(device), K, L, primes)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
@@ -241,34 +241,35 @@ def _plan_for(shape, device, K, L) -> Plan:
             batch = int(np.prod(shape[:-1])) if len(shape) > 1 else 1
             import torch
             with torch.cuda.device(device):
-                p = Plan(n, batch, K=K, L=L)
+                p = Plan(n, batch, K=K, L=L, primes=primes)
             _plans[key] = p
     return p
 
 
-def _run(x, direction, K, L):
+def _run(x, direction, K, L, primes=2):
     import torch
     if x.dtype != torch.complex128:
         raise TypeError("expected complex128")
     xc = x.contiguous()
-    p = _plan_for(xc.shape, xc.device, K, L)
+    p = _plan_for(xc.shape, xc.device, K, L, primes)
     with torch.cuda.device(xc.device):
         return p.execute(xc, direction)
 
 
-def fft(x, K: int = 3, L: int = 3):
-    """Forward DFT along the last axis (Sec. 3.2, Eq. dft)."""
-    return _run(x, FORWARD, K, L)
+def fft(x, K: int | None = None, L: int = 3, primes: int = 2):
+    """Forward DFT along the last axis (Sec. 3.2, Eq. dft).  K defaults to 3
+    with two CRT moduli and to 2 with three."""
+    return _run(x, FORWARD, K, L, primes)
 
 
-def ifft(x, K: int = 3, L: int = 3):
+def ifft(x, K: int | None = None, L: int = 3, primes: int = 2):
     """Inverse DFT along the last axis, conj(DFT(conj x)) / n (Eq. idft)."""
-    return _run(x, INVERSE, K, L)
+    return _run(x, INVERSE, K, L, primes)
 
 
-def adjoint(x, K: int = 3, L: int = 3):
+def adjoint(x, K: int | None = None, L: int = 3, primes: int = 2):
     """Adjoint DFT along the last axis, conj(DFT(conj x))."""
-    return _run(x, ADJOINT, K, L)
+    return _run(x, ADJOINT, K, L, primes)
 
 
 def _autograd_class():
@@ -280,13 +281,13 @@ def _autograd_class():
         backward pass is the adjoint transform through the same pipeline."""
 
         @staticmethod
-        def forward(ctx, x, K=3, L=3):
-            ctx.K, ctx.L = K, L
-            return _run(x, FORWARD, K, L)
+        def forward(ctx, x, K=None, L=3, primes=2):
+            ctx.K, ctx.L, ctx.primes = K, L, primes
+            return _run(x, FORWARD, K, L, primes)
 
         @staticmethod
         def backward(ctx, g):
-            return _run(g, ADJOINT, ctx.K, ctx.L), None, None
+            return _run(g, ADJOINT, ctx.K, ctx.L, ctx.primes), None, None, None
 
     return OzakiDFT
 

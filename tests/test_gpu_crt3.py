@@ -167,3 +167,26 @@ def test_headline_length_three_moduli(torch_mod):
         return float(np.sqrt(np.sum(np.abs(v - ref) ** 2)) / np.sqrt(np.sum(np.abs(ref) ** 2)))
 
     assert rel(y) <= 1.5 * rel(y2) and rel(y) < 1e-15
+
+
+def test_autograd_three_moduli(torch_mod):
+    """OzakiDFT with three moduli: forward equals the oracle's primes=3
+    transform, the backward pass is the oracle's primes=3 adjoint of the
+    incoming gradient (bit for bit), and gradcheck passes."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 1000
+    x = wl.uniform(n, batch=2, seed=12)
+    w = np.random.default_rng(3).random((2, n))
+    xd = _gpu(torch, x).requires_grad_(True)
+    X = oz.OzakiDFT.apply(xd, None, 3, 3)
+    seen = []
+    X.register_hook(lambda gX: seen.append(gX.detach().clone()))
+    (torch.from_numpy(w).cuda() * X.abs() ** 2).sum().backward()
+    kp = kplan3(n)
+    Xh, gX, g = X.detach().cpu().numpy(), seen[0].cpu().numpy(), xd.grad.cpu().numpy()
+    for b in range(2):
+        assert max_ulp(Xh[b], bl.fft(x[b], plan=kp)) == 0
+        assert max_ulp(g[b], bl.adjoint(gX[b], plan=kp)) == 0
+    xs = _gpu(torch, wl.uniform(12, batch=2, seed=1)).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: oz.OzakiDFT.apply(t, None, 3, 3), (xs,), eps=1e-6, atol=1e-7, rtol=1e-5)
