@@ -79,10 +79,14 @@ hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, co
 
 // Single passes of the above (measurement hook): which = 0 both passes,
 // 1 column pass, 2 row pass (forward); 1 row pass with the fused
-// multiply-accumulate, 2 column pass (inverse).
+// multiply-accumulate, 2 column pass (inverse).  With walk_ts set (which 0
+// or 1) the forward launch also computes every listed transform's
+// accumulation schedule (as launch_groups) in one extra workgroup per
+// transform.
 hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K,
                             bool valid_full, int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb,
-                            const TwStep& st, int which, hipStream_t s);
+                            const TwStep& st, int which, hipStream_t s, TState* walk_ts = nullptr,
+                            const KernelDesc* kd = nullptr, int L = 0);
 // fused_fwd: the row pass also does the forward row NTTs of the slices (X
 // holds the forward column pass's output); needs fused_rows_ok.
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,

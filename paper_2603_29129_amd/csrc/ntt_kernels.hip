@@ -32,6 +32,7 @@
 
 #include "crt_dev.h"
 #include "internal.h"
+#include "schedule_dev.h"
 
 #include <mutex>
 #include <type_traits>
@@ -694,11 +695,40 @@ __device__ __forceinline__ bool fwd_select(u32* X, const TDesc* td, const TState
   return true;
 }
 
+// With a schedule walk attached (walk.ts set) the launch has one more
+// vector slice: its first workgroup per transform computes the transform's
+// accumulation schedule in one thread while the others transform, since the
+// schedule and the forward NTTs depend only on the split.
+struct WalkArgs {
+  TState* ts = nullptr;
+  const KernelDesc* kd = nullptr;
+  int L = 0;
+};
+__device__ __forceinline__ bool walk_slice(const WalkArgs& w, const TDesc* td, const int* tlist, u32* smem) {
+  if (!w.ts || blockIdx.y != gridDim.y - 1) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int t = tlist[blockIdx.z];
+    const TDesc& d = td[t];
+    TState& s = w.ts[t];
+    const KernelDesc& kk = w.kd[d.kd];
+    int (&E)[2][KMAX] = *reinterpret_cast<int(*)[2][KMAX]>(smem);
+    int (&Ew)[2][KMAX] = *reinterpret_cast<int(*)[2][KMAX]>(smem + 2 * KMAX);
+    for (int part = 0; part < 2; ++part)
+      for (int k = 0; k < KMAX; ++k) {
+        E[part][k] = s.E[part][k];
+        Ew[part][k] = kk.Ew[part][k];
+      }
+    schedule_walk(d, s, kk, E, Ew, w.L);
+  }
+  return true;
+}
+
 template <int M>
 __global__ void __launch_bounds__(NTT_THREADS) k_fwd_single(u32* X, const TDesc* td, const TState* ts,
                                                             const int* tlist, int K, bool valid_full, int vi_lo,
-                                                            TwBlock tb) {
+                                                            TwBlock tb, WalkArgs walk) {
   extern __shared__ u32 smem[];
+  if (walk_slice(walk, td, tlist, smem)) return;
   FwdSel o;
   if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
   fwd_single_body<M>(o.vec, o.valid, o.prime, tb.fwd[o.prime], smem);
@@ -707,8 +737,9 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_single(u32* X, const TDesc*
 template <int M1>
 __global__ void __launch_bounds__(COL_THREADS) k_fwd_cols(u32* X, const TDesc* td, const TState* ts,
                                                           const int* tlist, int K, bool valid_full, int vi_lo,
-                                                          NttGeom g, TwBlock tb, TwStep st) {
+                                                          NttGeom g, TwBlock tb, TwStep st, WalkArgs walk) {
   extern __shared__ u32 smem[];
+  if (walk_slice(walk, td, tlist, smem)) return;
   FwdSel o;
   if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
   fwd_cols_body<M1>(o.vec, o.valid, o.prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[o.prime], smem);
@@ -1778,17 +1809,26 @@ hipError_t launch_inv_cols_standalone(u32* data, int prime, int count, const Ntt
 
 hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, bool valid_full,
                             int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb, const TwStep& st, int which,
-                            hipStream_t s) {
+                            hipStream_t s, TState* walk_ts, const KernelDesc* kd, int L) {
   const int nv = vi_hi - vi_lo;
   if (count <= 0 || nv <= 0) return hipSuccess;
+  WalkArgs walk;
+  if (walk_ts && which != 2) {
+    walk.ts = walk_ts;
+    walk.kd = kd;
+    walk.L = L;
+  }
+  const int ny = nv + (walk.ts ? 1 : 0);
   hipError_t e = hipSuccess;
   if (!g.two_pass()) {
     if (which == 2) return hipSuccess;
     if (!with_m<0, LOG2_BLOCK_MAX>(g.logN, [&](auto mc) {
           constexpr int M = decltype(mc)::value;
           if ((e = big_lds((const void*)k_fwd_single<M>)) != hipSuccess) return;
-          hipLaunchKernelGGL(k_fwd_single<M>, dim3(1, nv, count), dim3(NTT_THREADS), smem_single(g.logN), s, X, td, ts,
-                             tlist, K, valid_full, vi_lo, tb);
+          // the walk slice stages 4 KMAX exponents in LDS
+          const size_t lds = std::max(smem_single(g.logN), sizeof(int) * 4 * KMAX);
+          hipLaunchKernelGGL(k_fwd_single<M>, dim3(1, ny, count), dim3(NTT_THREADS), lds, s, X, td, ts, tlist, K,
+                             valid_full, vi_lo, tb, walk);
         }))
       return hipErrorInvalidValue;
     return e != hipSuccess ? e : hipGetLastError();
@@ -1796,8 +1836,9 @@ hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int
   if (which != 2 && !with_m<M1_LO, M1_HI>(g.m1, [&](auto mc) {
         constexpr int M1 = decltype(mc)::value;
         if ((e = big_lds((const void*)k_fwd_cols<M1>)) != hipSuccess) return;
-        hipLaunchKernelGGL(k_fwd_cols<M1>, dim3(1u << (g.m2 - g.lc), nv, count), dim3(COL_THREADS), smem_cols(g), s, X,
-                           td, ts, tlist, K, valid_full, vi_lo, g, tb, st);
+        const size_t lds = std::max(smem_cols(g), sizeof(int) * 4 * KMAX);
+        hipLaunchKernelGGL(k_fwd_cols<M1>, dim3(1u << (g.m2 - g.lc), ny, count), dim3(COL_THREADS), lds, s, X, td, ts,
+                           tlist, K, valid_full, vi_lo, g, tb, st, walk);
       }))
     return hipErrorInvalidValue;
   if (e != hipSuccess) return e;

@@ -507,13 +507,13 @@ static int enqueue_batched(fft_ozaki_plan_s* p, const void* in, void* out, int d
       HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s));
     HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
   }
-  HIPCHK(launch_groups(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, p->L, s));
   for (auto& lc : p->classes) {
     // forward NTTs; where the forward row pass is folded into the inverse
-    // row pass, only the column pass here
+    // row pass, only the column pass here.  The accumulation schedule of the
+    // class's transforms is computed inside the same launch.
     const int which = fused_rows_ok(lc.geom, K) ? 1 : 0;
     HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K, lc.geom,
-                            p->tb, step_for(p, lc.logN), which, s));
+                            p->tb, step_for(p, lc.logN), which, s, p->d_ts, p->d_kd, p->L));
   }
   for (auto& lc : p->classes) {
     const int cnt = (int)lc.tids.size();
