@@ -17,7 +17,8 @@ it reports the plain form on the same input, the relative l2 error against
 a long-double DFT, per-stage device times, the roofline of the dominant
 kernel, the binary32 target precision (complex64 in and out, K = 2) on the
 same input rounded to binary32, the three-modulus CRT plan (K = 2 slices of
-36 bits) on the same input, and the CPU oracle timed on a bounded sample.
+36 bits) on the same input, one transform of the workload on its own, and
+the CPU oracle timed on a bounded sample.
 """
 
 import argparse
@@ -288,6 +289,22 @@ def main():
     del x32d, out32
     print(f"# binary32 target (K=2): {ms32:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # one transform of the same workload (the configuration's single case),
+    # batched form: latency of one n = 2^18 transform
+    plan1 = oz.Plan(n, 1, mode="batched")
+    x1 = xd[:1].contiguous()
+    out1 = torch.empty_like(x1)
+    for _ in range(args.warmup):
+        plan1.forward(x1, out1)
+    torch.cuda.synchronize()
+    ms1 = time_events(torch, lambda k: [plan1.forward(x1, out1) for _ in range(k)], args.steps)
+    single = {"batch": 1, "ms_per_step": round(ms1, 4), "value": round(5.0 * n * math.log2(n) / (ms1 * 1e-3) / 1e9, 2),
+              "bit_identical_to_headline_transform_0": bool(torch.equal(out1.view(torch.float64),
+                                                                        out[:1].view(torch.float64)))}
+    plan1.close()
+    del out1, x1
+    print(f"# single transform: {ms1:.3f} ms", file=sys.stderr, flush=True)
+
     # three CRT moduli (d = 3): K = 2 slices of alpha = 36 bits, same input
     # and output type; the standalone NTTs run per length class and prime
     plan3 = oz.Plan(n, B, mode="batched", primes=3)
@@ -393,6 +410,7 @@ def main():
         "padded_embedding": padded,
         "binary32_target": binary32,
         "three_moduli": three_moduli,
+        "single_transform": single,
         "rel_l2_error": rel,
         "max_rel_error": maxrel,
         "ntt_counts": {"forward_runtime": counts["forward_runtime"], "inverse": counts["inverse"],
