@@ -190,3 +190,23 @@ def test_autograd_three_moduli(torch_mod):
         assert max_ulp(g[b], bl.adjoint(gX[b], plan=kp)) == 0
     xs = _gpu(torch, wl.uniform(12, batch=2, seed=1)).requires_grad_(True)
     assert torch.autograd.gradcheck(lambda t: oz.OzakiDFT.apply(t, None, 3, 3), (xs,), eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+def test_many_transforms_chunked_launches(torch_mod):
+    """5000 transforms of n = 16 with three moduli and K = 2: the inverse
+    NTTs cover 5000 x 16 = 80000 group vectors per prime, more than one
+    launch's 65535, so the selector numbers vectors across two launches.
+    Sampled transforms (both launches) bit-exact against the oracle."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n, B = 16, 5000
+    x = wl.paper_phi(n, 1.0, seed=21, batch=B)
+    plan = oz.Plan(n, B, primes=3)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan3(n)
+    for b in (0, 1, 4095, 4096, 4097, 4999):
+        tr = bl.forward_trace(x[b], 2, 3, kp)
+        assert max_ulp(y[b], tr["y"]) <= ULP_TOL, b
+        assert plan.transform_info(b)["ngroups"] == [len(g) for g in component_schedule(
+            [[E for _, E in tr["slices"][v]] for v in range(2)], [kp.exps(0), kp.exps(1)], 3, "complex",
+            acc_limit(n, tr["alpha"], primes=3), alpha=tr["alpha"])], b
