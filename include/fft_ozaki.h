@@ -11,6 +11,8 @@
  * of Sec. 4.4), convolved exactly by 32-bit NTTs modulo p0 = 2130706433 and
  * p1 = 2113929217 with NTT-domain accumulation of at most L products
  * (Alg. 8), rebuilt by Garner's CRT (Sec. 3.3) and recombined to binary64.
+ * Optionally a third modulus p2 = 2013265921 widens the CRT range (Sec. 3.3
+ * with d = 3 moduli, see fft_ozaki_options.primes).
  * The four real convolutions of the complex convolution share their splits
  * (Sec. 4.5) and the kernel's splits and NTTs are computed once per plan
  * (Sec. 4.5, precomputed offline).  Outputs are deterministic: the integer
