@@ -56,3 +56,30 @@ def test_user_stream_and_graph_cache(torch_mod):
     assert float((inv - x).abs().max()) < 1e-14
     again = plan.forward(x)
     assert torch.equal(again.view(torch.float64), ref.view(torch.float64))
+
+
+@pytest.mark.parametrize("primes", [2, 3])
+def test_graph_replays_with_new_data(torch_mod, primes):
+    """The batched plan captures one graph per (in, out, direction) and
+    replays it: four replays into the same buffers with new input data each
+    time, eager torch work and synchronisations in between, every replay
+    equal bit for bit to the eager plain form (two moduli) or to a fresh
+    plan's first execution (three moduli)."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n, B = 4096 + 7, 3
+    plan = oz.Plan(n, B, primes=primes)
+    xin = torch.empty((B, n), dtype=torch.complex128, device="cuda")
+    yout = torch.empty_like(xin)
+    noise = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+    for r in range(4):
+        x = torch.from_numpy(wl.paper_phi(n, float(r), seed=40 + r, batch=B)).cuda()
+        xin.copy_(x)
+        plan.forward(xin, out=yout)
+        noise.mul_(1.0001).add_(0.5)                   # eager work between the replays
+        torch.cuda.synchronize()
+        if primes == 2:
+            want = oz.Plan(n, B, mode="plain").forward(x)
+        else:
+            want = oz.Plan(n, B, primes=3).forward(x)
+        assert torch.equal(yout.view(torch.float64), want.view(torch.float64)), r
