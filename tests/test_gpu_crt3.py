@@ -210,3 +210,24 @@ def test_many_transforms_chunked_launches(torch_mod):
         assert plan.transform_info(b)["ngroups"] == [len(g) for g in component_schedule(
             [[E for _, E in tr["slices"][v]] for v in range(2)], [kp.exps(0), kp.exps(1)], 3, "complex",
             acc_limit(n, tr["alpha"], primes=3), alpha=tr["alpha"])], b
+
+
+def test_part_shift_three_moduli(torch_mod):
+    """alpha = 28 (n = 2^14, L = 2^20) lets the part shift apply with three
+    moduli: Re x' or Im x' extracted times 2 as 64-bit slice integers;
+    outputs bit-exact against the oracle, shifts and groups as its schedule."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n, L = 1 << 14, 1 << 20
+    x = wl.paper_phi(n, 0.0, seed=0, batch=2) * 2.0 ** -6
+    x[0, 0] = 1 + 0.4j
+    x[1, 0] = 0.3 + 1j
+    plan = oz.Plan(n, 2, L=L, primes=3)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan3(n, 2, L)
+    assert kp.alpha == 28
+    for b, xs in enumerate(([1, 0], [0, 1])):
+        tr = bl.forward_trace(x[b], 2, L, kp)
+        check_info(plan, b, tr, kp)
+        assert plan.transform_info(b)["xsh"] == xs, b
+        assert max_ulp(y[b], tr["y"]) <= ULP_TOL, b
