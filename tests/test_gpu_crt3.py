@@ -231,3 +231,22 @@ def test_part_shift_three_moduli(torch_mod):
         check_info(plan, b, tr, kp)
         assert plan.transform_info(b)["xsh"] == xs, b
         assert max_ulp(y[b], tr["y"]) <= ULP_TOL, b
+
+
+def test_k8_two_pass_three_moduli(torch_mod):
+    """K = 8 at a two-pass length (n = 8192, cyclic N = 8192): the fused row
+    pass holds 2K = 16 kernel-operand columns and runs one group per chunk
+    (its largest LDS footprint); one transform with a 2^-300 half for the
+    wide recombination.  Bit-exact against the oracle."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 8192
+    x = wl.uniform(n, batch=2, seed=31)
+    x[1, ::2] *= 2.0 ** -300
+    plan = oz.Plan(n, 2, K=8, primes=3)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan3(n, 8, 3)
+    for b in range(2):
+        tr = bl.forward_trace(x[b], 8, 3, kp)
+        check_info(plan, b, tr, kp)
+        assert max_ulp(y[b], tr["y"]) <= ULP_TOL, b
