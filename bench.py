@@ -325,8 +325,21 @@ def main():
                     "ntt_counts": {"forward_runtime": i3["forward_runtime"], "inverse": i3["inverse"],
                                    "forward_offline": i3["forward_offline"]}}
     plan3.close()
+    # the same with L = 12: alpha = 35, a CRT bound of 14 products, 3 groups per component
+    plan3b = oz.Plan(n, B, mode="batched", primes=3, L=12)
+    for _ in range(args.warmup):
+        plan3b.forward(xd, out3)
+    torch.cuda.synchronize()
+    ms3b = time_events(torch, lambda k: [plan3b.forward(xd, out3) for _ in range(k)], args.steps)
+    i3b = plan3b.transform_info(0)
+    three_moduli["L12"] = {"alpha": i3b["alpha"], "acc_limit": i3b["acc_limit"], "ms_per_step": round(ms3b, 4),
+                           "value": round(flops / (ms3b * 1e-3) / 1e9, 2),
+                           "rel_l2_error": longdouble_errors(np, out3[0].cpu().numpy(), x[0])[0],
+                           "ntt_counts": {"forward_runtime": i3b["forward_runtime"], "inverse": i3b["inverse"]}}
+    plan3b.close()
     del out3
-    print(f"# three moduli (K=2, alpha={i3['alpha']}): {ms3:.3f} ms/step", file=sys.stderr, flush=True)
+    print(f"# three moduli (K=2, alpha={i3['alpha']}): {ms3:.3f} ms/step; L=12 (alpha={i3b['alpha']}): "
+          f"{ms3b:.3f} ms/step", file=sys.stderr, flush=True)
 
     y = out.cpu().numpy()
     infos = [plan.transform_info(b) for b in range(B)]
