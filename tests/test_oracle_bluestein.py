@@ -123,6 +123,53 @@ def test_printed_counts():
     assert gc["K3_L3_total_phi01"] - 12 == gc["K3_L3_runtime"]
 
 
+@pytest.mark.parametrize("n", [1 << 10, 1 << 12])
+def test_oracle_ntt_counts_printed(n):
+    """The oracle's own counter (ntt_counts) on full forward traces against
+    the printed totals: 64 transforms at K = L = 3 for phi = 0, 1 (Sec. 5.4),
+    52 of them at runtime (Sec. 5.5), 96 at K = 3, L = 1 (Sec. 5.3); and the
+    split of the totals into runtime forward, offline forward and inverse
+    transforms that the closed forms of Sec. 4.5 give for gapless splits:
+    4K + 4K offline / runtime forward, 8(2K - 1) inverse (L >= K) or 8K^2
+    (L = 1)."""
+    gc = GOLDEN["ntt_counts"]
+    K = 3
+    for L, phis, total in ((3, (0.0, 1.0), gc["K3_L3_total_phi01"]), (1, (0.0, 1.0, 4.0), gc["K3_L1_total"])):
+        kp = bl.KernelPlan(n, K, L)
+        for phi in phis:
+            x = wl.paper_phi(n, phi, 0)[0]
+            c = bl.ntt_counts(bl.forward_trace(x, K, L, kp), kp)
+            assert c["total"] == total
+            assert c["forward_offline"] == 4 * K and c["forward_runtime"] == 4 * K
+            assert c["inverse"] == (8 * (2 * K - 1) if L >= K else 8 * K * K)
+            assert c["runtime"] == c["forward_runtime"] + c["inverse"]
+            assert c["total"] == c["runtime"] + c["forward_offline"]
+            if L == 3:
+                assert c["runtime"] == gc["K3_L3_runtime"]
+                assert c["total"] == 24 * K - 8 and c["runtime"] == 20 * K - 8
+            else:
+                assert c["total"] == 8 * K + 8 * K * K
+
+
+def test_oracle_ntt_counts_planted_mistakes():
+    """ntt_counts must see both primes and the offline kernel transforms: a
+    trace with one slice fewer per input part drops exactly 2 x 2 runtime
+    forward transforms, and a three-modulus plan counts 3 per vector."""
+    n, K = 1 << 10, 3
+    kp = bl.KernelPlan(n, K, 3)
+    x = wl.paper_phi(n, 0.0, 0)[0]
+    tr = bl.forward_trace(x, K, 3, kp)
+    c = bl.ntt_counts(tr, kp)
+    short = dict(tr, slices=[tr["slices"][0][:-1], tr["slices"][1][:-1]])
+    cs = bl.ntt_counts(short, kp)
+    assert c["forward_runtime"] - cs["forward_runtime"] == 4
+    assert cs["inverse"] == c["inverse"] and cs["forward_offline"] == c["forward_offline"]
+    kp3 = bl.KernelPlan(n, 2, 3, primes=3)
+    c3 = bl.ntt_counts(bl.forward_trace(x, 2, 3, kp3), kp3)
+    assert c3["forward_offline"] == 3 * 2 * 2 and c3["forward_runtime"] == 3 * 2 * 2
+    assert c3["inverse"] % 3 == 0
+
+
 @pytest.mark.slow
 def test_kernel_split_count_large_n():
     g = GOLDEN["kernel_split_count_large_n"]
