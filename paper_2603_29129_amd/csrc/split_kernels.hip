@@ -361,7 +361,10 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
       r = r - x;
       if (k >= start) {
         if constexpr (NP == 2) {
-        const int a = (int)(x * ldexp(1.0, alpha - E + sh));   // |a| <= 2^(alpha + sh) <= 2^30 < p0, p1
+        // x is a multiple of 2^(E - alpha) with |x| <= 2^E, so scaling x itself is
+        // exact; the factor 2^(alpha - E + sh) alone can exceed the binary64 range
+        // (E - alpha down to -1022, sh up to 2)
+        const int a = (int)ldexp(x, alpha - E + sh);   // |a| <= 2^(alpha + sh) <= 2^30 < p0, p1
         const u32 r0 = a < 0 ? (u32)(a + (int)P0) : (u32)a;
         const u32 r1 = a < 0 ? (u32)(a + (int)P1) : (u32)a;
         u32* v0 = Xb + (((size_t)((part * K + k) * 2)) << d.logN);
@@ -374,7 +377,7 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
         }
         } else {
         // three moduli: |a| <= 2^alpha with alpha up to 45, kept in 64 bits
-        const long long a = (long long)(x * ldexp(1.0, alpha - E + sh));
+        const long long a = (long long)ldexp(x, alpha - E + sh);   // exact, as above
         const u32 r[3] = {(u32)(((a % (long long)P0) + P0) % P0), (u32)(((a % (long long)P1) + P1) % P1),
                           (u32)(((a % (long long)P2) + P2) % P2)};
         u32* v0 = Xb + (((size_t)(part * K + k)) << d.logN);

@@ -205,6 +205,32 @@ def test_part_shift(torch_mod, n, xsh):
         assert [plan.transform_info(b)["ngroups"] for b in range(4)] == [[6, 6], [6, 6], [5, 5], [10, 10]]
 
 
+def test_part_shift_lowest_grid(torch_mod):
+    """Regression: the shifted part's last slice on the lowest grid
+    2^-1022 (alpha = 27 at n = 12; scaled by 2^-968 the Re x' slices have
+    exponents -968, -995 and Im x' -970, so Re x' is taken times 2^2 and its
+    second slice is scaled by 2^(alpha - E + 2) = 2^1024, beyond binary64;
+    the slice itself must be scaled, not the factor formed).  Both the
+    batched and the plain form, 0 ulp from the oracle, every stage exact."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 12
+    base = _spiked(n, [1 + 1j, 1 + 1j, 1 + 1j, 1 + 0.2j])[3]
+    x = np.stack([base * 2.0 ** -968, base * 2.0 ** -966, base * 2.0 ** -967])
+    kp = kplan(n, 3, 3)
+    want_ex = ([-968, -995], [-966, -993], [-967, -994])
+    for mode in ("batched", "plain"):
+        plan = oz.Plan(n, 3, mode=mode)
+        y = plan.forward(_gpu(torch, x)).cpu().numpy()
+        for b in range(3):
+            tr = bl.forward_trace(x[b], 3, 3, kp)
+            info = plan.transform_info(b)
+            assert info["status"] == 0 and info["xsh"] == [2, 0], (mode, b)
+            assert info["Ex"][0] == want_ex[b], (mode, b)
+            check_stages(plan, b, tr, kp, 3)
+            assert max_ulp(y[b], tr["y"]) == 0, (mode, b)
+
+
 def test_part_shift_headline_length(torch_mod):
     """n = 2^18 (folded forward rows, fused column pass): a transform with
     the Re x' top exponent one above Im x' next to one with them equal, in
