@@ -59,7 +59,8 @@ class _TInfo(ctypes.Structure):
                 ("Ew", (ctypes.c_int * 8) * 2), ("ngroups", ctypes.c_int * 2), ("acc_limit", ctypes.c_int),
                 ("xsh", ctypes.c_int * 2),
                 ("forward_runtime", ctypes.c_int),
-                ("forward_offline", ctypes.c_int), ("inverse", ctypes.c_int), ("ntt_log2N1", ctypes.c_int)]
+                ("forward_offline", ctypes.c_int), ("inverse", ctypes.c_int), ("ntt_log2N1", ctypes.c_int),
+                ("tile_cols_log2", ctypes.c_int), ("tile_rows_log2", ctypes.c_int)]
 
 
 _lib = None
@@ -232,8 +233,10 @@ _plans: dict = {}
 _plans_lock = threading.Lock()
 
 
-def _plan_for(shape, device, K, L, primes=2) -> Plan:
-    key = (tuple(shape), str(device), K, L, primes)
+def _plan_for(shape, device, K, L, primes=2, stream=0) -> Plan:
+    # one plan per stream as well: a plan's workspace serves one execution
+    # at a time, and executions on different streams may overlap
+    key = (tuple(shape), str(device), K, L, primes, int(stream))
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
@@ -251,9 +254,10 @@ def _run(x, direction, K, L, primes=2):
     if x.dtype != torch.complex128:
         raise TypeError("expected complex128")
     xc = x.contiguous()
-    p = _plan_for(xc.shape, xc.device, K, L, primes)
+    stream = _stream_handle(torch, xc.device)
+    p = _plan_for(xc.shape, xc.device, K, L, primes, stream)
     with torch.cuda.device(xc.device):
-        return p.execute(xc, direction)
+        return p.execute(xc, direction, stream=stream)
 
 
 def fft(x, K: int | None = None, L: int = 3, primes: int = 2):
