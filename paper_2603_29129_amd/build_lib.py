@@ -1,6 +1,9 @@
 """Builds the HIP library libfft_ozaki.so for gfx950 in the package folder.
 
     python -m paper_2603_29129_amd.build_lib
+
+Each source is compiled to an object of its own (in parallel), then the
+objects are linked; every object carries its own gfx950 code object.
 """
 
 from __future__ import annotations
@@ -8,6 +11,8 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -18,7 +23,6 @@ FLAGS = [
     "-O3",
     "--offload-arch=gfx950",
     "-fPIC",
-    "-shared",
     "-std=c++17",
     # every binary64 operation rounds on its own; fused forms are written explicitly
     "-ffp-contract=off",
@@ -29,15 +33,30 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(PKG, "csrc", s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I" + os.path.join(ROOT, "include"), "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfft_ozaki.so")
+    inc = "-I" + os.path.join(ROOT, "include")
+    with tempfile.TemporaryDirectory(prefix="fft_ozaki_build_") as tmpd:
+        def compile_one(src):
+            obj = os.path.join(tmpd, os.path.splitext(src)[0] + ".o")
+            cmd = [hipcc, *FLAGS, inc, "-c", "-o", obj, os.path.join(PKG, "csrc", src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            res = subprocess.run(cmd, capture_output=True, text=True)
+            return obj, res
+
+        with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+            results = list(ex.map(compile_one, SOURCES))
+        for obj, res in results:
+            if res.returncode != 0:
+                sys.stderr.write(res.stdout + res.stderr)
+                raise RuntimeError(f"hipcc failed compiling {obj}")
+        tmp = LIB + ".tmp"
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in results]]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libfft_ozaki.so")
     os.replace(tmp, LIB)
     return LIB
 
