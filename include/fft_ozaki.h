@@ -252,6 +252,31 @@ const char* fft_ozaki_last_error_message(void);
 int fft_ozaki_ntt(int prime, int log2N, int64_t count, void* data, int inverse, void* stream);
 int fft_ozaki_ntt_layout(int log2N, int* log2N1);
 
+/* Allocation-free execution, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the forward / inverse / adjoint DFT of `batch` transforms of
+ * length n with the default options (as fft_ozaki_plan(n, batch) followed by
+ * fft_ozaki_execute; outputs are the same bit for bit), in -> out on device
+ * arrays laid out as for fft_ozaki_execute, asynchronous on `stream`.
+ *
+ * All tables and buffers live in one region of device memory that the
+ * library reserves statically, FFT_OZAKI_STATIC_WORKSPACE_BYTES per device
+ * it runs on, held until the process ends; the call allocates and frees no
+ * device memory (host bookkeeping only).  The region keeps the tables of the
+ * last (n, batch): a call with another (n, batch) rebuilds them first, which
+ * waits for `stream` and for the device (so it cannot be captured into a
+ * graph: make one call with the size before capturing); calls with the size
+ * of the previous call only enqueue kernels.  Sizes whose workspace would
+ * exceed the region are rejected with FFT_OZAKI_ERR_INVALID before any device
+ * call (the region holds up to 183 transforms of n = 2^10, 6 of n = 2^14 or
+ * one of n = 2^16).
+ * Every call on a device shares that device's region: calls that overlap on
+ * one device (other streams, other threads) race and must be serialised by
+ * the caller.  Data-dependent faults give NaN outputs as in the planned form;
+ * the per-transform status is not queryable here. */
+#define FFT_OZAKI_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int fft_ozaki_execute_static(int64_t n, int64_t batch, const void* in, void* out, int direction, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

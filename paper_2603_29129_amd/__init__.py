@@ -94,6 +94,7 @@ def lib():
                     "fft_ozaki_last_error_message": ([], ctypes.c_char_p),
                     "fft_ozaki_ntt": ([ci, ci, i64, vp, ci, vp], ci),
                     "fft_ozaki_ntt_layout": ([ci, ctypes.POINTER(ci)], ci),
+                    "fft_ozaki_execute_static": ([i64, i64, vp, vp, ci, vp], ci),
                 }
                 for name, (args, res) in sig.items():
                     f = getattr(L, name)
@@ -306,6 +307,26 @@ class _LazyAutograd:
 
 
 OzakiDFT = _LazyAutograd()
+
+
+def execute_static(x, direction: int = FORWARD, out=None):
+    """DFT along the last axis of a contiguous complex128 CUDA tensor through
+    the allocation-free entry point (fft_ozaki_execute_static: default
+    options, the library's static device workspace, no device allocation by
+    the library); `out` (same shape) is allocated by torch when not given."""
+    import torch
+    if x.dtype != torch.complex128 or not x.is_cuda or not x.is_contiguous():
+        raise TypeError("x must be a contiguous complex128 CUDA tensor")
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise TypeError("out must be a contiguous complex128 tensor shaped like x on its device")
+    n = x.shape[-1]
+    batch = x.numel() // n if n else 0
+    with torch.cuda.device(x.device):
+        _check(lib().fft_ozaki_execute_static(n, batch, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                              int(direction), ctypes.c_void_p(_stream_handle(torch, x.device))))
+    return out
 
 
 def ntt(data, prime: int, inverse: bool = False):

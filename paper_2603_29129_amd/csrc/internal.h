@@ -28,9 +28,24 @@ struct TwTables {
   TwStep step[MAX_LOG2_N + 1];
 };
 
-// Host-side table creation (plan time).
-int build_block_twiddles(TwBlock* out, void** allocs);
-int build_step_twiddles(int logN, TwStep* out, void** allocs);
+// Device memory of a plan: hipMalloc, or carved from one caller-given region
+// (the allocation-free entry point), 256-byte aligned.  carve() returns
+// nullptr when the region cannot hold the request.
+struct DevArena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  void* carve(size_t bytes) {
+    const size_t off = (used + 255) & ~(size_t)255;
+    if (off > size || bytes > size - off) return nullptr;
+    used = off + bytes;
+    return base + off;
+  }
+};
+
+// Host-side table creation (plan time); with an arena the tables are carved
+// from it (allocs then receives nullptr entries), otherwise hipMalloc'd.
+int build_block_twiddles(TwBlock* out, void** allocs, DevArena* arena = nullptr);
+int build_step_twiddles(int logN, TwStep* out, void** allocs, DevArena* arena = nullptr);
 
 // --- NTT launches -----------------------------------------------------------
 // Which vectors of a standalone launch hold data; the others are skipped.

@@ -1982,7 +1982,7 @@ static u32 root_of_unity(int prime, u64 N) {
   return powmod(gen, (u64)(p - 1) / N, p);
 }
 
-static hipError_t upload_powers(uint2** dst, u32 w, u32 count, u32 p) {
+static hipError_t upload_powers(uint2** dst, u32 w, u32 count, u32 p, DevArena* arena) {
   uint2* h = (uint2*)malloc(sizeof(uint2) * count);
   if (!h) return hipErrorOutOfMemory;
   u64 v = 1;
@@ -1991,29 +1991,35 @@ static hipError_t upload_powers(uint2** dst, u32 w, u32 count, u32 p) {
     h[e].y = shoup_companion((u32)v, p);
     v = v * w % p;
   }
-  hipError_t err = hipMalloc(dst, sizeof(uint2) * count);
+  hipError_t err = hipSuccess;
+  if (arena) {
+    *dst = static_cast<uint2*>(arena->carve(sizeof(uint2) * count));
+    if (!*dst) err = hipErrorOutOfMemory;
+  } else {
+    err = hipMalloc(dst, sizeof(uint2) * count);
+  }
   if (err == hipSuccess) err = hipMemcpy(*dst, h, sizeof(uint2) * count, hipMemcpyHostToDevice);
   free(h);
   return err;
 }
 
-int build_block_twiddles(TwBlock* out, void** allocs) {
+int build_block_twiddles(TwBlock* out, void** allocs, DevArena* arena) {
   for (int prime = 0; prime < NPRIME_MAX; ++prime) {
     const u32 p = prime == 0 ? P0 : (prime == 1 ? P1 : P2);
     const u32 w = root_of_unity(prime, BLOCK_MAX);
     const u32 wi = powmod(w, p - 2, p);
     uint2 *f = nullptr, *iv = nullptr;
-    if (upload_powers(&f, w, BLOCK_MAX / 2, p) != hipSuccess) return -1;
-    if (upload_powers(&iv, wi, BLOCK_MAX / 2, p) != hipSuccess) return -1;
+    if (upload_powers(&f, w, BLOCK_MAX / 2, p, arena) != hipSuccess) return -1;
+    if (upload_powers(&iv, wi, BLOCK_MAX / 2, p, arena) != hipSuccess) return -1;
     out->fwd[prime] = f;
     out->inv[prime] = iv;
-    allocs[2 * prime] = f;
-    allocs[2 * prime + 1] = iv;
+    allocs[2 * prime] = arena ? nullptr : f;
+    allocs[2 * prime + 1] = arena ? nullptr : iv;
   }
   return 0;
 }
 
-int build_step_twiddles(int logN, TwStep* out, void** allocs) {
+int build_step_twiddles(int logN, TwStep* out, void** allocs, DevArena* arena) {
   const u64 N = 1ull << logN;
   const u32 nhi = N > 4096 ? (u32)(N >> 12) : 1u;
   int a = 0;
@@ -2024,12 +2030,12 @@ int build_step_twiddles(int logN, TwStep* out, void** allocs) {
     for (int dir = 0; dir < 2; ++dir) {
       const u32 base = dir ? wi : w;
       uint2 *lo = nullptr, *hi = nullptr;
-      if (upload_powers(&lo, base, 4096, p) != hipSuccess) return -1;
-      if (upload_powers(&hi, powmod(base, 4096, p), nhi, p) != hipSuccess) return -1;
+      if (upload_powers(&lo, base, 4096, p, arena) != hipSuccess) return -1;
+      if (upload_powers(&hi, powmod(base, 4096, p), nhi, p, arena) != hipSuccess) return -1;
       out->lo[dir][prime] = lo;
       out->hi[dir][prime] = hi;
-      allocs[a++] = lo;
-      allocs[a++] = hi;
+      allocs[a++] = arena ? nullptr : lo;
+      allocs[a++] = arena ? nullptr : hi;
     }
   }
   return 0;

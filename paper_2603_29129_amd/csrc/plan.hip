@@ -147,12 +147,21 @@ struct fft_ozaki_plan_s {
   // the batched form left X with the forward column pass only for the
   // lengths whose forward row pass is folded into the inverse row pass
   bool x_rows_pending = false;
+  // non-null: all device memory is carved from this region (nothing is
+  // allocated or freed, no capture stream is created)
+  fo::DevArena* arena = nullptr;
 };
 
 namespace fo {
 
 static int dmalloc(fft_ozaki_plan_s* p, void** ptr, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (p->arena) {
+    *ptr = p->arena->carve(bytes);
+    if (!*ptr) return fail(FFT_OZAKI_ERR_NOMEM, "static workspace exhausted");
+    p->bytes += (i64)bytes;
+    return FFT_OZAKI_OK;
+  }
   hipError_t e = hipMalloc(ptr, bytes);
   if (e != hipSuccess) return fail(FFT_OZAKI_ERR_NOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
   p->allocs.push_back(*ptr);
@@ -282,19 +291,36 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   if ((rc = dmalloc(p, (void**)&kh.W, 4 * (size_t)(2 * np * K) * N))) return rc;
   if ((rc = dmalloc(p, (void**)&kh.Wq, 4 * (size_t)(2 * np * K) * N))) return rc;
   HIPCHK(hipMemset(kh.W, 0, 4 * (size_t)(2 * np * K) * N));
+  // temporaries of the kernel split (freed at the end; carved and left in
+  // place with an arena)
   int* flag = nullptr;
   double2* xp = nullptr;
   TState* ts = nullptr;
   TDesc* td = nullptr;
   KernelDesc* kd = nullptr;
   int* tl = nullptr;
-  HIPCHK(hipMalloc(&flag, sizeof(int)));
+  std::vector<void*> temps;
+  auto tmalloc = [&](void** ptr, size_t bytes) -> int {
+    if (p->arena) {
+      *ptr = p->arena->carve(bytes);
+      return *ptr ? FFT_OZAKI_OK : fail(FFT_OZAKI_ERR_NOMEM, "static workspace exhausted");
+    }
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) return fail(FFT_OZAKI_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    temps.push_back(*ptr);
+    return FFT_OZAKI_OK;
+  };
+  struct FreeTemps {
+    std::vector<void*>& v;
+    ~FreeTemps() {
+      for (void* a : v) (void)hipFree(a);
+    }
+  } free_temps{temps};
+  if ((rc = tmalloc((void**)&flag, sizeof(int))) || (rc = tmalloc((void**)&xp, sizeof(double2) * n)) ||
+      (rc = tmalloc((void**)&ts, sizeof(TState))) || (rc = tmalloc((void**)&td, sizeof(TDesc))) ||
+      (rc = tmalloc((void**)&kd, sizeof(KernelDesc))) || (rc = tmalloc((void**)&tl, sizeof(int))))
+    return rc;
   HIPCHK(hipMemset(flag, 0, sizeof(int)));
-  HIPCHK(hipMalloc(&xp, sizeof(double2) * n));
-  HIPCHK(hipMalloc(&ts, sizeof(TState)));
-  HIPCHK(hipMalloc(&td, sizeof(TDesc)));
-  HIPCHK(hipMalloc(&kd, sizeof(KernelDesc)));
-  HIPCHK(hipMalloc(&tl, sizeof(int)));
   TDesc h{};
   h.n = (int)n;
   h.N = (int)N;
@@ -344,12 +370,6 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   }
   HIPCHK(hipDeviceSynchronize());
   (void)idx;
-  (void)hipFree(flag);
-  (void)hipFree(xp);
-  (void)hipFree(ts);
-  (void)hipFree(td);
-  (void)hipFree(kd);
-  (void)hipFree(tl);
   return FFT_OZAKI_OK;
 }
 
@@ -357,9 +377,10 @@ static int build_plan(fft_ozaki_plan_s* p) {
   const int K = p->K;
   const int count = (int)p->lengths.size();
   HIPCHK(hipGetDevice(&p->device));
-  void* tw_allocs[2 * NPRIME_MAX];
-  if (build_block_twiddles(&p->tb, tw_allocs)) return fail(FFT_OZAKI_ERR_NOMEM, "twiddle tables");
-  for (void* a : tw_allocs) p->allocs.push_back(a);
+  void* tw_allocs[2 * NPRIME_MAX] = {};
+  if (build_block_twiddles(&p->tb, tw_allocs, p->arena)) return fail(FFT_OZAKI_ERR_NOMEM, "twiddle tables");
+  for (void* a : tw_allocs)
+    if (a) p->allocs.push_back(a);
   // distinct lengths and N classes
   std::map<i64, int> kidx;
   std::map<int, int> cidx;
@@ -382,10 +403,11 @@ static int build_plan(fft_ozaki_plan_s* p) {
   }
   for (auto& lc : p->classes) {
     if (ntt_geom(lc.logN).two_pass() && !p->steps.count(lc.logN)) {
-      void* sa[4 * NPRIME_MAX];
+      void* sa[4 * NPRIME_MAX] = {};
       TwStep st{};
-      if (build_step_twiddles(lc.logN, &st, sa)) return fail(FFT_OZAKI_ERR_NOMEM, "step twiddles");
-      for (void* a : sa) p->allocs.push_back(a);
+      if (build_step_twiddles(lc.logN, &st, sa, p->arena)) return fail(FFT_OZAKI_ERR_NOMEM, "step twiddles");
+      for (void* a : sa)
+        if (a) p->allocs.push_back(a);
       p->steps[lc.logN] = st;
     }
     lc.geom = ntt_geom(lc.logN);
@@ -486,7 +508,7 @@ static int build_plan(fft_ozaki_plan_s* p) {
     if ((rc = dmalloc(p, (void**)&lc.d_tlist, sizeof(int) * lc.tids.size()))) return rc;
     HIPCHK(hipMemcpy(lc.d_tlist, lc.tids.data(), sizeof(int) * lc.tids.size(), hipMemcpyHostToDevice));
   }
-  HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+  if (!p->arena) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
   HIPCHK(hipDeviceSynchronize());
   return FFT_OZAKI_OK;
 }
@@ -752,6 +774,61 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
     default:
       return fail(FFT_OZAKI_ERR_INVALID, "unknown stage");
   }
+}
+
+// --- allocation-free execution ---------------------------------------------
+// One region of device memory reserved by the library itself (a static
+// device array, one copy per device, held until the process ends) holds the
+// tables and buffers of a default-options plan of the last (n, batch) seen on
+// that device.  Host code reaches the region only through the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[FFT_OZAKI_STATIC_WORKSPACE_BYTES];
+constexpr int STATIC_DEVICES = 64;
+struct StaticSlot {
+  void* ptr = nullptr;                 // this device's address of `scratch`
+  DevArena arena;
+  fft_ozaki_plan_s* plan = nullptr;    // host description of what the region holds
+};
+static std::mutex g_static_mu;
+static StaticSlot g_static[STATIC_DEVICES];
+
+// Upper bound of the region an arena plan of `batch` transforms of length n
+// takes with the default options (K = L = 3, N = n for a power-of-two n, two
+// moduli): the carves of build_plan and prepare_kernel, each counted with
+// its largest alignment padding.
+static size_t static_bytes(i64 n, i64 batch) {
+  const int K = 3, np = 2;
+  const int logN = conv_log2(n, true);
+  const size_t N = (size_t)1 << logN, B = (size_t)batch;
+  const bool two = ntt_geom(logN).two_pass();
+  size_t b = 0;
+  auto add = [&](size_t x) { b += (x ? x : 16) + 255; };
+  for (int i = 0; i < 2 * NPRIME_MAX; ++i) add(sizeof(uint2) * (BLOCK_MAX / 2));
+  if (two)
+    for (int i = 0; i < 2 * NPRIME_MAX; ++i) {
+      add(sizeof(uint2) * 4096);
+      add(sizeof(uint2) * (N > 4096 ? N >> 12 : 1));
+    }
+  add(sizeof(double2) * (size_t)n);                        // chirp
+  add(4 * (size_t)(2 * np * K) * N);                       // W
+  add(4 * (size_t)(2 * np * K) * N);                       // Wq
+  add(sizeof(int));                                        // split temporaries
+  add(sizeof(double2) * (size_t)n);
+  add(sizeof(TState));
+  add(sizeof(TDesc));
+  add(sizeof(KernelDesc));
+  add(sizeof(int));
+  const size_t SL = (size_t)K * K, zs = (size_t)((n + 3) & ~(i64)3);
+  add(sizeof(double2) * (size_t)n * B);                    // x'
+  add(4 * ((size_t)(4 * K) << logN) * B);                  // slice spectra
+  add(two ? 4 * ((8 * SL) << logN) * B : 0);               // group rows
+  add(4 * 8 * SL * zs * B);                                // compact outputs
+  add(sizeof(TDesc) * B);
+  add(sizeof(TState) * B);
+  add(sizeof(int) * B);
+  add(sizeof(KernelDesc));
+  add(sizeof(int) * B);                                    // the class's transform list
+  return b;
 }
 
 // Global tables for the standalone NTT entry point, per device.
@@ -1055,6 +1132,57 @@ int fft_ozaki_ntt(int prime, int log2N, int64_t count, void* data, int inverse, 
   HIPCHK(launch_ntt_standalone((u32*)data, log2N, prime, (int)count, inverse != 0, ntt_geom(log2N), tb, st,
                                (hipStream_t)stream));
   return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_execute_static(int64_t n, int64_t batch, const void* in, void* out, int direction, void* stream) {
+  g_err.clear();
+  if (n < 1 || batch < 1) return fail(FFT_OZAKI_ERR_INVALID, "need n >= 1 and batch >= 1");
+  if (n > (1 << 24) || batch > (1 << 24)) return fail(FFT_OZAKI_ERR_INVALID, "n or batch too large");
+  if (!in || !out) return fail(FFT_OZAKI_ERR_INVALID, "in/out is NULL");
+  if (direction < 0 || direction > 2) return fail(FFT_OZAKI_ERR_INVALID, "direction must be 0, 1 or 2");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(FFT_OZAKI_ERR_INVALID, "in/out must be 16-byte aligned");
+  if (conv_log2(n, true) > MAX_LOG2_N) return fail(FFT_OZAKI_ERR_INVALID, "convolution length exceeds 2^24");
+  if (alpha_for(n, 3) < 1) return fail(FFT_OZAKI_ERR_INVALID, "split width alpha < 1 for this n");
+  const size_t need = static_bytes(n, batch);
+  if (need > (size_t)FFT_OZAKI_STATIC_WORKSPACE_BYTES)
+    return fail(FFT_OZAKI_ERR_INVALID, "n = " + std::to_string(n) + ", batch = " + std::to_string(batch) +
+                                           " needs up to " + std::to_string(need) +
+                                           " bytes of workspace; the static workspace holds " +
+                                           std::to_string((size_t)FFT_OZAKI_STATIC_WORKSPACE_BYTES));
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= STATIC_DEVICES) return fail(FFT_OZAKI_ERR_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  StaticSlot& sl = g_static[dev];
+  if (!sl.ptr) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(FFT_OZAKI_ERR_HIP, "hipGetSymbolAddress returned NULL");
+    sl.ptr = ptr;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  fft_ozaki_plan_s* p = sl.plan;
+  if (!p || p->lengths.size() != (size_t)batch || p->lengths[0] != n) {
+    // the region holds another size's tables: rebuild them once the work
+    // already queued on this stream (which may still read them) is done
+    HIPCHK(hipStreamSynchronize(s));
+    delete sl.plan;
+    sl.plan = nullptr;
+    p = new (std::nothrow) fft_ozaki_plan_s();
+    if (!p) return fail(FFT_OZAKI_ERR_NOMEM, "host allocation");
+    sl.arena = DevArena{};
+    sl.arena.base = static_cast<char*>(sl.ptr);
+    sl.arena.size = (size_t)FFT_OZAKI_STATIC_WORKSPACE_BYTES;
+    p->arena = &sl.arena;
+    p->lengths.assign((size_t)batch, n);
+    const int rc = build_plan(p);
+    if (rc) {
+      delete p;
+      return rc;
+    }
+    sl.plan = p;
+  }
+  return enqueue_batched(p, in, out, direction, s);
 }
 
 }  // extern "C"

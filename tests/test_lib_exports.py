@@ -76,3 +76,12 @@ def test_host_only_calls():
     assert L.fft_ozaki_ntt_layout(25, ctypes.byref(m)) == -1
     assert L.fft_ozaki_ntt(2, 10, 1, None, 0, None) == -1                 # data NULL
     assert L.fft_ozaki_ntt(3, 10, 0, None, 0, None) == -1                 # no prime 3
+    # the allocation-free entry point checks its arguments before any device call
+    fake = ctypes.c_void_p(256)
+    assert L.fft_ozaki_execute_static(1 << 18, 1, fake, fake, 0, None) == -1
+    assert b"static workspace" in L.fft_ozaki_last_error_message()
+    assert L.fft_ozaki_execute_static(1 << 14, 7, fake, fake, 0, None) == -1   # 6 fit, 7 do not
+    assert L.fft_ozaki_execute_static(0, 1, fake, fake, 0, None) == -1
+    assert L.fft_ozaki_execute_static(16, 1, None, fake, 0, None) == -1
+    assert L.fft_ozaki_execute_static(16, 1, fake, fake, 3, None) == -1
+    assert L.fft_ozaki_execute_static(16, 1, ctypes.c_void_p(264), fake, 0, None) == -1   # misaligned
