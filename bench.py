@@ -77,7 +77,8 @@ def stage_kernels(info, K):
     m2 = logN - m1
     li = min(max(9 - m2, 0), m1)
     if K <= 3 and m2 + li == 9:
-        rows = f"k_inv_rows_reg<{m2}, {'true' if folded_rows(info, K) else 'false'}>"
+        # the folded row pass runs as the persistent pipelined kernel
+        rows = f"k_inv_rows_pipe<{m2}>" if folded_rows(info, K) else f"k_inv_rows_reg<{m2}, false>"
     else:
         rows = f"k_inv_rows<{m2}>"
     out = {4: f"k_fwd_cols<{m1}>", 5: None if folded_rows(info, K) else f"k_fwd_rows<{m2}>", 6: rows}

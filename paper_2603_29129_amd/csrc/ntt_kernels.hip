@@ -34,7 +34,9 @@
 #include "internal.h"
 #include "schedule_dev.h"
 
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <unordered_set>
 #include <utility>
@@ -77,20 +79,7 @@ constexpr int KT = 3;            // slices per operand handled from registers in
 // compile-time offsets from tw + (off << s).  When ST = 1 (off = 0) the roots
 // of the round are the same for every group (`twr`, preloaded) and those with
 // j mod hd = 0 are 1, so those butterflies skip the product.
-// Root w_M^e of a block transform from its table.  MIRROR: the table holds
-// the inverse roots w_M^-e for e <= M/2 (one entry more than usual) and the
-// forward root is taken from it as w^e = -w^(e - M/2) = -(w^-1)^(M/2 - e):
-// p minus the value, and the Shoup companion of p - w is the bitwise
-// complement of that of w (0 < w < p).  This lets a kernel that runs
-// inverse transforms also run forward ones with one table.
-template <int M, bool MIRROR>
-__device__ __forceinline__ uint2 block_root(const uint2* __restrict__ tw, int e, u32 p) {
-  if (!MIRROR) return tw[e];
-  const uint2 r = tw[(M >> 1) - e];
-  return make_uint2(p - r.x, ~r.y);
-}
-
-template <int RL, int S0, int ST, bool INV, bool HOIST, int MLEN = 0, bool MIRROR = false>
+template <int RL, int S0, int ST, bool INV, bool HOIST>
 __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const uint2* __restrict__ tw,
                                               const uint2 (&twr)[1 << RL], u32 p) {
   constexpr int R = 1 << RL;
@@ -106,8 +95,7 @@ __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const 
       const int jj = j & (hd - 1);
       const bool trivial = (ST == 1) && jj == 0;
       uint2 w = make_uint2(1u, 0u);
-      if (!trivial) w = (ST == 1 || HOIST) ? twr[hd + jj] : MIRROR ? block_root<MLEN, true>(tw, (off + jj * ST) << s, p)
-                                                                    : tws[(jj * ST) << s];
+      if (!trivial) w = (ST == 1 || HOIST) ? twr[hd + jj] : tws[(jj * ST) << s];
       const u32 x = a[j], y = a[j + hd];
       if (!INV) {
         a[j] = add_mod(x, y, p);
@@ -129,9 +117,9 @@ __device__ __forceinline__ void radix_group_t(u32 (&a)[1 << RL], int off, const 
 // dependent product chains (at the tail the second group repeats the first
 // and is not stored).  The row kernels keep one group per iteration: there
 // the extra registers cost a wave per SIMD, which is worth more.
-template <int M, int S0, int RL, bool INV, bool COLS, bool HOIST, bool MIRROR = false, int PL = 8>
+template <int M, int S0, int RL, bool INV, bool COLS, bool HOIST, int PL = 8>
 __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const uint2* __restrict__ tw,
-                                             const uint2 (&twr)[1 << RL], u32 p) {
+                                             const uint2 (&twr)[1 << RL], u32 p, int tid, int nthr) {
   constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
   const int total = COLS ? (1 << (nv + LGPV)) : (nv << LGPV);
   const int sst = COLS ? (ST << nv) : 0;     // element stride of a group, column layout
@@ -176,18 +164,18 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
     }
   };
   if (!COLS) {
-    for (int g = threadIdx.x; g < total; g += blockDim.x) {
+    for (int g = tid; g < total; g += nthr) {
       int off;
       u32* p0 = locate(g, off);
       u32 a[R];
       load(a, p0);
-      radix_group_t<RL, S0, ST, INV, HOIST, (1 << M), MIRROR>(a, off, tw, twr, p);
+      radix_group_t<RL, S0, ST, INV, HOIST>(a, off, tw, twr, p);
       store(a, p0);
     }
     return;
   }
-  for (int g = threadIdx.x; g < total; g += 2 * blockDim.x) {
-    const int g2 = g + blockDim.x;
+  for (int g = tid; g < total; g += 2 * nthr) {
+    const int g2 = g + nthr;
     const bool two = g2 < total;
     int off1, off2;
     u32* p1 = locate(g, off1);
@@ -195,8 +183,8 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
     u32 a[R], b[R];
     load(a, p1);
     load(b, p2);
-    radix_group_t<RL, S0, ST, INV, HOIST, (1 << M), MIRROR>(a, off1, tw, twr, p);
-    radix_group_t<RL, S0, ST, INV, HOIST, (1 << M), MIRROR>(b, off2, tw, twr, p);
+    radix_group_t<RL, S0, ST, INV, HOIST>(a, off1, tw, twr, p);
+    radix_group_t<RL, S0, ST, INV, HOIST>(b, off2, tw, twr, p);
     store(a, p1);
     if (two) store(b, p2);
   }
@@ -209,48 +197,61 @@ __device__ __forceinline__ void round_groups(u32* lds, int nv, int ldr, const ui
 // always when ST = 1, and in the row layout when blockDim is a multiple of
 // the groups per vector (then the lanes of a stage would otherwise read the
 // strided table w^((off + jj ST) 2^s) once per group, on few LDS banks).
-template <int M, int S0, int RL, bool INV, bool COLS, bool MIRROR = false, int PL = 8>
-__device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* __restrict__ tw, u32 p) {
+template <int M, int S0, int RL, bool INV, bool COLS, int PL = 8>
+__device__ __forceinline__ void round_t(u32* lds, int nv, int ldr, const uint2* __restrict__ tw, u32 p, int tid,
+                                        int nthr) {
   constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
-  constexpr int MM = 1 << M;
   uint2 twr[R];
   if (ST == 1) {
 #pragma unroll
     for (int ss = 0; ss < RL; ++ss) {
       const int hd = R >> (ss + 1);
 #pragma unroll
-      for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = block_root<MM, MIRROR>(tw, jj << (S0 + ss), p);
+      for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = tw[jj << (S0 + ss)];
     }
-    round_groups<M, S0, RL, INV, COLS, false, MIRROR, PL>(lds, nv, ldr, tw, twr, p);
+    round_groups<M, S0, RL, INV, COLS, false, PL>(lds, nv, ldr, tw, twr, p, tid, nthr);
     return;
   }
-  if (!COLS && (blockDim.x & ((1u << LGPV) - 1)) == 0) {
-    const int off = (int)(threadIdx.x & ((1u << LGPV) - 1)) & (ST - 1);
+  if (!COLS && (nthr & ((1 << LGPV) - 1)) == 0) {
+    const int off = (tid & ((1 << LGPV) - 1)) & (ST - 1);
 #pragma unroll
     for (int ss = 0; ss < RL; ++ss) {
       const int hd = R >> (ss + 1);
 #pragma unroll
-      for (int jj = 0; jj < hd; ++jj) twr[hd + jj] = block_root<MM, MIRROR>(tw, (off + jj * ST) << (S0 + ss), p);
+      for (int jj = 0; jj < hd; ++jj) twr[hd + jj] = tw[(off + jj * ST) << (S0 + ss)];
     }
-    round_groups<M, S0, RL, INV, COLS, true, MIRROR, PL>(lds, nv, ldr, tw, twr, p);
+    round_groups<M, S0, RL, INV, COLS, true, PL>(lds, nv, ldr, tw, twr, p, tid, nthr);
     return;
   }
-  round_groups<M, S0, RL, INV, COLS, false, MIRROR, PL>(lds, nv, ldr, tw, twr, p);
+  round_groups<M, S0, RL, INV, COLS, false, PL>(lds, nv, ldr, tw, twr, p, tid, nthr);
+}
+
+// Orders the LDS accesses of one wave around this point (a wave's LDS
+// instructions are performed in issue order, so no workgroup barrier is
+// needed when only this wave reads what it wrote).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Rounds I.. of a length-2^M block NTT: ceil(M/3) rounds, the M stages spread
 // evenly (the first M mod nr rounds take one stage more); the inverse runs
-// the mirrored rounds in reverse order.
-template <int M, int I, bool INV, bool COLS, bool MIRROR = false, int PL = 8>
-__device__ __forceinline__ void rounds_t(u32* lds, int nv, int ldr, const uint2* tw, u32 p) {
+// the mirrored rounds in reverse order.  The groups of a round are spread
+// over nthr threads (tid = this thread's index among them).  WAVE: the
+// threads are the lanes of one wave, which alone works on these vectors,
+// so the rounds are separated by wave_sync instead of a workgroup barrier.
+template <int M, int I, bool INV, bool COLS, int PL = 8, bool WAVE = false>
+__device__ __forceinline__ void rounds_t(u32* lds, int nv, int ldr, const uint2* tw, u32 p, int tid, int nthr) {
   constexpr int NR = (M + 2) / 3, RB = NR ? M / NR : 0, RX = NR ? M % NR : 0;
   if constexpr (I < NR) {
     constexpr int IDX = INV ? NR - 1 - I : I;
     constexpr int S0 = IDX * RB + (IDX < RX ? IDX : RX);
     constexpr int RL = RB + (IDX < RX ? 1 : 0);
-    round_t<M, S0, RL, INV, COLS, MIRROR, PL>(lds, nv, ldr, tw, p);
-    __syncthreads();
-    rounds_t<M, I + 1, INV, COLS, MIRROR, PL>(lds, nv, ldr, tw, p);
+    round_t<M, S0, RL, INV, COLS, PL>(lds, nv, ldr, tw, p, tid, nthr);
+    if constexpr (WAVE) wave_sync();
+    else __syncthreads();
+    rounds_t<M, I + 1, INV, COLS, PL, WAVE>(lds, nv, ldr, tw, p, tid, nthr);
   }
 }
 
@@ -260,7 +261,7 @@ __device__ __forceinline__ void rounds_t(u32* lds, int nv, int ldr, const uint2*
 // rounds inline with compile-time geometry.
 template <int M, bool INV, bool COLS, int PL = 8>
 __device__ __forceinline__ void block_ntt(u32* lds, int nv, int ldr, const uint2* tw, u32 p) {
-  rounds_t<M, 0, INV, COLS, false, PL>(lds, nv, ldr, tw, p);
+  rounds_t<M, 0, INV, COLS, PL>(lds, nv, ldr, tw, p, (int)threadIdx.x, (int)blockDim.x);
 }
 
 // Copies the roots w_M^e (e < M/2) of a length-2^m block NTT into LDS from the
@@ -270,17 +271,12 @@ __device__ __forceinline__ void load_block_tw(uint2* tw, const uint2* __restrict
   for (int e = threadIdx.x; e < half; e += blockDim.x) tw[e] = src[e << (LOG2_BLOCK_MAX - m)];
 }
 
-// floor(v 2^32 / p) for v < p, exactly.  p is one of the NTT primes, so
-// 2^32 / p is a constant picked by uniform selects.  The binary64 product
-// v (2^32 / p) is below 2^32 with an error under 2^-19, so its truncation is
-// off by at most one either way; one step on the sign and size of the exact
-// 64-bit remainder fixes it (a single select, no loop, no division).
+// floor(v 2^32 / p) for v < p, exactly, in integer arithmetic: p is one of
+// the NTT primes, so each branch divides by a compile-time constant (which
+// the compiler turns into multiplications).
 __device__ __forceinline__ u32 companion_dev(u32 v, u32 p) {
-  const double rp = p == P0 ? 4294967296.0 / (double)P0
-                   : (p == P1 ? 4294967296.0 / (double)P1 : 4294967296.0 / (double)P2);
-  const u32 c = (u32)((double)v * rp);
-  const long long r = (long long)(((u64)v << 32) - (u64)c * p);
-  return r < 0 ? c - 1 : (r >= (long long)p ? c + 1 : c);
+  const u64 w = (u64)v << 32;
+  return (u32)(p == P0 ? w / P0 : (p == P1 ? w / P1 : w / P2));
 }
 
 // (w_N^e, companion) from the two-level step tables.
@@ -864,6 +860,55 @@ __device__ __forceinline__ void walk_target(const V (&xa)[KT], const V (&wa)[KT]
   }
 }
 
+// The same walk when all four slice counts equal C and every group of the
+// component goes to LDS: fully unrolled, the only branches are the group
+// ends (bit w of gend, w a compile-time position); group g is written to
+// lds0 + g rstride.
+template <bool MERGED, bool NEGB, int C, typename V>
+__device__ __forceinline__ void walk_full(const V (&xa)[KT], const V (&wa)[KT], const V (&qa)[KT], const V (&xb)[KT],
+                                          const V (&wb)[KT], const V (&qb)[KT], u64 gend, u32* lds0, int rstride,
+                                          u32 p) {
+  V acc;
+  zero_acc(acc);
+  u32* dst = lds0;
+  int w = 0;
+  auto close = [&]() {
+    if ((gend >> w) & 1) {
+      put_acc(dst, acc);
+      zero_acc(acc);
+      dst += rstride;
+    }
+    ++w;
+  };
+  if constexpr (MERGED) {
+#pragma unroll
+    for (int d = 2 * C - 2; d >= 0; --d) {
+#pragma unroll
+      for (int ss = (d - C + 1 > 0 ? d - C + 1 : 0); ss <= (C - 1 < d ? C - 1 : d); ++ss) {
+        walk_step<NEGB>(acc, 0, xa[ss], wa[d - ss], qa[d - ss], p);
+        close();
+      }
+#pragma unroll
+      for (int ss = (d - C + 1 > 0 ? d - C + 1 : 0); ss <= (C - 1 < d ? C - 1 : d); ++ss) {
+        walk_step<NEGB>(acc, 1, xb[ss], wb[d - ss], qb[d - ss], p);
+        close();
+      }
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int d = 2 * C - 2; d >= 0; --d) {
+#pragma unroll
+        for (int ss = (d - C + 1 > 0 ? d - C + 1 : 0); ss <= (C - 1 < d ? C - 1 : d); ++ss) {
+          if (h == 0) walk_step<NEGB>(acc, 0, xa[ss], wa[d - ss], qa[d - ss], p);
+          else walk_step<NEGB>(acc, 1, xb[ss], wb[d - ss], qb[d - ss], p);
+          close();
+        }
+      }
+    }
+  }
+}
 // One output component with operands read per walk position (any slice
 // counts): the members (convolution, s, t) recorded by the schedule.
 __device__ void walk_mem(const MacArgs& a, const TState& s, int tg, int gbase, int g0, int g1, size_t e, u32* lds0,
@@ -954,6 +999,20 @@ __device__ __forceinline__ void mac_regs(const V (&xr)[KT], const V (&xi)[KT], c
     mac_regs_t<true>(xr, xi, r.w0, r.q0, r.w1, r.q1, s, kw0, kw1, 0, 1, gofs, g0, g1, lds0, rstride, p);
   else
     mac_regs_t<false>(xr, xi, r.w0, r.q0, r.w1, r.q1, s, kw0, kw1, 0, 1, gofs, g0, g1, lds0, rstride, p);
+}
+
+// Both output components, all counts C, all groups to LDS rows 0 .. gtot-1.
+template <int C, typename V>
+__device__ __forceinline__ void mac_full(const V (&xr)[KT], const V (&xi)[KT], const WRegs<V>& r, const TState& s,
+                                         bool merged, u32* lds0, int rstride, u32 p) {
+  u32* lds1 = lds0 + s.ngroups[0] * rstride;
+  if (merged) {
+    walk_full<true, true, C>(xr, r.w0, r.q0, xi, r.w1, r.q1, s.gend[0][0], lds0, rstride, p);
+    walk_full<true, false, C>(xi, r.w0, r.q0, xr, r.w1, r.q1, s.gend[1][0], lds1, rstride, p);
+  } else {
+    walk_full<false, true, C>(xr, r.w0, r.q0, xi, r.w1, r.q1, s.gend[0][0], lds0, rstride, p);
+    walk_full<false, false, C>(xi, r.w0, r.q0, xr, r.w1, r.q1, s.gend[1][0], lds1, rstride, p);
+  }
 }
 
 // Output components [tg_lo, tg_hi] at positions e, e+1 (e even).
@@ -1137,19 +1196,11 @@ __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u
 // position per thread, the kernel-slice operands stay in registers for the
 // run and the slice spectra of the next transform load while the current
 // one is transformed; more groups than one chunk holds recompute the
-// products from the registers per chunk.
-//
-// FWD: the forward row pass of the slice vectors is done here too, so X
-// holds only the forward column pass's output: the thread's values are
-// multiplied by the row twiddle, the rows (one per slice present) are
-// transformed in LDS by the forward block NTT, and each thread reads back
-// the NTT-domain values of its position.  The forward twiddle w_N^{j2 k1} is
-// c T(N2 - j2) with T(m) = w_N^{-m k1} (the inverse row twiddles, T(N2) for
-// j2 = 0) and c = w_N^{N2 k1}; the factor c is folded into the thread's
-// kernel-slice operands, so the products come out unscaled.  The forward
-// block roots are read from the inverse table (block_root<.., true>).
+// products from the registers per chunk.  (The batched schedule runs the
+// pipelined form below, which also does the forward row pass; this one
+// serves the per-group launches of the plain form.)
 constexpr int INV_ROW_THREADS = 512;
-template <int M2, bool FWD>
+template <int M2>
 __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* X, u32* G, const TDesc* td,
                                                                   const TState* ts, const KernelDesc* kd,
                                                                   const int* tlist, int count, int K, int slot_lo,
@@ -1168,8 +1219,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   const int gch = max(1, inv_vmax(m2) >> g.lrows_inv);          // groups per chunk
   const u32 Nmask = (1u << g.logN) - 1;
   uint2* tw = reinterpret_cast<uint2*>(smem);                // inverse roots, entries 0 .. N2/2
-  u32* rtw = smem + N2 + 4;                                   // w_N^{-j2 k1} per tile element, then companions,
-                                                              // then T(N2) per row (nr values, nr companions)
+  u32* rtw = smem + N2 + 4;                                   // w_N^{-j2 k1} per tile element, then companions
   u32* tile = rtw + 2 * (nr << m2) + 2 * nr;
   load_block_tw(tw, tb.inv[prime], m2);
   if (threadIdx.x == 0) tw[N2 >> 1] = make_uint2(p - 1, shoup_companion(p - 1, p));   // w^(-N2/2) = -1
@@ -1187,18 +1237,6 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   WRegs<u32> wr;
   int wkd = -1;
   u32 xr[KT], xi[KT];
-  // forward row twiddle T(N2 - j2) of this position: an entry of rtw, or
-  // for j2 = 0 the row's T(N2), stored after rtw (the factor c is formed
-  // where the kernel-slice operands are loaded)
-  const u32 e_c = FWD ? ((u32)N2 * bitrev(i1_0 + (e_loc >> m2), g.m1)) & Nmask : 0u;   // N2 k1 mod N
-  if (FWD) {
-    if ((e_loc & (N2 - 1)) == 0) {
-      const uint2 t = step_root(e_c, st.lo[1][prime], st.hi[1][prime], p);
-      rtw[2 * (nr << m2) + (e_loc >> m2)] = t.x;
-      rtw[2 * (nr << m2) + nr + (e_loc >> m2)] = t.y;
-    }
-    __syncthreads();                                          // rtw complete
-  }
   int bn = b_lo;                                              // transform whose slices are in xr, xi
   while (bn < b_hi && ts[tlist[bn]].status) ++bn;
   if (bn < b_hi) {
@@ -1212,46 +1250,12 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
     const KernelDesc& kk = kd[d.kd];
     if (d.kd != wkd) {
       load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], pos);
-      if (FWD) {                                              // fold c into the kernel-slice operands
-        const uint2 cfac = step_root(e_c, st.lo[0][prime], st.hi[0][prime], p);
-#pragma unroll
-        for (int k = 0; k < KT; ++k) {
-          if (k < kk.kw[0]) {
-            wr.w0[k] = shoup_mul(wr.w0[k], cfac.x, cfac.y, p);
-            wr.q0[k] = companion_dev(wr.w0[k], p);
-          }
-          if (k < kk.kw[1]) {
-            wr.w1[k] = shoup_mul(wr.w1[k], cfac.x, cfac.y, p);
-            wr.q1[k] = companion_dev(wr.w1[k], p);
-          }
-        }
-      }
       wkd = d.kd;
     }
     const int gofs[2] = {0, s.ngroups[0]};
     const int gtot = s.ngroups[0] + s.ngroups[1];
     int b2 = bn + 1;
     while (b2 < b_hi && ts[tlist[b2]].status) ++b2;
-    const int kx0 = s.kx[0], kx1 = s.kx[1];
-    if (FWD && kx0 + kx1 > 0) {
-      // forward rows: slice k of Re x' in tile vector k, of Im x' in kx0 + k
-      const int r = e_loc >> m2, j2 = e_loc & (N2 - 1);
-      const int fi = j2 ? r * N2 + N2 - j2 : 2 * (nr << m2) + r;
-      const u32 fx = rtw[fi], fy = rtw[fi + (j2 ? (nr << m2) : nr)];
-#pragma unroll
-      for (int k = 0; k < KT; ++k) {
-        if (k < kx0) lds_me[(k * nr) * ldr] = shoup_mul(xr[k], fx, fy, p);
-        if (k < kx1) lds_me[((kx0 + k) * nr) * ldr] = shoup_mul(xi[k], fx, fy, p);
-      }
-      __syncthreads();
-      rounds_t<M2, 0, false, false, true, PL>(tile, (kx0 + kx1) * nr, ldr, tw, p);
-#pragma unroll
-      for (int k = 0; k < KT; ++k) {
-        if (k < kx0) xr[k] = lds_me[(k * nr) * ldr];
-        if (k < kx1) xi[k] = lds_me[((kx0 + k) * nr) * ldr];
-      }
-      __syncthreads();                                        // the tile is rewritten by the products
-    }
     for (int g0 = 0; g0 < gtot; g0 += gch) {
       const int g1 = min(gtot, g0 + gch);
       mac_regs(xr, xi, wr, s, d.acc_mode == ACC_COMPLEX, kk.kw[0], kk.kw[1], gofs, g0, g1, lds_me, nr * ldr, p);
@@ -1269,6 +1273,170 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
       load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], pos);
     }
     bn = b2;
+  }
+}
+
+// Persistent, pipelined form of the folded inverse row pass (the batched
+// schedule's row pass whenever fused_rows_ok holds).  The work units are
+// (row tile, prime, transform); workgroup i of the grid (sized to the
+// workgroups that fit the GPU at once) takes the contiguous units
+// [i U / grid, (i + 1) U / grid), U = tiles x primes x transforms, in the
+// order (tile, prime) major, transform minor, so a workgroup mostly stays on
+// one tile and prime and keeps the kernel-slice operands of its position in
+// registers.  One position of the tile per thread, as in k_inv_rows_reg.
+//
+// Per transform: the thread forms every group's NTT-domain sum at its
+// position into the group tiles of LDS region A and, in the same step, the
+// next transform's row-twiddled forward column output into region B; after
+// one barrier every wave runs whole tiles (inverse row NTTs of the groups,
+// forward row NTTs of the next transform's slices; 16 tiles over 8 waves at
+// K = L = 3), each wave on its own tiles, so its rounds need no workgroup
+// barrier; after a second barrier each thread twiddles and stores the group
+// values of its own position and reads back the next transform's slice
+// spectra.  Nothing else touches another thread's position, so two barriers
+// per transform suffice.  The row twiddles w_N^{+-j2 k1} of the thread's
+// position are formed in registers once per (tile, prime).
+template <int M2>
+__global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_pipe(const u32* X, u32* G, const TDesc* td,
+                                                                   const TState* ts, const KernelDesc* kd,
+                                                                   const int* tlist, int count, int K, NttGeom g,
+                                                                   TwBlock tb, TwStep st) {
+  extern __shared__ u32 smem[];
+  constexpr int PL = 9;
+  constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ldl<PL>(N2), NW = INV_ROW_THREADS / 64;
+  const int lrows = g.lrows_inv, nr = 1 << lrows, SL = 2 * K * K;
+  const int gch = max(1, inv_vmax(m2) >> lrows);            // group tiles in LDS
+  const int gA = gch - 2 * K;                                 // region A: inverse group tiles per chunk
+  const int tstride = nr * ldr;                               // words per group tile
+  const u32 Nmask = (1u << g.logN) - 1;
+  uint2* tw = reinterpret_cast<uint2*>(smem);                // inverse roots, entries 0 .. N2/2
+  uint2* twf = reinterpret_cast<uint2*>(smem + N2 + 4);      // forward roots, entries 0 .. N2/2 - 1
+  u32* tileA = smem + 2 * N2 + 4;
+  u32* tileB = tileA + gA * tstride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e_loc = threadIdx.x;
+  const int r_loc = e_loc >> m2, j2 = e_loc & (N2 - 1);
+  const int off_me = r_loc * ldr + padl<PL>(j2);
+  const long units = (long)(2 << (g.m1 - lrows)) * count;
+  const long u_lo = units * blockIdx.x / gridDim.x, u_hi = units * (blockIdx.x + 1) / gridDim.x;
+
+  auto live = [&](int b) { return !ts[tlist[b]].status; };
+  // wave w transforms tiles w, w + NW, ..: A tiles (inverse) first, then B (forward)
+  // (the lane index passes through an empty asm statement per tile, so the
+  // compiler recomputes the rounds' lane offsets instead of keeping them all
+  // live across the kernel)
+  auto run_tiles = [&](int nA, int nB, u32 p) {
+    for (int r = wave; r < nA + nB; r += NW) {
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
+      if (r < nA) rounds_t<M2, 0, true, false, PL, true>(tileA + r * tstride, nr, ldr, tw, p, ln, 64);
+      else rounds_t<M2, 0, false, false, PL, true>(tileB + (r - nA) * tstride, nr, ldr, twf, p, ln, 64);
+    }
+  };
+
+  for (long u = u_lo; u < u_hi;) {
+    const int pair = (int)(u / count), b_lo = (int)(u % count);
+    const long seg_end = min(u_hi, (long)(pair + 1) * count);
+    const int b_hi = (int)(seg_end - (long)pair * count);
+    u = seg_end;
+    const int prime = pair & 1;
+    const u32 p = prime_of(prime);
+    const int i1_0 = (pair >> 1) << lrows;
+    const size_t base = (size_t)i1_0 << m2;
+    const u32 pos = (u32)base + (u32)e_loc;
+    // tables of this (tile, prime): block roots in LDS, row twiddles of this position
+    __syncthreads();                                          // the previous segment's rounds are done with tw
+    load_block_tw(tw, tb.inv[prime], m2);
+    load_block_tw(twf, tb.fwd[prime], m2);
+    if (threadIdx.x == 0) tw[N2 >> 1] = make_uint2(p - 1, shoup_companion(p - 1, p));   // w^(-N2/2) = -1
+    const u32 ek = ((u32)j2 * bitrev(i1_0 + r_loc, g.m1)) & Nmask;
+    const uint2 fwt = step_root(ek, st.lo[0][prime], st.hi[0][prime], p);   // w_N^{j2 k1}
+    const uint2 iwt = step_root(ek, st.lo[1][prime], st.hi[1][prime], p);   // w_N^{-j2 k1}
+    WRegs<u32> wr;
+    int wkd = -1;
+    u32 xr[KT], xi[KT], yr[KT], yi[KT];
+    int bn = b_lo;
+    while (bn < b_hi && !live(bn)) ++bn;
+    if (bn >= b_hi) continue;
+    auto next_live = [&](int b) {
+      ++b;
+      while (b < b_hi && !live(b)) ++b;
+      return b;
+    };
+    auto put_b = [&](int kx0, int kx1, int om) {              // row-twiddled column output into region B
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        if (k < kx0) tileB[k * tstride + om] = shoup_mul(yr[k], fwt.x, fwt.y, p);
+        if (k < kx1) tileB[(kx0 + k) * tstride + om] = shoup_mul(yi[k], fwt.x, fwt.y, p);
+      }
+    };
+    auto get_b = [&](int kx0, int kx1, int om) {              // slice spectra back from region B
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        if (k < kx0) xr[k] = tileB[k * tstride + om];
+        if (k < kx1) xi[k] = tileB[(kx0 + k) * tstride + om];
+      }
+    };
+    auto fetch = [&](int b) {                                 // column output of transform b into yr, yi
+      const int t = tlist[b];
+      load_xregs(yr, yi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], pos);
+    };
+    // prologue: forward rows of the first live transform; the second one's
+    // column output is fetched while they run
+    {
+      const int t = tlist[bn];
+      const int kx0 = ts[t].kx[0], kx1 = ts[t].kx[1];
+      fetch(bn);
+      put_b(kx0, kx1, off_me);
+      __syncthreads();                                        // tw and B complete
+      const int b2 = next_live(bn);
+      if (b2 < b_hi) fetch(b2);
+      run_tiles(0, kx0 + kx1, p);
+      __syncthreads();
+      get_b(kx0, kx1, off_me);
+    }
+    while (bn < b_hi) {
+      const int om = off_me;
+      const int t = tlist[bn];
+      const TDesc& d = td[t];
+      const TState& s = ts[t];
+      const KernelDesc& kk = kd[d.kd];
+      if (d.kd != wkd) {
+        load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], pos);
+        wkd = d.kd;
+      }
+      const int b2 = next_live(bn);                           // its column output is in yr, yi
+      const int b3 = b2 < b_hi ? next_live(b2) : b_hi;
+      const int nkx0 = b2 < b_hi ? ts[tlist[b2]].kx[0] : 0, nkx1 = b2 < b_hi ? ts[tlist[b2]].kx[1] : 0;
+      const int ng0 = s.ngroups[0], gtot = ng0 + s.ngroups[1];
+      const int kx0 = s.kx[0], kx1 = s.kx[1];
+      const bool merged = d.acc_mode == ACC_COMPLEX;
+      const int cfull = (kx0 == kx1 && kx0 == kk.kw[0] && kx0 == kk.kw[1]) ? kx0 : 0;
+      const int gofs[2] = {0, ng0};
+      for (int g0 = 0;; g0 += gA) {
+        const int g1 = min(gtot, g0 + gA);
+        const bool last = g1 >= gtot;
+        const int nB = last ? nkx0 + nkx1 : 0;
+        if (nB) put_b(nkx0, nkx1, om);
+        if (g1 > g0) {
+          if (gtot <= gA && cfull == KT) mac_full<KT>(xr, xi, wr, s, merged, tileA + om, tstride, p);
+          else if (gtot <= gA && cfull == 2) mac_full<2>(xr, xi, wr, s, merged, tileA + om, tstride, p);
+          else mac_regs(xr, xi, wr, s, merged, kk.kw[0], kk.kw[1], gofs, g0, g1, tileA + om, tstride, p);
+        }
+        __syncthreads();                                      // A and B written
+        if (last && b3 < b_hi) fetch(b3);                     // in flight during the rounds
+        run_tiles(g1 - g0, nB, p);
+        __syncthreads();                                      // rounds done
+        for (int gi = g0; gi < g1; ++gi) {                    // this position of every group row
+          const int slot = gi < ng0 ? gi : SL + gi - ng0;
+          const u32 v = shoup_mul(tileA[(gi - g0) * tstride + om], iwt.x, iwt.y, p);
+          G[d.G_off + ((size_t)(slot * 2 + prime) << g.logN) + pos] = v;
+        }
+        if (nB) get_b(nkx0, nkx1, om);
+        if (last) break;
+      }
+      bn = b2;
+    }
   }
 }
 
@@ -1690,6 +1858,30 @@ static size_t smem_inv_rows(const NttGeom& g) {
   return ((size_t)(1 << g.m2) + 4 + ((size_t)2 << (g.m2 + g.lrows_inv)) + ((size_t)2 << g.lrows_inv) +
           (size_t)row_ld(1 << g.m2) * (size_t)(gch << g.lrows_inv)) * 4;
 }
+// LDS of k_inv_rows_pipe: inverse and forward block roots, then gch group
+// tiles of nr pad9 rows.
+static size_t smem_inv_pipe(const NttGeom& g) {
+  const int gch = std::max(1, inv_vmax(g.m2) >> g.lrows_inv);
+  return ((size_t)(2 << g.m2) + 4 + (size_t)gch * ((size_t)pad9(1 << g.m2) << g.lrows_inv)) * 4;
+}
+// Workgroups of `fn` that the device runs at once (occupancy x CUs), cached
+// per device, kernel and LDS size.
+static int resident_workgroups(const void* fn, int threads, size_t smem) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, size_t>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_tuple(dev, fn, smem);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int nb = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, smem) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const int slots = std::max(1, nb) * std::max(1, ncu);
+  cache[key] = slots;
+  return slots;
+}
 static size_t smem_inv_single(int logN) {
   return ((size_t)(1 << logN) + (size_t)row_ld(1 << logN) * (size_t)inv_vmax(logN)) * 4;
 }
@@ -1896,8 +2088,27 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
     if (!with_m<M2_LO, M2_HI>(g.m2, [&](auto mc) {
           constexpr int M2 = decltype(mc)::value;
           if constexpr ((1 << M2) <= INV_ROW_THREADS) {   // the register form exists only for these lengths
+            if (reg && fused_fwd) {
+              // persistent pipelined form (all groups): one workgroup per resident slot
+              if (slot_lo != 0 || slot_hi < 4 * K * K) {
+                e = hipErrorInvalidValue;
+                return;
+              }
+              auto* kfn = &k_inv_rows_pipe<M2>;
+              if ((e = big_lds((const void*)kfn)) != hipSuccess) return;
+              const size_t sm = smem_inv_pipe(g);
+              const long units = pairs * count;
+              const int slots = resident_workgroups((const void*)kfn, INV_ROW_THREADS, sm);
+              if (slots <= 0) {
+                e = hipErrorInvalidValue;
+                return;
+              }
+              hipLaunchKernelGGL(kfn, dim3((unsigned)std::min<long>(units, slots)), dim3(INV_ROW_THREADS), sm, s, X, G,
+                                 td, ts, kd, tlist, count, K, g, tb, st);
+              return;
+            }
             if (reg) {
-              auto* kfn = fused_fwd ? &k_inv_rows_reg<M2, true> : &k_inv_rows_reg<M2, false>;
+              auto* kfn = &k_inv_rows_reg<M2>;
               if ((e = big_lds((const void*)kfn)) != hipSuccess) return;
               hipLaunchKernelGGL(kfn, dim3((unsigned)(pairs * runs)), dim3(INV_ROW_THREADS), smem_inv_rows(g), s, X,
                                  G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
