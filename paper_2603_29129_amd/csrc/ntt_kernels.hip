@@ -1626,55 +1626,11 @@ __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, 
 // get their column pass here, written to the compact buffer for the wide
 // recombination.
 
-// One round of the inverse column transforms of two tiles (prime 0 and 1):
-// the groups of tile 1 follow those of tile 0, so every wave works on one
-// prime.
-template <int M, int S0, int RL>
-__device__ __forceinline__ void round_dual(u32* tile0, u32* tile1, int nv, const uint2* tw0, const uint2* tw1) {
-  constexpr int R = 1 << RL, LBK = M - S0, LST = LBK - RL, ST = 1 << LST, LGPV = M - RL;
-  const int per = 1 << (nv + LGPV);
-  const int sst = ST << nv;
-  for (int g = threadIdx.x; g < 2 * per; g += blockDim.x) {
-    const bool hi = g >= per;
-    const int gg = hi ? g - per : g;
-    u32* lds = hi ? tile1 : tile0;
-    const uint2* tw = hi ? tw1 : tw0;
-    const u32 p = hi ? P1 : P0;
-    uint2 twr[R];
-    if (ST == 1) {
-#pragma unroll
-      for (int ss = 0; ss < RL; ++ss) {
-        const int hd = R >> (ss + 1);
-#pragma unroll
-        for (int jj = 1; jj < hd; ++jj) twr[hd + jj] = tw[jj << (S0 + ss)];
-      }
-    }
-    const int v = gg & ((1 << nv) - 1), q = gg >> nv;
-    const int off = q & (ST - 1);
-    const int base = ((q >> LST) << LBK) + off;
-    u32* p0 = lds + (base << nv) + v;
-    u32 a[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) a[j] = p0[j * sst];
-    radix_group_t<RL, S0, ST, true, false>(a, off, tw, twr, p);
-#pragma unroll
-    for (int j = 0; j < R; ++j) p0[j * sst] = a[j];
-  }
-}
-template <int M, int I>
-__device__ __forceinline__ void rounds_dual(u32* tile0, u32* tile1, int nv, const uint2* tw0, const uint2* tw1) {
-  constexpr int NR = (M + 2) / 3, RB = NR ? M / NR : 0, RX = NR ? M % NR : 0;
-  if constexpr (I < NR) {
-    constexpr int IDX = NR - 1 - I;                           // inverse: rounds in reverse order
-    constexpr int S0 = IDX * RB + (IDX < RX ? IDX : RX);
-    constexpr int RL = RB + (IDX < RX ? 1 : 0);
-    round_dual<M, S0, RL>(tile0, tile1, nv, tw0, tw1);
-    __syncthreads();
-    rounds_dual<M, I + 1>(tile0, tile1, nv, tw0, tw1);
-  }
-}
-
 constexpr int REC_THREADS = 1024, REC_OUT = 4;   // 4096-position tiles
+// Column stride of the fused column pass's tiles: each column of N1 = 2^m1
+// values is a pad9 row; the stride is 8 mod 64 words so that the eight
+// columns read together at one tile position fall on different LDS banks.
+__host__ __device__ constexpr int rec_ldc(int m1) { return pad9(1 << m1) + ((8 - pad9(1 << m1)) & 63); }
 template <int M1>
 __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td,
                                                               const TState* ts, const KernelDesc* kd,
@@ -1704,17 +1660,40 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
   }
   uint2* tw0 = reinterpret_cast<uint2*>(smem);               // inverse roots, 2^(M1-1) per prime
   uint2* tw1 = tw0 + (1 << (M1 - 1));
-  u32* tile0 = smem + (2 << M1);
-  u32* tile1 = tile0 + TILE;
+  // the tile of each prime holds its 2^LC columns as pad9 rows (column c at
+  // c LDC); two buffers of both primes' tiles: group v uses buffer v & 1, so
+  // the next group's values are written while other waves still read this
+  // one's.  Each wave owns CPW columns of one prime and runs their inverse
+  // NTTs on its own (wave-local rounds).
+  // this thread's quad of the tile: row i, columns c4 .. c4 + 3
+  const int qi = threadIdx.x >> LQ, qc = (threadIdx.x & ((1 << LQ) - 1)) << 2;
+  constexpr int LDC = rec_ldc(M1), TT = LDC << LC;            // words per prime tile
+  u32* tiles = smem + (2 << M1);
   load_block_tw(tw0, tb.inv[0], M1);
   load_block_tw(tw1, tb.inv[1], M1);
+  constexpr int NWV = REC_THREADS / 64, CPW = (2 << LC) / NWV;   // columns per wave
+  static_assert(CPW >= 1 && CPW * NWV == (2 << LC), "column split");
+  const int lane = threadIdx.x & 63, wcol = (int)(threadIdx.x >> 6) * CPW;
+  const int wprime = wcol >> LC, wc0 = wcol & ((1 << LC) - 1);
+  auto put_tile = [&](u32* tile, const u32x4& q) {           // quad of row qi, columns qc .. qc + 3
+    u32* b = tile + qc * LDC + pad9(qi);
+    b[0] = q[0];
+    b[LDC] = q[1];
+    b[2 * LDC] = q[2];
+    b[3 * LDC] = q[3];
+  };
+  auto at = [&](const u32* tile, int o) { return tile[(o & ((1 << LC) - 1)) * LDC + pad9(o >> LC)]; };
+  auto columns = [&](u32* tile0, u32* tile1) {
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    rounds_t<M1, 0, true, false, 9, true>((wprime ? tile1 : tile0) + wc0 * LDC, CPW, LDC, wprime ? tw1 : tw0,
+                                          wprime ? P1 : P0, ln, 64);
+  };
   ColVecs cv;                                                 // group numbering (slot_of)
   cv.ng0 = s.ngroups[0];
   cv.SL = 2 * K * K;
   const int V = cv.ng0 + s.ngroups[1];                        // groups; Re y' groups are [0, ng0)
   const u32* gb = G + d.G_off;
-  // this thread's quad of the tile: row i, columns c4 .. c4 + 3
-  const int qi = threadIdx.x >> LQ, qc = (threadIdx.x & ((1 << LQ) - 1)) << 2;
   const size_t goff = ((size_t)qi << m2) + j2_0 + qc;
   u32x4 st0 = {0, 0, 0, 0}, st1 = {0, 0, 0, 0};
   auto fetch = [&](int v) {
@@ -1724,24 +1703,25 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
   };
   if (wide) {
     if (V > 0) fetch(0);
-    __syncthreads();                                          // root tables
     for (int v = 0; v < V; ++v) {
-      *reinterpret_cast<u32x4*>(tile0 + (qi << LC) + qc) = st0;
-      *reinterpret_cast<u32x4*>(tile1 + (qi << LC) + qc) = st1;
-      __syncthreads();
+      u32* tile0 = tiles + (v & 1) * 2 * TT;
+      u32* tile1 = tile0 + TT;
+      put_tile(tile0, st0);
+      put_tile(tile1, st1);
+      __syncthreads();                                        // tiles (and the root tables) complete
       if (v + 1 < V) fetch(v + 1);
-      rounds_dual<M1, 0>(tile0, tile1, LC, tw0, tw1);
+      columns(tile0, tile1);
+      __syncthreads();                                        // columns done
       u32* z0 = Z + d.Z_off + (size_t)(cv.slot_of(2 * v) * 2) * d.zs;
 #pragma unroll
       for (int k = 0; k < REC_OUT; ++k) {
         const int o = threadIdx.x + k * REC_THREADS;
         const int j = (o >> LC) * N2 + j2_0 + (o & ((1 << LC) - 1));
         if (j < n) {
-          z0[j] = tile0[o];
-          z0[d.zs + j] = tile1[o];
+          z0[j] = at(tile0, o);
+          z0[d.zs + j] = at(tile1, o);
         }
       }
-      __syncthreads();
     }
     return;
   }
@@ -1754,8 +1734,9 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
     for (int l = 0; l < NL_FAST; ++l) acc[k][l] = 0;
   }
   if (V > 0) fetch(0);
-  __syncthreads();                                            // root tables
   for (int v = 0; v < V; ++v) {
+    u32* tile0 = tiles + (v & 1) * 2 * TT;
+    u32* tile1 = tile0 + TT;
     if (v == cv.ng0 && v > 0) {                               // Re y' complete
 #pragma unroll
       for (int k = 0; k < REC_OUT; ++k) {
@@ -1767,19 +1748,19 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
         for (int l = 0; l < NL_FAST; ++l) acc[k][l] = 0;
       }
     }
-    *reinterpret_cast<u32x4*>(tile0 + (qi << LC) + qc) = st0;
-    *reinterpret_cast<u32x4*>(tile1 + (qi << LC) + qc) = st1;
-    __syncthreads();
+    put_tile(tile0, st0);
+    put_tile(tile1, st1);
+    __syncthreads();                                          // tiles (and the root tables) complete
     if (v + 1 < V) fetch(v + 1);
-    rounds_dual<M1, 0>(tile0, tile1, LC, tw0, tw1);
+    columns(tile0, tile1);
+    __syncthreads();                                          // columns done
     const int tg = v >= cv.ng0 ? 1 : 0;                       // the signs are applied in the NTT domain
     const int sh = s.groups[tg][v - (tg ? cv.ng0 : 0)].e - s.emin[tg];
 #pragma unroll
     for (int k = 0; k < REC_OUT; ++k) {
       const int o = threadIdx.x + k * REC_THREADS;
-      limb_add(acc[k], garner(tile0[o], tile1[o]), sh);
+      limb_add(acc[k], garner(at(tile0, o), at(tile1, o)), sh);
     }
-    __syncthreads();
   }
   double pi[REC_OUT];
   const bool has_im = V > cv.ng0;
@@ -2153,7 +2134,7 @@ hipError_t launch_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td,
   with_m<7, 9>(g.m1, [&](auto mc) {
     constexpr int M1 = decltype(mc)::value;
     constexpr int LC = 12 - M1;
-    const size_t smem = ((size_t)(2 << M1) + 2 * 4096) * 4;
+    const size_t smem = ((size_t)(2 << M1) + 4 * ((size_t)rec_ldc(M1) << LC)) * 4;
     if ((e = big_lds((const void*)k_inv_cols_rec<M1>)) != hipSuccess) return;
     hipLaunchKernelGGL(k_inv_cols_rec<M1>, dim3(1u << (g.m2 - LC), 1, count), dim3(REC_THREADS), smem, s, G, Z, out,
                        td, ts, kd, tlist, K, g.m2, tb, dir, io32);
