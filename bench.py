@@ -189,13 +189,44 @@ def longdouble_errors(np, y, x):
     return rel, mx
 
 
-def cpu_baseline(xs, n, budget_s):
-    """The oracle, as it is, on transforms of the same workload, one after the
-    other until about budget_s seconds of host time have passed (at least
-    one)."""
+_ORACLE_PLAN = None
+
+
+def _oracle_init(plan):
+    global _ORACLE_PLAN
+    _ORACLE_PLAN = plan
+
+
+def _oracle_one(x):
     from oracle import bluestein as bl
-    # same embedding as the GPU plan (cyclic N = n for a power-of-two n); the
-    # kernel plan is input independent and not timed (as on the GPU)
+    bl.forward_trace(x, 3, 3, _ORACLE_PLAN)
+    return 1
+
+
+def host_cpu():
+    """The host's logical CPU count, the CPUs this process may run on and
+    the processor model line."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)), "model": model}
+
+
+def cpu_baseline(xs, n, budget_s, max_procs=16):
+    """The oracle, as it is, on transforms of the same workload: one process
+    transform after transform until about budget_s seconds have passed (at
+    least one), then all transforms of the batch spread over a pool of
+    processes (at most max_procs, the GPU host's CPU share).  The kernel plan
+    is input independent and not timed (as on the GPU)."""
+    import multiprocessing as mp
+    from oracle import bluestein as bl
+    # same embedding as the GPU plan (cyclic N = n for a power-of-two n)
     plan = bl.KernelPlan(n, 3, 3, cyclic=bl.is_pow2(n))
     t0 = time.perf_counter()
     done = 0
@@ -203,11 +234,141 @@ def cpu_baseline(xs, n, budget_s):
         bl.forward_trace(xs[done], 3, 3, plan)
         done += 1
     dt = time.perf_counter() - t0
-    return {"value": round(done * 5.0 * n * math.log2(n) / dt / 1e9, 6), "unit": "GFLOP/s", "cores": 1,
+    flop = 5.0 * n * math.log2(n)
+    host = host_cpu()
+    procs = max(1, min(max_procs, host["usable_cpus"], len(xs)))
+    with mp.get_context("spawn").Pool(procs, initializer=_oracle_init, initargs=(plan,)) as pool:
+        # every worker started and holding the plan (bounded waits: a worker
+        # that dies would otherwise leave the pool waiting)
+        pool.map_async(_oracle_init, [plan] * procs).get(timeout=600)
+        t1 = time.perf_counter()
+        pool.map_async(_oracle_one, list(xs), chunksize=1).get(timeout=600)
+        dt_pool = time.perf_counter() - t1
+    return {"value": round(len(xs) * flop / dt_pool / 1e9, 6), "unit": "GFLOP/s", "cores": procs,
             "kind": "oracle",
-            "sample": f"{done} transform(s) of the same workload (n={n}, transforms 0..{done - 1}), K=3, L=3, "
-                      f"kernel plan precomputed; {dt:.1f} s wall on the host, single-threaded numpy/Python-int oracle",
-            "seconds": round(dt, 2)}
+            "sample": f"all {len(xs)} transforms of the same workload (n={n}), K=3, L=3, kernel plan precomputed, "
+                      f"one transform per task over {procs} worker processes (numpy/Python-int oracle, "
+                      f"single-threaded per process); {dt_pool:.1f} s wall",
+            "seconds": round(dt_pool, 2),
+            "single_process": {"value": round(done * flop / dt / 1e9, 6), "cores": 1, "transforms": done,
+                               "seconds": round(dt, 2)},
+            "host": host}
+
+
+def events_ms(torch, fn, reps, warmup=3):
+    """Device time per call of fn() between HIP events on torch's current
+    stream (the stream the library launches on), after warmup calls."""
+    for _ in range(warmup):
+        fn()
+    return time_events(torch, lambda k: [fn() for _ in range(k)], reps)
+
+
+def gflops(lengths, ms):
+    return round(sum(5.0 * n * math.log2(n) for n in lengths if n > 1) / (ms * 1e-3) / 1e9, 2)
+
+
+def config_plain_1k(np, torch, oz, wl, reps):
+    """n = 2^10, one transform, uniform[-1, 1] (seed 0): latency of the
+    batched form (graph replay) and of the plain form (one launch per NTT,
+    host synchronisations included), same bits."""
+    x = wl.plain_1k(seed=0)
+    xd = torch.from_numpy(x).cuda()
+    out = {}
+    ys = {}
+    for mode in ("batched", "plain"):
+        plan = oz.Plan(1024, 1, mode=mode)
+        y = torch.empty_like(xd)
+        ms = events_ms(torch, lambda: plan.forward(xd, y), reps)
+        ys[mode] = y.cpu().numpy()
+        out[mode] = {"ms": round(ms, 4), "GFLOPs": gflops([1024], ms)}
+        plan.close()
+    rel, mx = longdouble_errors(np, ys["batched"][0], x[0])
+    out.update({"N": 1024, "rel_l2_error": rel, "max_rel_error": mx,
+                "plain_bit_identical": bool(np.array_equal(ys["plain"].view(np.uint64), ys["batched"].view(np.uint64)))})
+    return out
+
+
+def config_batch64(np, torch, oz, wl, reps, n, gen):
+    """64 transforms of length n, uniform[-1, 1] (seed 0): forward and
+    inverse (batched form), the round trip's largest error relative to the
+    largest input magnitude."""
+    x = gen(seed=0)
+    xd = torch.from_numpy(x).cuda()
+    plan = oz.Plan(n, x.shape[0])
+    y = torch.empty_like(xd)
+    z = torch.empty_like(xd)
+    ms_f = events_ms(torch, lambda: plan.forward(xd, y), reps)
+    ms_i = events_ms(torch, lambda: plan.inverse(y, z), reps)
+    rel, mx = longdouble_errors(np, y[0].cpu().numpy(), x[0])
+    rt = float((z - xd).abs().max() / xd.abs().max())
+    info = plan.transform_info(0)
+    plan.close()
+    return {"n": n, "batch": int(x.shape[0]), "N": info["N"], "forward_ms": round(ms_f, 4),
+            "forward_GFLOPs": gflops([n] * x.shape[0], ms_f), "inverse_ms": round(ms_i, 4),
+            "inverse_GFLOPs": gflops([n] * x.shape[0], ms_i), "rel_l2_error": rel, "max_rel_error": mx,
+            "round_trip_max_error": rt}
+
+
+def config_mixed_256(np, torch, oz, wl, reps):
+    """256 transforms, lengths log-uniform in [2^10, 2^16] (every third moved
+    to a prime), uniform[-1, 1] entries, one graph replay per step; the plan
+    is autotuned (tile shapes of its length classes)."""
+    ns, xs = wl.mixed_256(seed=0)
+    x = np.concatenate(xs)
+    xd = torch.from_numpy(x).cuda()
+    out = {"transforms": len(ns), "total_length": int(sum(ns)), "length_classes": None}
+    for tag, kw in (("default", {}), ("autotuned", {"autotune": True})):
+        plan = oz.Plan(lengths=ns, **kw)
+        y = torch.empty_like(xd)
+        ms = events_ms(torch, lambda: plan.forward(xd, y), reps)
+        out[tag] = {"ms": round(ms, 4), "GFLOPs": gflops(ns, ms)}
+        out["length_classes"] = plan.info()["num_length_classes"]
+        if tag == "default":
+            y0 = y.cpu().numpy()
+        else:
+            out["autotuned"]["bit_identical_to_default"] = bool(np.array_equal(y.cpu().numpy().view(np.uint64),
+                                                                              y0.view(np.uint64)))
+        plan.close()
+    rel, mx = longdouble_errors(np, y0[:ns[0]], xs[0])
+    out.update({"rel_l2_error_transform_0": rel, "max_rel_error_transform_0": mx})
+    return out
+
+
+def config_grad_64k(np, torch, oz, wl, reps):
+    """32 x 2^16 uniform[-1, 1] (seed 0), weights uniform[0, 1] (seed 1):
+    forward + backward of loss = sum(w |DFT(x)|^2) through OzakiDFT (the
+    backward is the adjoint DFT through the same pipeline)."""
+    x, w = wl.grad_64k(seed=0)
+    xd = torch.from_numpy(x).cuda()
+    wd = torch.from_numpy(w).cuda()
+
+    def step():
+        xx = xd.detach().requires_grad_(True)
+        y = oz.OzakiDFT.apply(xx)
+        loss = (wd * (y.real ** 2 + y.imag ** 2)).sum()
+        loss.backward()
+        return xx.grad
+
+    ms = events_ms(torch, step, reps)
+    n, B = x.shape[1], x.shape[0]
+    return {"n": n, "batch": B, "ms_forward_backward": round(ms, 4),
+            "GFLOPs": gflops([n] * (2 * B), ms), "transforms_per_step": 2 * B}
+
+
+def config_per_conv(np, torch, oz, xd, out_ref, reps):
+    """The headline input through the paper's schedule (Alg. 8 for each real
+    convolution, 12 + 40 NTTs per transform) instead of the library's
+    complex accumulation (12 + 20); same bits."""
+    n, B = xd.shape[1], xd.shape[0]
+    plan = oz.Plan(n, B, accumulation="per_conv")
+    y = torch.empty_like(xd)
+    ms = events_ms(torch, lambda: plan.forward(xd, y), reps)
+    i0 = plan.transform_info(0)
+    res = {"ms_per_step": round(ms, 4), "value": gflops([n] * B, ms),
+           "ntt_counts": {"forward_runtime": i0["forward_runtime"], "inverse": i0["inverse"]},
+           "bit_identical_to_headline": bool(torch.equal(y.view(torch.float64), out_ref.view(torch.float64)))}
+    plan.close()
+    return res
 
 
 def main():
@@ -223,6 +384,13 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for HBM counter calibration)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (n = 2^10, 64 x 2^14, 64 x 10007, 256 mixed lengths, "
+                         "32 x 2^16 forward + backward)")
+    ap.add_argument("--config-reps", type=int, default=20)
+    ap.add_argument("--only-config", default=None,
+                    choices=["plain_1k", "batch_16k", "batch_prime", "mixed_256", "grad_64k"],
+                    help="run only this configuration and print its figures (for profiling)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -236,6 +404,18 @@ def main():
 
     import paper_2603_29129_amd as oz
     import workloads as wl
+
+    if args.only_config:
+        r = args.config_reps
+        c = args.only_config
+        res = {"plain_1k": lambda: config_plain_1k(np, torch, oz, wl, r),
+               "batch_16k": lambda: config_batch64(np, torch, oz, wl, r, 16384, wl.batch_16k),
+               "batch_prime": lambda: config_batch64(np, torch, oz, wl, r, 10007, wl.batch_prime),
+               "mixed_256": lambda: config_mixed_256(np, torch, oz, wl, r),
+               "grad_64k": lambda: config_grad_64k(np, torch, oz, wl, r)}[c]()
+        torch.cuda.synchronize()
+        print(json.dumps({"config": c, **res}), flush=True)
+        return
 
     n, B = args.n, args.batch
     print(f"# bench: n={n} batch={B} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
@@ -389,11 +569,33 @@ def main():
         torch.cuda.synchronize()
         pms = (time.perf_counter() - t0) * 1e3 / args.plain_steps
         same = bool(torch.equal(pout.view(torch.float64), out.view(torch.float64)))
+        pms_dev = events_ms(torch, lambda: pplan.forward(xd, pout), args.plain_steps, warmup=0)
         plain = {"ms_per_step": round(pms, 3), "value": round(flops / (pms * 1e-3) / 1e9, 2),
                  "batched_over_plain": round(pms / ms, 2), "bit_identical_to_batched": same,
-                 "timing": "host wall clock (the plain form synchronises the host)"}
+                 "timing": "host wall clock (the plain form synchronises the host)",
+                 "device_event_ms": round(pms_dev, 3),
+                 "batched_over_plain_device_events": round(pms_dev / ms, 2)}
         pplan.close()
         print(f"# plain: {pms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    configs = None
+    per_conv = config_per_conv(np, torch, oz, xd, out, args.steps)
+    print(f"# per-convolution schedule: {per_conv['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_configs:
+        r = args.config_reps
+        configs = {"plain_1k": config_plain_1k(np, torch, oz, wl, r)}
+        print(f"# n=2^10: {configs['plain_1k']['batched']['ms']:.4f} ms batched, "
+              f"{configs['plain_1k']['plain']['ms']:.4f} ms plain", file=sys.stderr, flush=True)
+        configs["batch_16k"] = config_batch64(np, torch, oz, wl, r, 16384, wl.batch_16k)
+        configs["batch_prime"] = config_batch64(np, torch, oz, wl, r, 10007, wl.batch_prime)
+        print(f"# 64 x 2^14: {configs['batch_16k']['forward_ms']:.3f} ms, 64 x 10007: "
+              f"{configs['batch_prime']['forward_ms']:.3f} ms", file=sys.stderr, flush=True)
+        configs["mixed_256"] = config_mixed_256(np, torch, oz, wl, r)
+        print(f"# 256 mixed lengths: {configs['mixed_256']['default']['ms']:.3f} ms "
+              f"(autotuned {configs['mixed_256']['autotuned']['ms']:.3f} ms)", file=sys.stderr, flush=True)
+        configs["grad_64k"] = config_grad_64k(np, torch, oz, wl, r)
+        print(f"# 32 x 2^16 forward+backward: {configs['grad_64k']['ms_forward_backward']:.3f} ms",
+              file=sys.stderr, flush=True)
 
     if args.calibrate_copy:
         a = torch.empty(1 << 25, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -404,7 +606,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(x, n, 12.0)
-        print(f"# cpu oracle: {cpu['seconds']} s", file=sys.stderr, flush=True)
+        print(f"# cpu oracle: {cpu['single_process']['seconds']} s (1 process), {cpu['seconds']} s "
+              f"({cpu['cores']} processes)", file=sys.stderr, flush=True)
 
     counts = infos[0]
     line = {
@@ -435,6 +638,8 @@ def main():
         "ntt_counts": {"forward_runtime": counts["forward_runtime"], "inverse": counts["inverse"],
                        "forward_offline": counts["forward_offline"]},
         "plain": plain,
+        "per_conv_schedule": per_conv,
+        "configs": configs,
         "stages_ms": {str(k): round(v, 4) for k, v in stage_ms.items()},
         "per_kernel": per_kernel,
         "roofline": roofline,

@@ -196,6 +196,9 @@ typedef struct {
                                       and their products weigh 2^xsh[part] in a group; see debug stage 2 */
   int forward_runtime, forward_offline, inverse;
   int ntt_log2N1;                  /* NTT-domain layout: see fft_ozaki_ntt */
+  int tile_cols_log2;              /* two-pass lengths: log2 of the columns per workgroup of the forward
+                                      column pass (the autotuned shape when the plan was autotuned) */
+  int tile_rows_log2;              /* log2 of the rows per workgroup of the standalone row passes */
 } fft_ozaki_transform_info;
 int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_transform_info* info);
 

@@ -31,13 +31,23 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# host-side AddressSanitizer and UndefinedBehaviorSanitizer (the device code
+# is built as usual): a checking build of the host and C-ABI code
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str | None = None) -> str:
+    """Compiles the library to `out` (default: libfft_ozaki.so in the
+    package); sanitize adds the host-side sanitizers."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     inc = "-I" + os.path.join(ROOT, "include")
+    lib = out or LIB
+    extra = HOST_SANITIZE if sanitize else []
     with tempfile.TemporaryDirectory(prefix="fft_ozaki_build_") as tmpd:
         def compile_one(src):
             obj = os.path.join(tmpd, os.path.splitext(src)[0] + ".o")
-            cmd = [hipcc, *FLAGS, inc, "-c", "-o", obj, os.path.join(PKG, "csrc", src)]
+            cmd = [hipcc, *FLAGS, *extra, inc, "-c", "-o", obj, os.path.join(PKG, "csrc", src)]
             if verbose:
                 print(" ".join(cmd), flush=True)
             res = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,16 +59,17 @@ def build(verbose: bool = False) -> str:
             if res.returncode != 0:
                 sys.stderr.write(res.stdout + res.stderr)
                 raise RuntimeError(f"hipcc failed compiling {obj}")
-        tmp = LIB + ".tmp"
-        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in results]]
+        tmp = lib + ".tmp"
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *extra, "-o", tmp, *[o for o, _ in results],
+               "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             sys.stderr.write(res.stdout + res.stderr)
             raise RuntimeError("hipcc failed linking libfft_ozaki.so")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -20,9 +20,12 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "internal.h"
 #include "fft_ozaki.h"
@@ -31,10 +34,39 @@ namespace fo {
 
 static thread_local std::string g_err;
 
+// FFT_OZAKI_LOG=1 (or higher) in the environment: plan decisions and
+// failures are written to stderr, one line each.
+static int log_level() {
+  static const int lvl = [] {
+    const char* v = getenv("FFT_OZAKI_LOG");
+    return v ? atoi(v) : 0;
+  }();
+  return lvl;
+}
+#define FO_LOG(...)                          \
+  do {                                       \
+    if (log_level() > 0) {                   \
+      fprintf(stderr, "[fft_ozaki] ");       \
+      fprintf(stderr, __VA_ARGS__);          \
+      fputc('\n', stderr);                   \
+    }                                        \
+  } while (0)
+
 static int fail(int code, const std::string& msg) {
   g_err = msg;
+  FO_LOG("error %d: %s", code, msg.c_str());
   return code;
 }
+
+// A range in the profiler's marker trace (rocprofv3 --marker-trace) around
+// a host-side step: the execute calls, and each stage of the plain form and
+// of the measurement hook, as in the paper's time breakdown (Sec. 5.5).
+struct Range {
+  explicit Range(const char* name) { roctxRangePush(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 #define HIPCHK(call)                                                                        \
   do {                                                                                      \
@@ -150,12 +182,26 @@ struct fft_ozaki_plan_s {
   // non-null: all device memory is carved from this region (nothing is
   // allocated or freed, no capture stream is created)
   fo::DevArena* arena = nullptr;
+  int fail_at = 0, alloc_count = 0;   // allocation-failure test hook
 };
 
 namespace fo {
 
+// Test hook: FFT_OZAKI_TEST_FAIL_ALLOC=k makes the k-th device allocation of
+// each plan build report failure (as hipMalloc running out of memory would),
+// so the error path and the release of the earlier allocations can be tested.
+static int fail_alloc_at() {
+  const char* v = getenv("FFT_OZAKI_TEST_FAIL_ALLOC");
+  return v ? atoi(v) : 0;
+}
+
 static int dmalloc(fft_ozaki_plan_s* p, void** ptr, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (p->fail_at > 0 && ++p->alloc_count == p->fail_at) {
+    *ptr = nullptr;
+    return fail(FFT_OZAKI_ERR_NOMEM, "device allocation " + std::to_string(p->alloc_count) + " of " +
+                                         std::to_string(bytes) + " bytes failed (injected)");
+  }
   if (p->arena) {
     *ptr = p->arena->carve(bytes);
     if (!*ptr) return fail(FFT_OZAKI_ERR_NOMEM, "static workspace exhausted");
@@ -190,7 +236,13 @@ static const TwStep& step_for(fft_ozaki_plan_s* p, int logN) {
 
 // --- autotuning of the NTT tile shapes -------------------------------------
 // Candidate (log2 columns per workgroup, log2 rows per workgroup) pairs are
-// timed on a scratch vector; every candidate computes the same transform.
+// timed on scratch vectors through the standalone two-pass NTT (forward and
+// inverse); every candidate computes the same transform.  The column shape
+// is the one the batched schedule's forward column pass uses (the same
+// column body); the row shape is used by the standalone row passes (the
+// three-modulus plans and the plain form).  The pipelined row pass sizes its
+// grid from the device's occupancy and the fused column pass has a fixed
+// 4096-position tile, so neither has a shape to tune.
 
 static std::string tune_key(int logN) {
   int dev = 0;
@@ -254,20 +306,23 @@ static int autotune_geom(fft_ozaki_plan_s* p, int logN, NttGeom* out) {
     for (int r = 0; r <= 4; ++r) {
       if (def.m2 + r > 14 || r > def.m1) continue;
       NttGeom g = ntt_geom(logN, c, r);
-      for (int w = 0; w < 2; ++w) {
-        (void)launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr);
-        (void)launch_ntt_standalone(buf, logN, 0, vecs, true, g, p->tb, st, nullptr);
-      }
+      hipError_t le = hipSuccess;                           // a shape whose launch fails is not a candidate
+      auto pair = [&]() {
+        const hipError_t a = launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr);
+        const hipError_t b = launch_ntt_standalone(buf, logN, 0, vecs, true, g, p->tb, st, nullptr);
+        if (le == hipSuccess) le = a != hipSuccess ? a : b;
+      };
+      for (int w = 0; w < 2; ++w) pair();
       HIPCHK(hipEventRecord(e0, nullptr));
-      for (int w = 0; w < 5; ++w) {
-        (void)launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr);
-        (void)launch_ntt_standalone(buf, logN, 0, vecs, true, g, p->tb, st, nullptr);
-      }
+      for (int w = 0; w < 5; ++w) pair();
       HIPCHK(hipEventRecord(e1, nullptr));
       HIPCHK(hipEventSynchronize(e1));
       float ms = 0;
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (hipGetLastError() == hipSuccess && ms < best) {
+      const hipError_t ke = hipGetLastError();
+      FO_LOG("autotune N=2^%d: column tile 2^%d, row tile 2^%d: %.4f ms%s", logN, c, r, ms,
+             (le != hipSuccess || ke != hipSuccess) ? " (launch failed, skipped)" : "");
+      if (le == hipSuccess && ke == hipSuccess && ms < best) {
         best = ms;
         *out = g;
       }
@@ -305,6 +360,8 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
       *ptr = p->arena->carve(bytes);
       return *ptr ? FFT_OZAKI_OK : fail(FFT_OZAKI_ERR_NOMEM, "static workspace exhausted");
     }
+    if (p->fail_at > 0 && ++p->alloc_count == p->fail_at)
+      return fail(FFT_OZAKI_ERR_NOMEM, "device allocation " + std::to_string(p->alloc_count) + " failed (injected)");
     hipError_t e = hipMalloc(ptr, bytes);
     if (e != hipSuccess) return fail(FFT_OZAKI_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     temps.push_back(*ptr);
@@ -376,6 +433,8 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
 static int build_plan(fft_ozaki_plan_s* p) {
   const int K = p->K;
   const int count = (int)p->lengths.size();
+  p->fail_at = fail_alloc_at();
+  p->alloc_count = 0;
   HIPCHK(hipGetDevice(&p->device));
   void* tw_allocs[2 * NPRIME_MAX] = {};
   if (build_block_twiddles(&p->tb, tw_allocs, p->arena)) return fail(FFT_OZAKI_ERR_NOMEM, "twiddle tables");
@@ -510,6 +569,15 @@ static int build_plan(fft_ozaki_plan_s* p) {
   }
   if (!p->arena) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
   HIPCHK(hipDeviceSynchronize());
+  FO_LOG("plan: %d transforms, %zu distinct lengths, %zu length classes, K=%d L=%d mode=%d primes=%d, "
+         "workspace %lld bytes%s",
+         count, p->kernels.size(), p->classes.size(), K, p->L, p->mode, p->primes, (long long)p->bytes,
+         p->arena ? " (static workspace)" : "");
+  for (auto& lc : p->classes)
+    FO_LOG("  class N=2^%d: %zu transforms, N1=2^%d N2=2^%d, column tile 2^%d, row tile 2^%d%s%s", lc.logN,
+           lc.tids.size(), lc.geom.m1, lc.geom.m2, lc.geom.lc, lc.geom.lrows,
+           fused_rows_ok(lc.geom, K) ? ", forward rows folded into the pipelined row pass" : "",
+           fused_cols_ok(lc.geom) ? ", CRT fused into the column pass" : "");
   return FFT_OZAKI_OK;
 }
 
@@ -652,6 +720,8 @@ static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, 
   hipGraphExec_t exec;
   HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   (void)hipGraphDestroy(graph);
+  FO_LOG("captured the batched schedule for in=%p out=%p direction=%d (%zu graphs cached before)", in, (void*)out,
+         dir, p->graphs.size());
   if (p->graphs.size() >= 4) {
     (void)hipStreamSynchronize(s);
     (void)hipGraphExecDestroy(p->graphs.front().exec);
@@ -673,6 +743,8 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
       return ntt_geom(d.logN);
     }();
     const TwStep& st = step_for(p, d.logN);
+    Range rt("transform");
+    std::unique_ptr<Range> stage(new Range("premultiply + split"));
     HIPCHK(launch_reset(p->d_ts, tl, 1, s));
     HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, io32_of(p), s));
     HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, tl, 1, K, s));
@@ -684,17 +756,20 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
       HIPCHK(hipStreamSynchronize(s));
       if (!act[0] && !act[1]) break;
     }
+    stage.reset(new Range("accumulation schedule"));
     HIPCHK(launch_groups(p->d_td, p->d_ts, p->d_kd, tl, 1, K, p->L, s));
     TState hs;
     HIPCHK(hipMemcpyAsync(&hs, &p->d_ts[t], sizeof hs, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (!hs.status) {
+      stage.reset(new Range("forward NTTs"));
       for (int part = 0; part < 2; ++part)
         for (int k = 0; k < hs.kx[part]; ++k)
           for (int prime = 0; prime < 2; ++prime) {
             const int vi = (part * K + k) * 2 + prime;
             HIPCHK(launch_fwd_pipeline(p->X, p->d_td, p->d_ts, tl, 1, K, false, vi, vi + 1, g, p->tb, st, s));
           }
+      stage.reset(new Range("NTT-domain multiply-accumulate + inverse NTTs"));
       for (int tg = 0; tg < 2; ++tg)
         for (int gi = 0; gi < hs.ngroups[tg]; ++gi) {
           const int slot = tg * SL + gi;
@@ -702,6 +777,7 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
                                      st, s));
         }
     }
+    stage.reset(new Range("CRT + recombination + postmultiply"));
     HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, tl, 1, d.n, K, dir, io32_of(p), s));
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -709,8 +785,13 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
 }
 
 // One stage of the batched sequence for all transforms (measurement hook).
+static const char* const kStageNames[9] = {"", "stage 1: premultiply + split", "stage 2: accumulation schedule",
+                                            "stage 3: forward NTTs", "stage 4: forward column pass",
+                                            "stage 5: forward row pass", "stage 6: row pass (fused MAC)",
+                                            "stage 7: column pass (fused CRT)", "stage 8: recombination"};
 static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
   const int K = p->K, count = (int)p->td.size();
+  Range range(stage >= 1 && stage <= 8 ? kStageNames[stage] : "stage");
   const void* in = p->last_in;
   void* out = p->last_out;
   const int dir = p->last_dir;
@@ -937,6 +1018,7 @@ int fft_ozaki_execute(fft_ozaki_plan_t plan, const void* in, void* out, int dire
   plan->last_in = in;
   plan->last_out = out;
   plan->last_dir = direction;
+  Range range(plan->mode == FFT_OZAKI_MODE_PLAIN ? "fft_ozaki_execute (plain)" : "fft_ozaki_execute (batched)");
   int rc = plan->mode == FFT_OZAKI_MODE_PLAIN ? run_plain(plan, in, out, direction, s)
                                               : run_batched(plan, in, out, direction, s);
   if (cur != plan->device) (void)hipSetDevice(cur);
@@ -1006,6 +1088,11 @@ int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_tr
   info->forward_offline = fo_;
   info->inverse = iv;
   info->ntt_log2N1 = ntt_geom(d.logN).m1;
+  for (auto& lc : plan->classes)
+    if (lc.logN == d.logN) {
+      info->tile_cols_log2 = lc.geom.lc;
+      info->tile_rows_log2 = lc.geom.lrows;
+    }
   return FFT_OZAKI_OK;
 }
 

@@ -48,13 +48,29 @@ def longdouble_errors(y, x):
     return mx, rel
 
 
-def run_case(n: int, K, L: int, phi: float, batch: int = 4, seed: int = 0) -> dict:
-    """One configuration on cuda:0."""
+def inputs(n: int, phi: float, seed: int = 0, batch: int = 1):
+    """The paper's test inputs (Sec. 5.1): real and imaginary parts each
+    (rand - 0.5) exp(phi randn), rand uniform on (0, 1], drawn from numpy's
+    PCG64 generator with the given seed: all real parts of the batch, then
+    all imaginary parts, each as a (batch, n) block of rand then randn."""
+    rng = np.random.default_rng(seed)
+
+    def part():
+        rand = 1.0 - rng.random((batch, n))
+        return (rand - 0.5) * np.exp(phi * rng.standard_normal((batch, n)))
+
+    re = part()
+    return re + 1j * part()
+
+
+def run_case(n: int, K, L: int, phi: float, batch: int = 4, seed: int = 0, x=None) -> dict:
+    """One configuration on cuda:0 (inputs from `inputs` unless x, a
+    (batch, n) complex128 array, is given)."""
     import torch
     import paper_2603_29129_amd as oz
-    import workloads as wl
     k = K_INF if K == "inf" else int(K)
-    x = wl.paper_phi(n, phi, seed=seed, batch=batch)
+    if x is None:
+        x = inputs(n, phi, seed=seed, batch=batch)
     xt = torch.from_numpy(x).cuda()
     runs = {}
     for acc in ("per_conv", "complex"):

@@ -83,3 +83,76 @@ def test_graph_replays_with_new_data(torch_mod, primes):
         else:
             want = oz.Plan(n, B, primes=3).forward(x)
         assert torch.equal(yout.view(torch.float64), want.view(torch.float64)), r
+
+
+def test_autotuned_plans_bit_identical(torch_mod, tmp_path):
+    """Plans with autotuned tile shapes give the default plan's bits (and the
+    oracle's on a sampled transform); a second plan reads the tune cache and
+    takes the same shapes."""
+    import paper_2603_29129_amd as oz
+    from oracle import bluestein as bl
+    from tests.gpu_helpers import max_ulp
+    torch = torch_mod
+    cache = str(tmp_path / "tune.txt")
+    ns, xs = wl.mixed_256(seed=0, count=24)          # lengths over the classes N = 2^12 .. 2^17
+    cases = [[1 << 14] * 2, [1 << 18] * 2, ns]
+    for lengths in cases:
+        if lengths is ns:
+            x = np.concatenate(xs)
+        else:
+            x = wl.uniform(lengths[0], batch=len(lengths), seed=3).reshape(-1)
+        xd = torch.from_numpy(x).cuda()
+        ref = oz.Plan(lengths=lengths).forward(xd).cpu().numpy()
+        p1 = oz.Plan(lengths=lengths, autotune=True, tune_cache=cache)
+        y1 = p1.forward(xd).cpu().numpy()
+        assert np.array_equal(y1.view(np.uint64), ref.view(np.uint64)), lengths[:2]
+        shapes1 = [(p1.transform_info(i)["tile_cols_log2"], p1.transform_info(i)["tile_rows_log2"])
+                   for i in range(len(lengths))]
+        p2 = oz.Plan(lengths=lengths, autotune=True, tune_cache=cache)
+        y2 = p2.forward(xd).cpu().numpy()
+        shapes2 = [(p2.transform_info(i)["tile_cols_log2"], p2.transform_info(i)["tile_rows_log2"])
+                   for i in range(len(lengths))]
+        assert shapes1 == shapes2
+        assert np.array_equal(y2.view(np.uint64), ref.view(np.uint64))
+        if lengths[0] == 1 << 14:
+            want = bl.fft(x[: 1 << 14], 3, 3, bl.KernelPlan(1 << 14, 3, 3, cyclic=True))
+            assert max_ulp(y1[: 1 << 14], want) == 0
+    with open(cache) as f:
+        keys = [line.split()[0] for line in f if line.strip()]
+    assert any(k.endswith(":18") for k in keys) and any(k.endswith(":14") for k in keys)
+
+
+def test_injected_allocation_failure(torch_mod, monkeypatch):
+    """A device allocation that fails during planning returns
+    FFT_OZAKI_ERR_NOMEM with a message, releases what was allocated, and
+    leaves the library usable."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    x = torch.from_numpy(wl.uniform(1 << 14, batch=2, seed=4)).cuda()
+    want = oz.Plan(1 << 14, 2).forward(x).cpu().numpy()
+    free0 = torch.cuda.mem_get_info()[0]
+    for k in (1, 2, 5, 9, 13):
+        monkeypatch.setenv("FFT_OZAKI_TEST_FAIL_ALLOC", str(k))
+        with pytest.raises(oz.FftOzakiError, match=r"out of memory \(-2\).*injected"):
+            oz.Plan(1 << 14, 2)
+    monkeypatch.delenv("FFT_OZAKI_TEST_FAIL_ALLOC")
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] >= free0 - (64 << 20)      # the failed plans freed their workspace
+    got = oz.Plan(1 << 14, 2).forward(x).cpu().numpy()
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_log_lines(tmp_path):
+    """FFT_OZAKI_LOG=1 reports the plan and the graph capture on stderr."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import torch, paper_2603_29129_amd as oz\n"
+            "x = torch.zeros(2, 1 << 14, dtype=torch.complex128, device='cuda')\n"
+            "oz.Plan(1 << 14, 2).forward(x); torch.cuda.synchronize(); print('done', flush=True)\n")
+    env = dict(os.environ, FFT_OZAKI_LOG="1", PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=100, cwd=root)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "[fft_ozaki] plan: 2 transforms" in r.stderr
+    assert "class N=2^14" in r.stderr and "captured the batched schedule" in r.stderr

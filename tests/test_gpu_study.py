@@ -17,9 +17,9 @@ def test_study_counts_match_oracle(phi):
     import paper_2603_29129_amd.study as st
     n, batch = 1024, 2
     for K, L in st.KL_GRID:
-        r = st.run_case(n, K, L, phi, batch=batch, seed=0)
-        k = st.K_INF if K == "inf" else K
         x = wl.paper_phi(n, phi, seed=0, batch=batch)
+        r = st.run_case(n, K, L, phi, batch=batch, x=x)
+        k = st.K_INF if K == "inf" else K
         kp = bl.KernelPlan(n, k, L, cyclic=True)
         counts = [bl.ntt_counts(bl.forward_trace(x[b], k, L, kp), kp) for b in range(batch)]
         assert r["ntt_runtime"] == max(c["runtime"] for c in counts), (K, L)
