@@ -61,13 +61,11 @@ def fused_columns(info):
 
 def folded_rows(info, K):
     """The batched form folds the forward row pass into the inverse row pass
-    (register form, K <= 3, 512-position row tiles that hold the 2K forward
-    slice rows)."""
+    (register form, K <= 3, 512-position row tiles: the pipelined row pass)."""
     logN, m1 = info["N"].bit_length() - 1, info["ntt_log2N1"]
     m2 = logN - m1
     li = min(max(9 - m2, 0), m1)
-    gch = max(1, (20 if m2 <= 9 else 20 >> (m2 - 9)) >> li)
-    return logN > 12 and K <= 3 and m2 + li == 9 and 2 * K <= gch
+    return logN > 12 and K <= 3 and m2 + li == 9
 
 
 def stage_kernels(info, K):

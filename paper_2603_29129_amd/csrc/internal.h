@@ -72,9 +72,11 @@ __device__ __forceinline__ bool vec_live(const VecSel& sel, int idx) {
 // Standalone transforms of `count` contiguous vectors (natural order in for the
 // forward transform, NTT-domain order out; the inverse takes NTT-domain order
 // and returns natural order multiplied by N^{-1}); `sel` skips vectors.
+// which (two-pass lengths): 0 both passes, 1 the column pass only, 2 the
+// row pass only (the autotuner times the passes separately).
 hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool inverse,
                                  const NttGeom& g, const TwBlock& tb, const TwStep& ts, hipStream_t s,
-                                 const VecSel& sel = VecSel{});
+                                 const VecSel& sel = VecSel{}, int which = 0);
 
 // Pipeline: forward NTTs of the slice residues of the listed transforms
 // (vector index vi = (part*K + k)*2 + prime; only k < kx[part] are done).

@@ -70,6 +70,10 @@ __host__ __device__ constexpr int row_ldl(int M) { return PL == 9 ? pad9(M) : ro
 constexpr int UNR = 4;           // 16-byte global loads in flight per thread
 constexpr int INV_TILE_ROWS = 20;        // group rows per inverse chunk: the 20 groups of K = L = 3 fit, 3 workgroups per CU
 constexpr int KT = 3;            // slices per operand handled from registers in the fused MAC
+// Group tiles (INV_ROW_THREADS = 512 positions each: nr rows of N2) in the
+// LDS of the pipelined row pass, whatever N2: forward slice tiles (2K) and
+// inverse group tiles share them.
+constexpr int PIPE_TILES = 20;
 
 // RL radix-2 stages (s = S0 .. S0+RL-1) on the 2^RL registers of one group of
 // a length-2^M transform.  The group holds elements base + j*ST, base =
@@ -1305,7 +1309,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_pipe(const u32*
   constexpr int PL = 9;
   constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ldl<PL>(N2), NW = INV_ROW_THREADS / 64;
   const int lrows = g.lrows_inv, nr = 1 << lrows, SL = 2 * K * K;
-  const int gch = max(1, inv_vmax(m2) >> lrows);            // group tiles in LDS
+  const int gch = PIPE_TILES;                                 // group tiles in LDS
   const int gA = gch - 2 * K;                                 // region A: inverse group tiles per chunk
   const int tstride = nr * ldr;                               // words per group tile
   const u32 Nmask = (1u << g.logN) - 1;
@@ -1842,7 +1846,7 @@ static size_t smem_inv_rows(const NttGeom& g) {
 // LDS of k_inv_rows_pipe: inverse and forward block roots, then gch group
 // tiles of nr pad9 rows.
 static size_t smem_inv_pipe(const NttGeom& g) {
-  const int gch = std::max(1, inv_vmax(g.m2) >> g.lrows_inv);
+  const int gch = PIPE_TILES;
   return ((size_t)(2 << g.m2) + 4 + (size_t)gch * ((size_t)pad9(1 << g.m2) << g.lrows_inv)) * 4;
 }
 // Workgroups of `fn` that the device runs at once (occupancy x CUs), cached
@@ -1897,7 +1901,7 @@ static hipError_t big_lds(const void* fn) {
 }
 
 hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool inverse, const NttGeom& g,
-                                 const TwBlock& tb, const TwStep& ts, hipStream_t s, const VecSel& sel) {
+                                 const TwBlock& tb, const TwStep& ts, hipStream_t s, const VecSel& sel, int which) {
   if (count <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
   if (!g.two_pass()) {
@@ -1931,14 +1935,15 @@ hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool
       hipLaunchKernelGGL(k_std_inv_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts, sel);
     }
   };
+  const bool do_cols = which != 2, do_rows = which != 1;
   if (!inverse) {
-    if (!with_m<M1_LO, M1_HI>(g.m1, cols)) return hipErrorInvalidValue;
+    if (do_cols && !with_m<M1_LO, M1_HI>(g.m1, cols)) return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
-    if (!with_m<M2_LO, M2_HI>(g.m2, rows)) return hipErrorInvalidValue;
+    if (do_rows && !with_m<M2_LO, M2_HI>(g.m2, rows)) return hipErrorInvalidValue;
   } else {
-    if (!with_m<M2_LO, M2_HI>(g.m2, rows)) return hipErrorInvalidValue;
+    if (do_rows && !with_m<M2_LO, M2_HI>(g.m2, rows)) return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
-    if (!with_m<M1_LO, M1_HI>(g.m1, cols)) return hipErrorInvalidValue;
+    if (do_cols && !with_m<M1_LO, M1_HI>(g.m1, cols)) return hipErrorInvalidValue;
   }
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -2033,9 +2038,9 @@ hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const 
 }
 
 bool fused_rows_ok(const NttGeom& g, int K) {
-  // the forward rows of the 2K slice vectors must fit the group tile
-  const int gch = std::max(1, inv_vmax(g.m2) >> g.lrows_inv);
-  return g.two_pass() && K <= KT && (1 << (g.m2 + g.lrows_inv)) == INV_ROW_THREADS && 2 * K <= gch;
+  // register form (K <= KT, 512-position row tiles), and the 2K forward
+  // slice tiles leave room for inverse group tiles in the pipelined pass
+  return g.two_pass() && K <= KT && (1 << (g.m2 + g.lrows_inv)) == INV_ROW_THREADS && 2 * K < PIPE_TILES;
 }
 
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,

@@ -235,21 +235,30 @@ static const TwStep& step_for(fft_ozaki_plan_s* p, int logN) {
 }
 
 // --- autotuning of the NTT tile shapes -------------------------------------
-// Candidate (log2 columns per workgroup, log2 rows per workgroup) pairs are
-// timed on scratch vectors through the standalone two-pass NTT (forward and
-// inverse); every candidate computes the same transform.  The column shape
-// is the one the batched schedule's forward column pass uses (the same
-// column body); the row shape is used by the standalone row passes (the
-// three-modulus plans and the plain form).  The pipelined row pass sizes its
-// grid from the device's occupancy and the fused column pass has a fixed
-// 4096-position tile, so neither has a shape to tune.
+// Two shapes per length class are tuned by timing them on scratch vectors as
+// many as the class's slice vectors (4 K per transform, up to 256 MiB), with
+// the plan's own twiddle tables:
+//  * log2 columns per workgroup of the column passes: the forward column
+//    pass alone (the same column body runs as the first pass of the batched
+//    schedule's forward NTTs);
+//  * log2 rows per workgroup of the standalone row passes: forward and
+//    inverse row passes (they run in the three-modulus plans and in the
+//    plain form).
+// Every candidate computes the same transform, so results do not depend on
+// the shapes.  The pipelined row pass sizes its grid from the device's
+// occupancy and the fused column pass has a fixed 4096-position tile, so
+// neither has a shape to tune.  The tune cache key holds the GPU
+// architecture, log2 N and the scratch vector count rounded up to a power
+// of two.
 
-static std::string tune_key(int logN) {
+static std::string tune_key(int logN, int vecs) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   hipDeviceProp_t pr;
   (void)hipGetDeviceProperties(&pr, dev);
-  return std::string(pr.gcnArchName) + ":" + std::to_string(logN);
+  int v = 1;
+  while (v < vecs) v <<= 1;
+  return std::string(pr.gcnArchName) + ":" + std::to_string(logN) + ":" + std::to_string(v);
 }
 
 static bool tune_lookup(const std::string& path, const std::string& key, int* lc, int* lr) {
@@ -279,58 +288,81 @@ static void tune_store(const std::string& path, const std::string& key, int lc, 
   fclose(f);
 }
 
-static int autotune_geom(fft_ozaki_plan_s* p, int logN, NttGeom* out) {
+static int autotune_geom(fft_ozaki_plan_s* p, int logN, int transforms, NttGeom* out) {
   NttGeom def = ntt_geom(logN);
   *out = def;
   if (!def.two_pass()) return FFT_OZAKI_OK;
-  const std::string key = tune_key(logN);
+  const size_t vec_bytes = (size_t)4 << logN;
+  const int vecs = (int)std::max<size_t>(1, std::min<size_t>((size_t)4 * p->K * transforms,
+                                                             std::min<size_t>(65535, ((size_t)256 << 20) / vec_bytes)));
+  const std::string key = tune_key(logN, vecs);
+  auto lc_ok = [&](int c) { return c >= 2 && c <= 6 && def.m1 + c <= 14 && c <= def.m2; };
+  auto lr_ok = [&](int r) { return r >= 0 && r <= 4 && def.m2 + r <= 14 && r <= def.m1; };
   int lc = -1, lr = -1;
   // a cached entry is used only if it is one of the shapes tried below
-  if (tune_lookup(p->tune_cache, key, &lc, &lr) && lc >= 2 && lc <= 6 && def.m1 + lc <= 14 && lc <= def.m2 &&
-      lr >= 0 && lr <= 4 && def.m2 + lr <= 14 && lr <= def.m1) {
+  if (tune_lookup(p->tune_cache, key, &lc, &lr) && lc_ok(lc) && lr_ok(lr)) {
     *out = ntt_geom(logN, lc, lr);
+    FO_LOG("autotune N=2^%d (%d vectors): cached column tile 2^%d, row tile 2^%d", logN, vecs, lc, lr);
     return FFT_OZAKI_OK;
   }
-  const int vecs = 8;
   u32* buf = nullptr;
-  const size_t words = (size_t)vecs << logN;
-  HIPCHK(hipMalloc(&buf, words * 4));
-  HIPCHK(hipMemset(buf, 0, words * 4));
+  HIPCHK(hipMalloc(&buf, vec_bytes * vecs));
+  struct Free {
+    u32* b;
+    ~Free() { (void)hipFree(b); }
+  } free_buf{buf};
+  HIPCHK(hipMemset(buf, 0, vec_bytes * vecs));
   const TwStep& st = step_for(p, logN);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  float best = 1e30f;
+  // time `reps` calls of run(g) after two untimed ones; a shape whose launch
+  // fails is not a candidate (infinite time)
+  auto time_shape = [&](const NttGeom& g, auto run) -> float {
+    hipError_t le = hipSuccess;
+    auto once = [&]() {
+      const hipError_t e = run(g);
+      if (le == hipSuccess) le = e;
+    };
+    once();
+    once();
+    if (hipEventRecord(e0, nullptr) != hipSuccess) return 1e30f;
+    for (int w = 0; w < 5; ++w) once();
+    if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1e30f;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 1e30f;
+    const hipError_t ke = hipGetLastError();
+    return (le == hipSuccess && ke == hipSuccess) ? ms : 1e30f;
+  };
+  float best_c = 1e30f, best_r = 1e30f;
+  int pick_c = def.lc, pick_r = def.lrows;
   for (int c = 2; c <= 6; ++c) {
-    if (def.m1 + c > 14 || c > def.m2) continue;
-    for (int r = 0; r <= 4; ++r) {
-      if (def.m2 + r > 14 || r > def.m1) continue;
-      NttGeom g = ntt_geom(logN, c, r);
-      hipError_t le = hipSuccess;                           // a shape whose launch fails is not a candidate
-      auto pair = [&]() {
-        const hipError_t a = launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr);
-        const hipError_t b = launch_ntt_standalone(buf, logN, 0, vecs, true, g, p->tb, st, nullptr);
-        if (le == hipSuccess) le = a != hipSuccess ? a : b;
-      };
-      for (int w = 0; w < 2; ++w) pair();
-      HIPCHK(hipEventRecord(e0, nullptr));
-      for (int w = 0; w < 5; ++w) pair();
-      HIPCHK(hipEventRecord(e1, nullptr));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      const hipError_t ke = hipGetLastError();
-      FO_LOG("autotune N=2^%d: column tile 2^%d, row tile 2^%d: %.4f ms%s", logN, c, r, ms,
-             (le != hipSuccess || ke != hipSuccess) ? " (launch failed, skipped)" : "");
-      if (le == hipSuccess && ke == hipSuccess && ms < best) {
-        best = ms;
-        *out = g;
-      }
+    if (!lc_ok(c)) continue;
+    const float ms = time_shape(ntt_geom(logN, c, def.lrows), [&](const NttGeom& g) {
+      return launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr, VecSel{}, 1);
+    });
+    FO_LOG("autotune N=2^%d (%d vectors): column tile 2^%d: %.4f ms", logN, vecs, c, ms);
+    if (ms < best_c) {
+      best_c = ms;
+      pick_c = c;
+    }
+  }
+  for (int r = 0; r <= 4; ++r) {
+    if (!lr_ok(r)) continue;
+    const float ms = time_shape(ntt_geom(logN, pick_c, r), [&](const NttGeom& g) {
+      const hipError_t a = launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr, VecSel{}, 2);
+      const hipError_t b = launch_ntt_standalone(buf, logN, 0, vecs, true, g, p->tb, st, nullptr, VecSel{}, 2);
+      return a != hipSuccess ? a : b;
+    });
+    FO_LOG("autotune N=2^%d (%d vectors): row tile 2^%d: %.4f ms", logN, vecs, r, ms);
+    if (ms < best_r) {
+      best_r = ms;
+      pick_r = r;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(buf);
+  *out = ntt_geom(logN, pick_c, pick_r);
   tune_store(p->tune_cache, key, out->lc, out->lrows);
   return FFT_OZAKI_OK;
 }
@@ -460,6 +492,8 @@ static int build_plan(fft_ozaki_plan_s* p) {
       p->classes.push_back(lc);
     }
   }
+  std::map<int, int> class_count;
+  for (i64 n : p->lengths) ++class_count[conv_log2(n, p->cyclic)];
   for (auto& lc : p->classes) {
     if (ntt_geom(lc.logN).two_pass() && !p->steps.count(lc.logN)) {
       void* sa[4 * NPRIME_MAX] = {};
@@ -471,7 +505,7 @@ static int build_plan(fft_ozaki_plan_s* p) {
     }
     lc.geom = ntt_geom(lc.logN);
     if (p->autotune) {
-      int rc = autotune_geom(p, lc.logN, &lc.geom);
+      int rc = autotune_geom(p, lc.logN, class_count[lc.logN], &lc.geom);
       if (rc) return rc;
     }
   }
