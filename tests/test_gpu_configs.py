@@ -171,3 +171,60 @@ def test_maximum_length(torch_mod, n):
         p2 = oz.Plan(n, 2)
         y2 = p2.forward(_gpu(torch, x2)).cpu().numpy()
         assert np.array_equal(y2[1].view(np.uint64), yh.view(np.uint64))
+
+
+def test_prime_near_2_18(torch_mod):
+    """n = 262139 (prime, convolution length 2^19, N1 = 1024: the pipelined
+    row pass, then the column pass and the recombination as separate
+    kernels): both transforms of a batch 0 ulp from the oracle on wide-range
+    inputs, and equal to the plain form (one launch per NTT)."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 262139
+    x = wl.wide_256k(seed=2, batch=2, n=n)
+    xd = _gpu(torch, x)
+    plan = oz.Plan(n, 2)
+    assert plan.transform_info(0)["N"] == 1 << 19 and plan.transform_info(0)["ntt_log2N1"] == 10
+    y = plan.forward(xd).cpu().numpy()
+    yp = oz.Plan(n, 2, mode="plain").forward(xd).cpu().numpy()
+    assert np.array_equal(y.view(np.uint64), yp.view(np.uint64))
+    kp = bl.KernelPlan(n, 3, 3)
+    for b in range(2):
+        assert max_ulp(y[b], bl.fft(x[b], 3, 3, kp)) == 0, b
+
+
+def test_padded_2_18_and_wide_span(torch_mod):
+    """The padded embedding of n = 2^18 (N = 2^19) gives the cyclic
+    embedding's bits; a transform whose group exponents span about 300 bits
+    (wide accumulator in the recombination) is 0 ulp from the oracle in
+    both."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = 1 << 18
+    x = wl.uniform(n, batch=2, seed=31)
+    x[1, ::2] *= 2.0 ** -300
+    xd = _gpu(torch, x)
+    yc = oz.Plan(n, 2, K=8).forward(xd).cpu().numpy()
+    pad = oz.Plan(n, 2, K=8, cyclic=False)
+    assert pad.transform_info(0)["N"] == 1 << 19
+    yp = pad.forward(xd).cpu().numpy()
+    assert np.array_equal(yc.view(np.uint64), yp.view(np.uint64))
+    want = bl.fft(x[1], 8, 3, bl.KernelPlan(n, 8, 3))
+    assert max_ulp(yp[1], want) == 0
+
+
+def test_length_2_19_two_pass_n1_1024_n2_1024(torch_mod):
+    """n = 2^19 - 1 (N = 2^20: N1 = N2 = 1024, the general row pass and the
+    unfused column pass): batched equals plain, and the transform is 0 ulp
+    from the oracle."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n = (1 << 19) - 1
+    x = wl.uniform(n, batch=1, seed=32)
+    xd = _gpu(torch, x)
+    plan = oz.Plan(n, 1)
+    assert plan.transform_info(0)["N"] == 1 << 20
+    y = plan.forward(xd).cpu().numpy()
+    yp = oz.Plan(n, 1, mode="plain").forward(xd).cpu().numpy()
+    assert np.array_equal(y.view(np.uint64), yp.view(np.uint64))
+    assert max_ulp(y[0], bl.fft(x[0], 3, 3, bl.KernelPlan(n, 3, 3))) == 0
