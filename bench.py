@@ -353,6 +353,26 @@ def config_grad_64k(np, torch, oz, wl, reps):
             "GFLOPs": gflops([n] * (2 * B), ms), "transforms_per_step": 2 * B}
 
 
+def rotating_buffers(np, torch, oz, plan, xd, out_ref, reps, pairs=8):
+    """The headline plan executed over `pairs` (in, out) pairs in turn (one
+    captured graph, its array pointers rebound per call) against the same
+    plan on one fixed pair; the outputs of every pair equal the headline's."""
+    xs = [xd.clone() for _ in range(pairs)]
+    outs = [torch.empty_like(xd) for _ in range(pairs)]
+    state = {"i": 0}
+
+    def one():
+        i = state["i"] % pairs
+        plan.forward(xs[i], outs[i])
+        state["i"] += 1
+
+    ms_rot = events_ms(torch, one, reps * pairs, warmup=pairs)
+    ms_fix = events_ms(torch, lambda: plan.forward(xd, out_ref), reps)
+    same = all(torch.equal(o.view(torch.float64), out_ref.view(torch.float64)) for o in outs)
+    return {"pairs": pairs, "ms_per_call_rotating": round(ms_rot, 4), "ms_per_call_fixed_pair": round(ms_fix, 4),
+            "bit_identical": bool(same)}
+
+
 def config_per_conv(np, torch, oz, xd, out_ref, reps):
     """The headline input through the paper's schedule (Alg. 8 for each real
     convolution, 12 + 40 NTTs per transform) instead of the library's
@@ -577,6 +597,9 @@ def main():
         print(f"# plain: {pms:.3f} ms/step", file=sys.stderr, flush=True)
 
     configs = None
+    rotating = rotating_buffers(np, torch, oz, plan, xd, out, args.steps)
+    print(f"# {rotating['pairs']} rotating buffer pairs: {rotating['ms_per_call_rotating']:.3f} ms per call "
+          f"(fixed pair {rotating['ms_per_call_fixed_pair']:.3f})", file=sys.stderr, flush=True)
     per_conv = config_per_conv(np, torch, oz, xd, out, args.steps)
     print(f"# per-convolution schedule: {per_conv['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_configs:
@@ -636,6 +659,7 @@ def main():
         "ntt_counts": {"forward_runtime": counts["forward_runtime"], "inverse": counts["inverse"],
                        "forward_offline": counts["forward_offline"]},
         "plain": plain,
+        "rotating_buffers": rotating,
         "per_conv_schedule": per_conv,
         "configs": configs,
         "stages_ms": {str(k): round(v, 4) for k, v in stage_ms.items()},

@@ -167,6 +167,14 @@ struct TState {
   int span[2];             // per output component: largest shift above emin
 };
 
+// The caller's input and output arrays of one execution, read by the
+// kernels from device memory: a captured graph of the batched schedule then
+// serves any (in, out) pair, the pointers being written before each replay.
+struct IoPtrs {
+  const void* in;
+  void* out;
+};
+
 // Static per-transform descriptor.
 struct TDesc {
   int n, N, logN, alpha;

@@ -199,9 +199,10 @@ __device__ double recombine3_one(const u32* G, const TDesc& d, const TState& s, 
 // WIDE = false: transforms whose spans fit the fast accumulator and those
 // with a status (NaN outputs); WIDE = true: the others.
 template <bool WIDE>
-__global__ void k_recombine3(const u32* G, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+__global__ void k_recombine3(const u32* G, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
                              const int* tlist, int K, int dir, int io32) {
   const int t = tlist[blockIdx.z];
+  void* out = io->out;
   const TDesc& d = td[t];
   const TState& s = ts[t];
   const bool w0 = s.span[0] > SPAN_FAST3, w1 = s.span[1] > SPAN_FAST3;
@@ -247,13 +248,13 @@ hipError_t launch_mac3(const u32* X, u32* G, const TDesc* td, const TState* ts, 
   return hipGetLastError();
 }
 
-hipError_t launch_recombine3(const u32* G, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+hipError_t launch_recombine3(const u32* G, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
                              const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const int b = grid_for((size_t)nmax);
-  hipLaunchKernelGGL(k_recombine3<false>, dim3(b, 1, count), dim3(256), 0, s, G, out, td, ts, kd, tlist, K, dir,
+  hipLaunchKernelGGL(k_recombine3<false>, dim3(b, 1, count), dim3(256), 0, s, G, io, td, ts, kd, tlist, K, dir,
                      io32);
-  hipLaunchKernelGGL(k_recombine3<true>, dim3(b, 1, count), dim3(256), 0, s, G, out, td, ts, kd, tlist, K, dir,
+  hipLaunchKernelGGL(k_recombine3<true>, dim3(b, 1, count), dim3(256), 0, s, G, io, td, ts, kd, tlist, K, dir,
                      io32);
   return hipGetLastError();
 }

@@ -119,7 +119,7 @@ bool fused_rows_ok(const NttGeom& g, int K);
 // exponent span needs the wide accumulator only get their column pass,
 // written to the compact buffer Z for launch_recombine_wide.
 bool fused_cols_ok(const NttGeom& g);
-hipError_t launch_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td, const TState* ts,
+hipError_t launch_inv_cols_rec(const u32* G, u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts,
                                const KernelDesc* kd, const int* tlist, int count, int K, const NttGeom& g,
                                const TwBlock& tb, int dir, int io32, hipStream_t s);
 
@@ -142,7 +142,7 @@ hipError_t launch_mac3_rows(const u32* X, u32* G, const TDesc* td, const TState*
 hipError_t launch_inv_cols_standalone(u32* data, int prime, int count, const NttGeom& g, const TwBlock& tb,
                                       hipStream_t s, const VecSel& sel);
 // Garner CRT (d = 3), exact recombination, postmultiply, output.
-hipError_t launch_recombine3(const u32* G, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+hipError_t launch_recombine3(const u32* G, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
                              const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s);
 
 // --- split / chirp / groups / recombination --------------------------------
@@ -150,7 +150,7 @@ hipError_t launch_chirp(double2* chirp, int n, int* flag, hipStream_t s);
 hipError_t launch_reset(TState* ts, const int* tlist, int count, hipStream_t s);
 // in / out of the transforms: complex128, or complex64 when io32 (binary32
 // target precision: inputs widened exactly, outputs rounded once).
-hipError_t launch_premul(const void* in, double2* xp, const TDesc* td, const KernelDesc* kd,
+hipError_t launch_premul(const IoPtrs* io, double2* xp, const TDesc* td, const KernelDesc* kd,
                          TState* ts, const int* tlist, int count, int nmax, int dir, bool kernel_mode,
                          int io32, hipStream_t s);
 hipError_t launch_split_plan(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist, int count, int K,
@@ -162,12 +162,16 @@ hipError_t launch_split_check(const TDesc* td, TState* ts, const int* tlist, int
                               hipStream_t s);
 hipError_t launch_groups(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist,
                          int count, int K, int L, hipStream_t s);
-hipError_t launch_recombine(const u32* Z, void* out, const TDesc* td, const TState* ts,
+hipError_t launch_recombine(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts,
                             const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
                             int dir, int io32, hipStream_t s);
 // Only the transforms whose exponent span needs the wide accumulator.
-hipError_t launch_recombine_wide(const u32* Z, void* out, const TDesc* td, const TState* ts,
+hipError_t launch_recombine_wide(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts,
                                  const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
                                  int dir, int io32, hipStream_t s);
+// Writes the execution's array pointers to the plan's descriptor (one
+// thread); set_io_kernel is that kernel, to find its node in a graph.
+hipError_t launch_set_io(IoPtrs* io, const void* in, void* out, hipStream_t s);
+const void* set_io_kernel();
 
 }  // namespace fo

@@ -1636,7 +1636,7 @@ constexpr int REC_THREADS = 1024, REC_OUT = 4;   // 4096-position tiles
 // columns read together at one tile position fall on different LDS banks.
 __host__ __device__ constexpr int rec_ldc(int m1) { return pad9(1 << m1) + ((8 - pad9(1 << m1)) & 63); }
 template <int M1>
-__global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td,
+__global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32* Z, const IoPtrs* io, const TDesc* td,
                                                               const TState* ts, const KernelDesc* kd,
                                                               const int* tlist, int K, int m2, TwBlock tb, int dir,
                                                               int io32) {
@@ -1646,6 +1646,7 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
   const int t = tlist[blockIdx.z];
   const TDesc& d = td[t];
   const TState& s = ts[t];
+  void* out = io->out;
   // a transform whose exponent span needs the wide accumulator only gets
   // its column pass here: the residues go to the compact buffer Z for the
   // wide recombination
@@ -2130,7 +2131,7 @@ bool fused_cols_ok(const NttGeom& g) {
   return g.two_pass() && g.m1 >= 7 && g.m1 <= 9 && 12 - g.m1 <= g.m2;
 }
 
-hipError_t launch_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td, const TState* ts,
+hipError_t launch_inv_cols_rec(const u32* G, u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts,
                                const KernelDesc* kd, const int* tlist, int count, int K, const NttGeom& g,
                                const TwBlock& tb, int dir, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
@@ -2141,7 +2142,7 @@ hipError_t launch_inv_cols_rec(const u32* G, u32* Z, void* out, const TDesc* td,
     constexpr int LC = 12 - M1;
     const size_t smem = ((size_t)(2 << M1) + 4 * ((size_t)rec_ldc(M1) << LC)) * 4;
     if ((e = big_lds((const void*)k_inv_cols_rec<M1>)) != hipSuccess) return;
-    hipLaunchKernelGGL(k_inv_cols_rec<M1>, dim3(1u << (g.m2 - LC), 1, count), dim3(REC_THREADS), smem, s, G, Z, out,
+    hipLaunchKernelGGL(k_inv_cols_rec<M1>, dim3(1u << (g.m2 - LC), 1, count), dim3(REC_THREADS), smem, s, G, Z, io,
                        td, ts, kd, tlist, K, g.m2, tb, dir, io32);
   });
   return e != hipSuccess ? e : hipGetLastError();

@@ -136,11 +136,16 @@ struct LengthClass {
   i64 x3_base = 0, x3_ps = 0, g3_base = 0, g3_ps = 0;
 };
 
+// A captured batched schedule for one direction.  Its first node writes the
+// execution's array pointers to the plan's descriptor; a new (in, out) pair
+// only updates that node's arguments in the instantiated graph.
 struct GraphEntry {
-  const void* in;
-  void* out;
   int dir;
+  hipGraph_t graph;          // kept alive: io_node belongs to it
   hipGraphExec_t exec;
+  hipGraphNode_t io_node;
+  const void* in;            // the pointers io_node currently writes
+  void* out;
 };
 
 }  // namespace fo
@@ -169,6 +174,7 @@ struct fft_ozaki_plan_s {
   fo::u32* X = nullptr;
   fo::u32* G = nullptr;
   fo::u32* Z = nullptr;
+  fo::IoPtrs* d_io = nullptr;       // the current execution's in / out (read by the kernels)
   std::vector<void*> allocs;
   fo::i64 bytes = 0;
   hipStream_t cap = nullptr;
@@ -221,7 +227,10 @@ static void destroy_plan(fft_ozaki_plan_s* p) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
-  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  for (auto& g : p->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
   if (p->cap) (void)hipStreamDestroy(p->cap);
   for (void* a : p->allocs) (void)hipFree(a);
   (void)hipSetDevice(cur);
@@ -575,6 +584,7 @@ static int build_plan(fft_ozaki_plan_s* p) {
   if ((rc = dmalloc(p, (void**)&p->d_ts, sizeof(TState) * count))) return rc;
   if ((rc = dmalloc(p, (void**)&p->d_tall, sizeof(int) * count))) return rc;
   if ((rc = dmalloc(p, (void**)&p->d_kd, sizeof(KernelDesc) * p->kernels.size()))) return rc;
+  if ((rc = dmalloc(p, (void**)&p->d_io, sizeof(IoPtrs)))) return rc;
   HIPCHK(hipMemcpy(p->d_td, p->td.data(), sizeof(TDesc) * count, hipMemcpyHostToDevice));
   HIPCHK(hipMemset(p->d_ts, 0, sizeof(TState) * count));
   std::vector<int> all(count);
@@ -619,11 +629,11 @@ static int build_plan(fft_ozaki_plan_s* p) {
 static inline int io32_of(const fft_ozaki_plan_s* p) { return p->precision == FFT_OZAKI_PREC_FP32 ? 1 : 0; }
 
 // The batched launch sequence (also what gets captured into the graph).
-static int enqueue_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
+static int enqueue_batched(fft_ozaki_plan_s* p, int dir, hipStream_t s) {
   const int K = p->K, count = (int)p->td.size();
   HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
   for (auto& lc : p->classes)
-    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
+    HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
                          io32_of(p), s));
   HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
   for (int r = 0; r < K; ++r) {
@@ -647,13 +657,13 @@ static int enqueue_batched(fft_ozaki_plan_s* p, const void* in, void* out, int d
       // columns to the compact buffer, then the wide recombination)
       HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
                               p->tb, step_for(p, lc.logN), 1, s, fused_rows_ok(lc.geom, K)));
-      HIPCHK(launch_inv_cols_rec(p->G, p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir,
+      HIPCHK(launch_inv_cols_rec(p->G, p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir,
                                  io32_of(p), s));
-      HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s));
+      HIPCHK(launch_recombine_wide(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s));
     } else {
       HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
                               p->tb, step_for(p, lc.logN), 0, s, fused_rows_ok(lc.geom, K)));
-      HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s));
+      HIPCHK(launch_recombine(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s));
     }
   }
   return FFT_OZAKI_OK;
@@ -676,11 +686,11 @@ static int ntt_chunked(u32* data, int logN, int prime, i64 count, bool inverse, 
 // forward NTTs of the live slice vectors, the NTT-domain multiply-accumulate,
 // the inverse NTTs of the live group vectors, and Garner (d = 3) with the
 // exact recombination and postmultiply.
-static int enqueue_batched3(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
+static int enqueue_batched3(fft_ozaki_plan_s* p, int dir, hipStream_t s) {
   const int K = p->K, count = (int)p->td.size();
   HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
   for (auto& lc : p->classes)
-    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
+    HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
                          io32_of(p), s));
   HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
   for (int r = 0; r < K; ++r) {
@@ -723,20 +733,49 @@ static int enqueue_batched3(fft_ozaki_plan_s* p, const void* in, void* out, int 
                               s, gs)))
           return rc;
     }
-    HIPCHK(launch_recombine3(p->G, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, lc.nmax, K, dir, io32_of(p),
+    HIPCHK(launch_recombine3(p->G, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, lc.nmax, K, dir, io32_of(p),
                              s));
   }
   return FFT_OZAKI_OK;
 }
 
+// Arguments of the descriptor-writing node for (in, out).
+static hipError_t set_io_node(fft_ozaki_plan_s* p, GraphEntry& g, const void* in, void* out) {
+  IoPtrs* io = p->d_io;
+  void* args[3] = {&io, &in, &out};
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(set_io_kernel());
+  kp.gridDim = dim3(1);
+  kp.blockDim = dim3(1);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  const hipError_t e = hipGraphExecKernelNodeSetParams(g.exec, g.io_node, &kp);
+  if (e == hipSuccess) {
+    g.in = in;
+    g.out = out;
+  }
+  return e;
+}
+
 static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
   for (auto& lc : p->classes)
     if (p->primes == 2 && fused_rows_ok(lc.geom, p->K)) p->x_rows_pending = true;
-  for (auto& g : p->graphs) {
-    if (g.in == in && g.out == out && g.dir == dir) {
-      HIPCHK(hipGraphLaunch(g.exec, s));
-      return FFT_OZAKI_OK;
+  for (size_t i = 0; i < p->graphs.size(); ++i) {
+    GraphEntry& g = p->graphs[i];
+    if (g.dir != dir) continue;
+    if ((g.in != in || g.out != out) && set_io_node(p, g, in, out) != hipSuccess) {
+      // the node could not be updated: capture this direction again below
+      (void)hipGetLastError();
+      FO_LOG("graph argument update failed; capturing again");
+      (void)hipStreamSynchronize(s);
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+      p->graphs.erase(p->graphs.begin() + (long)i);
+      break;
     }
+    HIPCHK(hipGraphLaunch(g.exec, s));
+    return FFT_OZAKI_OK;
   }
   // capture on the plan's private stream, after the caller's prior work
   hipEvent_t ev;
@@ -747,27 +786,41 @@ static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, 
   (void)hipEventDestroy(ev);
   hipGraph_t graph;
   HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-  int rc = p->primes == 3 ? enqueue_batched3(p, in, out, dir, p->cap) : enqueue_batched(p, in, out, dir, p->cap);
+  hipError_t le = launch_set_io(p->d_io, in, out, p->cap);
+  int rc = le != hipSuccess ? fail(FFT_OZAKI_ERR_HIP, std::string("launch_set_io: ") + hipGetErrorString(le))
+                            : (p->primes == 3 ? enqueue_batched3(p, dir, p->cap) : enqueue_batched(p, dir, p->cap));
   hipError_t ce = hipStreamEndCapture(p->cap, &graph);
-  if (rc) return rc;
-  if (ce != hipSuccess) return fail(FFT_OZAKI_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
-  hipGraphExec_t exec;
-  HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  (void)hipGraphDestroy(graph);
-  FO_LOG("captured the batched schedule for in=%p out=%p direction=%d (%zu graphs cached before)", in, (void*)out,
-         dir, p->graphs.size());
-  if (p->graphs.size() >= 4) {
-    (void)hipStreamSynchronize(s);
-    (void)hipGraphExecDestroy(p->graphs.front().exec);
-    p->graphs.erase(p->graphs.begin());
+  if (rc) {
+    if (ce == hipSuccess) (void)hipGraphDestroy(graph);
+    return rc;
   }
-  p->graphs.push_back({in, out, dir, exec});
-  HIPCHK(hipGraphLaunch(exec, s));
+  if (ce != hipSuccess) return fail(FFT_OZAKI_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+  // the descriptor-writing node: the graph's only launch of that kernel
+  GraphEntry g{dir, graph, nullptr, nullptr, in, out};
+  size_t nn = 0;
+  HIPCHK(hipGraphGetNodes(graph, nullptr, &nn));
+  std::vector<hipGraphNode_t> nodes(nn);
+  HIPCHK(hipGraphGetNodes(graph, nodes.data(), &nn));
+  for (hipGraphNode_t nd : nodes) {
+    hipGraphNodeType ty;
+    if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams kp{};
+    if (hipGraphKernelNodeGetParams(nd, &kp) == hipSuccess && kp.func == set_io_kernel()) g.io_node = nd;
+  }
+  if (!g.io_node) {
+    (void)hipGraphDestroy(graph);
+    return fail(FFT_OZAKI_ERR_HIP, "captured graph has no descriptor node");
+  }
+  HIPCHK(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+  FO_LOG("captured the batched schedule for direction %d (%zu kernel and other nodes)", dir, nn);
+  p->graphs.push_back(g);
+  HIPCHK(hipGraphLaunch(g.exec, s));
   return FFT_OZAKI_OK;
 }
 
 static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
   const int K = p->K, SL = 2 * K * K;   // slots per output component
+  HIPCHK(launch_set_io(p->d_io, in, out, s));
   for (int t = 0; t < (int)p->td.size(); ++t) {
     const TDesc& d = p->td[t];
     const int* tl = p->d_tall + t;
@@ -780,7 +833,7 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
     Range rt("transform");
     std::unique_ptr<Range> stage(new Range("premultiply + split"));
     HIPCHK(launch_reset(p->d_ts, tl, 1, s));
-    HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, io32_of(p), s));
+    HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, io32_of(p), s));
     HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, tl, 1, K, s));
     for (int r = 0; r < K; ++r) {
       HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, tl, 1, d.n, K, false, s));
@@ -812,7 +865,7 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
         }
     }
     stage.reset(new Range("CRT + recombination + postmultiply"));
-    HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, tl, 1, d.n, K, dir, io32_of(p), s));
+    HIPCHK(launch_recombine(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, tl, 1, d.n, K, dir, io32_of(p), s));
   }
   HIPCHK(hipStreamSynchronize(s));
   return FFT_OZAKI_OK;
@@ -826,14 +879,13 @@ static const char* const kStageNames[9] = {"", "stage 1: premultiply + split", "
 static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
   const int K = p->K, count = (int)p->td.size();
   Range range(stage >= 1 && stage <= 8 ? kStageNames[stage] : "stage");
-  const void* in = p->last_in;
-  void* out = p->last_out;
+  // the plan's descriptor still holds the last execution's in / out
   const int dir = p->last_dir;
   switch (stage) {
     case 1:   // split: premultiply, maxima and the K extraction/check passes
       HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
       for (auto& lc : p->classes)
-        HIPCHK(launch_premul(in, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
+        HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
                          io32_of(p), s));
       HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
       for (int r = 0; r < K; ++r) {
@@ -867,7 +919,7 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
       for (auto& lc : p->classes) {
         const int cnt = (int)lc.tids.size();
         if (fused_cols_ok(lc.geom))
-          HIPCHK(launch_inv_cols_rec(p->G, p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb,
+          HIPCHK(launch_inv_cols_rec(p->G, p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb,
                                      dir, io32_of(p), s));
         else
           HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K,
@@ -878,10 +930,10 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
       for (auto& lc : p->classes) {
         const int cnt = (int)lc.tids.size();
         if (fused_cols_ok(lc.geom)) {
-          HIPCHK(launch_recombine_wide(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir,
+          HIPCHK(launch_recombine_wide(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir,
                                        io32_of(p), s));
         } else {
-          HIPCHK(launch_recombine(p->Z, out, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p),
+          HIPCHK(launch_recombine(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p),
                                   s));
         }
       }
@@ -1303,7 +1355,8 @@ int fft_ozaki_execute_static(int64_t n, int64_t batch, const void* in, void* out
     }
     sl.plan = p;
   }
-  return enqueue_batched(p, in, out, direction, s);
+  HIPCHK(launch_set_io(p->d_io, in, out, s));
+  return enqueue_batched(p, direction, s);
 }
 
 }  // extern "C"

@@ -62,9 +62,10 @@ __device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, 
 // those with a status, which get NaN), two outputs per thread;
 // WIDE = true: the others, one output per thread.
 template <bool WIDE>
-__global__ void k_recombine(const u32* Z, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+__global__ void k_recombine(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int K, int dir, int io32) {
   const int t = tlist[blockIdx.z];
+  void* out = io->out;
   const TDesc& d = td[t];
   const TState& s = ts[t];
   const bool wide0 = span_wide(s, 0), wide1 = span_wide(s, 1);
@@ -96,28 +97,40 @@ __global__ void k_recombine(const u32* Z, void* out, const TDesc* td, const TSta
   }
 }
 
-hipError_t launch_recombine(const u32* Z, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+hipError_t launch_recombine(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   int b = (nmax + 255) / 256;
   if (b > 2048) b = 2048;
   if (b < 1) b = 1;
   const int b2 = (b + 1) / 2;      // two outputs per thread
-  hipLaunchKernelGGL(k_recombine<false>, dim3(b2, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir, io32);
-  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir, io32);
+  hipLaunchKernelGGL(k_recombine<false>, dim3(b2, 1, count), dim3(256), 0, s, Z, io, td, ts, kd, tlist, K, dir, io32);
+  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, io, td, ts, kd, tlist, K, dir, io32);
   return hipGetLastError();
 }
 
 }  // namespace fo
 
 namespace fo {
-hipError_t launch_recombine_wide(const u32* Z, void* out, const TDesc* td, const TState* ts, const KernelDesc* kd,
+hipError_t launch_recombine_wide(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
                                  const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   int b = (nmax + 255) / 256;
   if (b > 2048) b = 2048;
   if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, out, td, ts, kd, tlist, K, dir, io32);
+  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, io, td, ts, kd, tlist, K, dir, io32);
   return hipGetLastError();
 }
+
+// One thread writes the execution's array pointers (a kernel, so that the
+// write is an ordinary stream operation, also inside captured graphs).
+__global__ void k_set_io(IoPtrs* io, const void* in, void* out) {
+  io->in = in;
+  io->out = out;
+}
+hipError_t launch_set_io(IoPtrs* io, const void* in, void* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_io, dim3(1), dim3(1), 0, s, io, in, out);
+  return hipGetLastError();
+}
+const void* set_io_kernel() { return reinterpret_cast<const void*>(&k_set_io); }
 }  // namespace fo

@@ -194,9 +194,10 @@ __device__ __forceinline__ u64 block_max_u64(u64 v) {
   return m;
 }
 
-__global__ void k_premul(const void* in, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
+__global__ void k_premul(const IoPtrs* io, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
                          const int* tlist, int dir, bool kernel_mode, int io32) {
   const int t = tlist[blockIdx.z];
+  const void* in = kernel_mode ? nullptr : io->in;
   const TDesc& d = td[t];
   const double2* ch = kd[d.kd].chirp;
   u64 m0 = 0, m1 = 0;
@@ -240,10 +241,10 @@ static int chunks_for(int nmax) {
   return b;
 }
 
-hipError_t launch_premul(const void* in, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
+hipError_t launch_premul(const IoPtrs* io, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
                          const int* tlist, int count, int nmax, int dir, bool kernel_mode, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_premul, dim3(chunks_for(nmax), 1, count), dim3(256), 0, s, in, xp, td, kd, ts, tlist, dir,
+  hipLaunchKernelGGL(k_premul, dim3(chunks_for(nmax), 1, count), dim3(256), 0, s, io, xp, td, kd, ts, tlist, dir,
                      kernel_mode, io32);
   return hipGetLastError();
 }

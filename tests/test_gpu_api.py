@@ -151,10 +151,35 @@ def test_log_lines(tmp_path):
     import sys
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     code = ("import torch, paper_2603_29129_amd as oz\n"
-            "x = torch.zeros(2, 1 << 14, dtype=torch.complex128, device='cuda')\n"
-            "oz.Plan(1 << 14, 2).forward(x); torch.cuda.synchronize(); print('done', flush=True)\n")
+            "p = oz.Plan(1 << 14, 2)\n"
+            "for i in range(8):\n"
+            "    x = torch.full((2, 1 << 14), float(i), dtype=torch.complex128, device='cuda')\n"
+            "    p.forward(x); p.inverse(x)\n"
+            "torch.cuda.synchronize(); print('done', flush=True)\n")
     env = dict(os.environ, FFT_OZAKI_LOG="1", PYTHONPATH=root)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=100, cwd=root)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "[fft_ozaki] plan: 2 transforms" in r.stderr
-    assert "class N=2^14" in r.stderr and "captured the batched schedule" in r.stderr
+    assert "class N=2^14" in r.stderr
+    # eight (in, out) pairs per direction, one capture per direction
+    assert r.stderr.count("captured the batched schedule for direction 0") == 1
+    assert r.stderr.count("captured the batched schedule for direction 1") == 1
+
+
+def test_rotating_buffers_reuse_the_graph(torch_mod):
+    """Executions over eight (in, out) pairs in turn, both directions, through
+    one batched plan (one captured graph per direction, its pointers
+    rebound per call) give the plain form's bits every time."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n, B = 1 << 14, 2
+    plan = oz.Plan(n, B)
+    ref = oz.Plan(n, B, mode="plain")
+    xs = [torch.from_numpy(wl.uniform(n, batch=B, seed=40 + i)).cuda() for i in range(8)]
+    outs = [torch.empty_like(xs[0]) for _ in range(8)]
+    for rnd in range(2):
+        for i in range(8):
+            d = (i + rnd) % 2
+            plan.execute(xs[i], d, out=outs[i])
+            want = ref.execute(xs[i], d)
+            assert torch.equal(outs[i].view(torch.float64), want.view(torch.float64)), (rnd, i)
