@@ -17,7 +17,7 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libfft_ozaki.so")
-SOURCES = ["ntt_kernels.hip", "split_kernels.hip", "recombine_kernels.hip", "crt3_kernels.hip", "plan.hip"]
+SOURCES = ["ntt_kernels.hip", "split_kernels.hip", "recombine_kernels.hip", "plan.hip"]
 
 FLAGS = [
     "-O3",

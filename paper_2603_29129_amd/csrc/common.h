@@ -104,7 +104,7 @@ struct TwStep {
 struct KernelDesc {
   int n, N, logN, alpha;
   const double2* chirp;    // (cos(pi q/n), sin(pi q/n)), q = j^2 mod 2n
-  const u32* W;            // [part][t][prime][N] NTT-domain values * N^{-1}
+  const u32* W;            // [part][t][prime][N] NTT-domain values * N^{-1} (prime < the plan's moduli)
   const u32* Wq;           // Shoup companions of W
   int kw[2];               // slice counts of Re w*, Im w*
   int Ew[2][KMAX];         // slice exponents
@@ -187,10 +187,6 @@ struct TDesc {
   i64 X_off;               // u32 offset of the slice/NTT buffer [part][k][prime][N]
   i64 G_off;               // u32 offset of the group buffer [slot][prime][N]
   i64 Z_off;               // u32 offset of the compact outputs [slot][prime][zs]
-  // three-modulus plans: X_off / G_off locate this transform's prime-0 block
-  // ([part][k][N] / [slot][N]); the blocks of primes 1, 2 follow at strides
-  // xps / gps (u32 words)
-  i64 xps, gps;
 };
 
 }  // namespace fo

@@ -1,5 +1,6 @@
-// Device helpers of the CRT and the exact recombination (Sec. 3.3, 4.4),
-// shared by the recombination kernels and the fused inverse column pass.
+// Device helpers of the CRT (two or three moduli) and the exact recombination
+// (Sec. 3.3, 4.4), shared by the recombination kernels and the fused inverse
+// column pass.
 #pragma once
 #include "internal.h"
 
@@ -135,7 +136,94 @@ __device__ __forceinline__ void put_out(void* out, i64 idx, double2 v, int io32)
   else reinterpret_cast<double2*>(out)[idx] = v;
 }
 
-// A transform's exponent span needs the wide accumulator (output component tg).
-__device__ __forceinline__ bool span_wide(const TState& s, int tg) { return s.span[tg] > 64 * W_FAST - 71; }
+// ---------------------------------------------------------------------------
+// Three moduli (Sec. 3.3's CRT with d = 3): Garner's mixed-radix form
+// z = z0 + p0 h1 + p0 p1 h2 over p0, p1, p2 (p0 p1 p2 < 2^93).
+constexpr u64 powmod_c(u64 b, u64 e, u64 p) {
+  u64 r = 1;
+  b %= p;
+  while (e) {
+    if (e & 1) r = r * b % p;
+    b = b * b % p;
+    e >>= 1;
+  }
+  return r;
+}
+constexpr u32 P0_MOD_P2 = P0 - P2;                                        // p0 < 2 p2
+constexpr u32 P0_MOD_P2_Q = (u32)(((u64)P0_MOD_P2 << 32) / P2);
+constexpr u32 PP_INV_MOD_P2 = (u32)powmod_c(PP % P2, P2 - 2, P2);        // (p0 p1)^{-1} mod p2
+constexpr u32 PP_INV_MOD_P2_Q = (u32)(((u64)PP_INV_MOD_P2 << 32) / P2);
+static_assert((PP % P2) * PP_INV_MOD_P2 % P2 == 1, "(p0 p1)^{-1} mod p2");
+// M = p0 p1 p2 as two 64-bit words, from p0 p1 = hi32 2^32 + lo32.
+constexpr u64 M_A = (PP & 0xFFFFFFFFull) * P2;                            // < 2^63
+constexpr u64 M_B = (PP >> 32) * P2;                                      // < 2^61
+constexpr u64 M_LO = M_A + (M_B << 32);
+constexpr u64 M_HI = (M_B >> 32) + (M_LO < M_A ? 1 : 0);
+// (M - 1) / 2 = M >> 1 (M odd)
+constexpr u64 MH_LO = (M_LO >> 1) | (M_HI << 63);
+constexpr u64 MH_HI = M_HI >> 1;
+
+// z in [0, M) from its residues: h1 = (z1 - z0) p0^{-1} mod p1,
+// h2 = (z2 - (z0 + p0 h1)) (p0 p1)^{-1} mod p2; then the symmetric remainder
+// in [-(M-1)/2, (M-1)/2] as the two's complement 128-bit value hi 2^64 + lo.
+__device__ __forceinline__ void garner3(u32 z0, u32 z1, u32 z2, u64& lo, i64& hi) {
+  const u32 z0m1 = umin32(z0, z0 - P1);                       // z0 mod p1 (z0 < p0 < 2 p1)
+  const u32 h1 = shoup_mul(sub_mod(z1, z0m1, P1), P0_INV_MOD_P1, P0INV_Q, P1);
+  const u64 t = (u64)z0 + (u64)h1 * P0;                        // z mod p0 p1, in [0, p0 p1)
+  const u32 z0m2 = umin32(z0, z0 - P2);                       // z0 mod p2 (z0 < p0 < 2 p2)
+  const u32 tm2 = add_mod(z0m2, shoup_mul(h1, P0_MOD_P2, P0_MOD_P2_Q, P2), P2);   // t mod p2
+  const u32 h2 = shoup_mul(sub_mod(z2, tm2, P2), PP_INV_MOD_P2, PP_INV_MOD_P2_Q, P2);
+  u64 l = PP * (u64)h2;
+  u64 h = __umul64hi(PP, (u64)h2);
+  l += t;
+  h += l < t ? 1ull : 0ull;
+  if (h > MH_HI || (h == MH_HI && l > MH_LO)) {
+    const u64 borrow = l < M_LO ? 1ull : 0ull;
+    l -= M_LO;
+    h = h - M_HI - borrow;
+  }
+  lo = l;
+  hi = (i64)h;
+}
+
+// The signed group value of residues z[0 .. NP-1] added, times 2^sh, to the
+// fast limbs: one piece for NP = 2 (|z| < 2^62); for NP = 3 (|z| < 2^92)
+// z mod 2^62 (non-negative) at sh and z >> 62 (|.| < 2^31) at sh + 62.
+template <int NP>
+__device__ __forceinline__ void limb_add_crt(u32 (&acc)[NL_FAST], const u32 (&z)[NP], int sh) {
+  if constexpr (NP == 2) {
+    limb_add(acc, garner(z[0], z[1]), sh);
+  } else {
+    u64 lo;
+    i64 hi;
+    garner3(z[0], z[1], z[2], lo, hi);
+    limb_add(acc, (i64)(lo & 0x3FFFFFFFFFFFFFFFull), sh);
+    limb_add(acc, (hi << 2) | (i64)(lo >> 62), sh + 62);
+  }
+}
+// The same into a W-word accumulator (the NP = 3 value as three pieces of at
+// most 64 bits).
+template <int NP, int W>
+__device__ __forceinline__ void acc_add_crt(u64 (&acc)[W], const u32 (&z)[NP], int sh) {
+  if constexpr (NP == 2) {
+    acc_add<W>(acc, garner(z[0], z[1]), sh);
+  } else {
+    u64 lo;
+    i64 hi;
+    garner3(z[0], z[1], z[2], lo, hi);
+    acc_add<W>(acc, (i64)(lo & 0xFFFFFFFFull), sh);
+    acc_add<W>(acc, (i64)(lo >> 32), sh + 32);
+    acc_add<W>(acc, hi, sh + 64);
+  }
+}
+
+// A transform's exponent span needs the wide accumulator (output component
+// tg): the fast limbs hold every sum while the span plus the group value's
+// bits (63 for two moduli, 93 for three) and 7 bits of carries stays below
+// their 64 W_FAST bits.
+template <int NP>
+__device__ __forceinline__ bool span_wide(const TState& s, int tg) {
+  return s.span[tg] > 64 * W_FAST - (NP == 2 ? 71 : 104);
+}
 
 }  // namespace fo

@@ -48,49 +48,29 @@ int build_block_twiddles(TwBlock* out, void** allocs, DevArena* arena = nullptr)
 int build_step_twiddles(int logN, TwStep* out, void** allocs, DevArena* arena = nullptr);
 
 // --- NTT launches -----------------------------------------------------------
-// Which vectors of a standalone launch hold data; the others are skipped.
-// Vector v = v0 + (index in the launch) belongs to transform tlist[v / per]
-// at local index r = v % per.  kind 0: every vector; kind 1 (slice
-// residues, r = part K + k): live while k < kx[part]; kind 2 (group sums,
-// r = component 2K^2 + g): live while g < ngroups[component].  A transform
-// with a status has no live vector.
-struct VecSel {
-  const TState* ts = nullptr;
-  const int* tlist = nullptr;
-  int per = 1, K = 1, kind = 0, v0 = 0;
-};
-__device__ __forceinline__ bool vec_live(const VecSel& sel, int idx) {
-  if (sel.kind == 0) return true;
-  const int v = sel.v0 + idx, r = v % sel.per;
-  const TState& s = sel.ts[sel.tlist[v / sel.per]];
-  if (s.status) return false;
-  if (sel.kind == 1) return r % sel.K < s.kx[r / sel.K];
-  const int SL = 2 * sel.K * sel.K;
-  return r % SL < s.ngroups[r / SL];
-}
-
 // Standalone transforms of `count` contiguous vectors (natural order in for the
 // forward transform, NTT-domain order out; the inverse takes NTT-domain order
-// and returns natural order multiplied by N^{-1}); `sel` skips vectors.
+// and returns natural order multiplied by N^{-1}).
 // which (two-pass lengths): 0 both passes, 1 the column pass only, 2 the
 // row pass only (the autotuner times the passes separately).
 hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool inverse,
                                  const NttGeom& g, const TwBlock& tb, const TwStep& ts, hipStream_t s,
-                                 const VecSel& sel = VecSel{}, int which = 0);
+                                 int which = 0);
 
-// Pipeline: forward NTTs of the slice residues of the listed transforms
-// (vector index vi = (part*K + k)*2 + prime; only k < kx[part] are done).
-// valid_full: the vectors are fully populated (kernel slices) instead of
-// holding zeros beyond n.  vi_lo/vi_hi restrict the vectors (plain form).
+// Pipeline, np = 2 or 3 moduli: forward NTTs of the slice residues of the
+// listed transforms (vector index vi = (part*K + k)*np + prime; only
+// k < kx[part] are done).  valid_full: the vectors are fully populated
+// (kernel slices) instead of holding zeros beyond n.  vi_lo/vi_hi restrict
+// the vectors (plain form).
 hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count,
-                               int K, bool valid_full, int vi_lo, int vi_hi, const NttGeom& g,
+                               int K, int np, bool valid_full, int vi_lo, int vi_hi, const NttGeom& g,
                                const TwBlock& tb, const TwStep& st, hipStream_t s);
 
 // Pipeline: NTT-domain multiply-accumulate of every Alg. 8 group followed by
 // the inverse NTT; writes the first n outputs of each group and prime to the
 // compact buffer.  slot_lo/slot_hi restrict the groups (plain form).
 hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts,
-                               const KernelDesc* kd, const int* tlist, int count, int K,
+                               const KernelDesc* kd, const int* tlist, int count, int K, int np,
                                int slot_lo, int slot_hi, const NttGeom& g, const TwBlock& tb,
                                const TwStep& st, hipStream_t s);
 
@@ -100,14 +80,14 @@ hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, co
 // or 1) the forward launch also computes every listed transform's
 // accumulation schedule (as launch_groups) in one extra workgroup per
 // transform.
-hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K,
+hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, int np,
                             bool valid_full, int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb,
                             const TwStep& st, int which, hipStream_t s, TState* walk_ts = nullptr,
                             const KernelDesc* kd = nullptr, int L = 0);
 // fused_fwd: the row pass also does the forward row NTTs of the slices (X
 // holds the forward column pass's output); needs fused_rows_ok.
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                            const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
+                            const int* tlist, int count, int K, int np, int slot_lo, int slot_hi, const NttGeom& g,
                             const TwBlock& tb, const TwStep& st, int which, hipStream_t s, bool fused_fwd = false);
 // The register form of the inverse row pass applies (K <= 3, 512-position
 // row tiles) and its group tile holds the 2K forward slice rows, so the
@@ -120,30 +100,11 @@ bool fused_rows_ok(const NttGeom& g, int K);
 // written to the compact buffer Z for launch_recombine_wide.
 bool fused_cols_ok(const NttGeom& g);
 hipError_t launch_inv_cols_rec(const u32* G, u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts,
-                               const KernelDesc* kd, const int* tlist, int count, int K, const NttGeom& g,
+                               const KernelDesc* kd, const int* tlist, int count, int K, int np, const NttGeom& g,
                                const TwBlock& tb, int dir, int io32, hipStream_t s);
 
 // Kernel slices: multiply by N^{-1} and build Shoup companions.
-hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s);
-
-// --- three moduli (d = 3 CRT) -------------------------------------------------
-// Kernel-spectra companions (Shoup) for W laid out [prime][part][k][N].
-hipError_t launch_companions3(const u32* W, u32* Wq, int K, int logN, hipStream_t s);
-// NTT-domain multiply-accumulate of every group of the listed transforms,
-// all three primes: G[prime * gps + slot N + e] (slot = component 2K^2 + g).
-hipError_t launch_mac3(const u32* X, u32* G, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                       const int* tlist, int count, int K, int logN, hipStream_t s);
-// Two-pass lengths: the multiply-accumulate fused into the inverse row pass
-// (rows of every live group to G, laid out as for launch_mac3), and the
-// inverse column pass alone (standalone kernels, `sel` skips vectors).
-hipError_t launch_mac3_rows(const u32* X, u32* G, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                            const int* tlist, int count, int K, const NttGeom& g, const TwBlock& tb, const TwStep& st,
-                            hipStream_t s);
-hipError_t launch_inv_cols_standalone(u32* data, int prime, int count, const NttGeom& g, const TwBlock& tb,
-                                      hipStream_t s, const VecSel& sel);
-// Garner CRT (d = 3), exact recombination, postmultiply, output.
-hipError_t launch_recombine3(const u32* G, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                             const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s);
+hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int np, int logN, hipStream_t s);
 
 // --- split / chirp / groups / recombination --------------------------------
 hipError_t launch_chirp(double2* chirp, int n, int* flag, hipStream_t s);
@@ -157,18 +118,19 @@ hipError_t launch_split_plan(const TDesc* td, TState* ts, const KernelDesc* kd, 
                              hipStream_t s);
 hipError_t launch_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts,
                                 const int* tlist, int count, int nmax, int K, bool kernel_mode,
-                                hipStream_t s, int np = 2);
+                                hipStream_t s, int np);
 hipError_t launch_split_check(const TDesc* td, TState* ts, const int* tlist, int count, int K,
                               hipStream_t s);
 hipError_t launch_groups(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist,
                          int count, int K, int L, hipStream_t s);
+// Garner CRT over np = 2 or 3 moduli, exact recombination, postmultiply.
 hipError_t launch_recombine(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts,
                             const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
-                            int dir, int io32, hipStream_t s);
+                            int dir, int io32, hipStream_t s, int np);
 // Only the transforms whose exponent span needs the wide accumulator.
 hipError_t launch_recombine_wide(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts,
                                  const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
-                                 int dir, int io32, hipStream_t s);
+                                 int dir, int io32, hipStream_t s, int np);
 // Writes the execution's array pointers to the plan's descriptor (one
 // thread); set_io_kernel is that kernel, to find its node in a graph.
 hipError_t launch_set_io(IoPtrs* io, const void* in, void* out, hipStream_t s);

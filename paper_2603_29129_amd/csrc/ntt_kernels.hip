@@ -1,5 +1,8 @@
-// Number-theoretic transforms modulo p0 = 2130706433 and p1 = 2113929217 on
-// gfx950 (Sec. 3.3: y(k) = sum_j x(j) w_N^{jk} mod p, inverse with N^{-1}).
+// Number-theoretic transforms modulo p0 = 2130706433 and p1 = 2113929217 (and
+// p2 = 2013265921 for plans with three moduli) on gfx950 (Sec. 3.3:
+// y(k) = sum_j x(j) w_N^{jk} mod p, inverse with N^{-1}).  NP is the number
+// of moduli of a plan; the slice spectra are laid out
+// [part][k][prime][N] and the group values [slot][prime][N], prime < NP.
 //
 // Design:
 //  * A block NTT of length M <= 4096 runs inside one workgroup on an LDS tile.
@@ -488,10 +491,8 @@ __device__ __forceinline__ void fwd_single_body(u32* vec, int valid, int prime, 
 // Standalone kernels (count contiguous vectors; blockIdx.z = vector).
 
 template <int M>
-__global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int prime, bool inverse, TwBlock tb,
-                                                             VecSel sel) {
+__global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int prime, bool inverse, TwBlock tb) {
   extern __shared__ u32 smem[];
-  if (!vec_live(sel, blockIdx.z)) return;
   constexpr int logN = M, N = 1 << logN;
   u32* vec = data + ((size_t)blockIdx.z << logN);
   if (!inverse) {
@@ -512,29 +513,23 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_single(u32* data, int prime
 }
 
 template <int M1>
-__global__ void __launch_bounds__(COL_THREADS) k_std_fwd_cols(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts,
-                                                               VecSel sel) {
+__global__ void __launch_bounds__(COL_THREADS) k_std_fwd_cols(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
   extern __shared__ u32 smem[];
-  if (!vec_live(sel, blockIdx.z)) return;
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   fwd_cols_body<M1>(vec, 1 << g.logN, prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[prime], smem);
 }
 
 template <int M2>
-__global__ void __launch_bounds__(NTT_THREADS) k_std_fwd_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts,
-                                                               VecSel sel) {
+__global__ void __launch_bounds__(NTT_THREADS) k_std_fwd_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
   extern __shared__ u32 smem[];
-  if (!vec_live(sel, blockIdx.z)) return;
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   fwd_rows_body<M2>(vec, prime, g, blockIdx.x << g.lrows, tb.fwd[prime], ts.lo[0][prime], ts.hi[0][prime], smem);
 }
 
 // Inverse row pass (standalone): DIT rows then w_N^{-j2 k1}.
 template <int M2>
-__global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts,
-                                                               VecSel sel) {
+__global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int prime, NttGeom g, TwBlock tb, TwStep ts) {
   extern __shared__ u32 smem[];
-  if (!vec_live(sel, blockIdx.z)) return;
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   const u32 p = prime_of(prime);
   constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
@@ -559,9 +554,8 @@ __global__ void __launch_bounds__(NTT_THREADS) k_std_inv_rows(u32* data, int pri
 
 // Inverse column pass (standalone): DIT columns, times N^{-1}, natural order.
 template <int M1>
-__global__ void __launch_bounds__(COL_THREADS) k_std_inv_cols(u32* data, int prime, NttGeom g, TwBlock tb, VecSel sel) {
+__global__ void __launch_bounds__(COL_THREADS) k_std_inv_cols(u32* data, int prime, NttGeom g, TwBlock tb) {
   extern __shared__ u32 smem[];
-  if (!vec_live(sel, blockIdx.z)) return;
   u32* vec = data + ((size_t)blockIdx.z << g.logN);
   const u32 p = prime_of(prime);
   constexpr int m1 = M1;
@@ -586,94 +580,6 @@ __global__ void __launch_bounds__(COL_THREADS) k_std_inv_cols(u32* data, int pri
   }
 }
 
-// Three-modulus plans, two-pass lengths: the NTT-domain multiply-accumulate
-// fused into the inverse row pass.  A workgroup takes nr rows (N2 positions
-// each) of one prime (blockIdx.y) of one transform (blockIdx.z).  For a chunk
-// of gch groups it forms every group's signed sum of its members' products
-// at those positions directly in the LDS tile (the operands of a position
-// staged in the thread's own LDS column, the transform's walk staged as
-// operand offsets and signs), runs the inverse row NTTs and the twiddles
-// w_N^{-j2 k1}, and stores the rows to the group buffer
-// G[prime * gps + slot N + position] for the standalone inverse column pass.
-// Slice spectra X[prime * xps + (part K + k) N + e], kernel spectra and
-// companions W, Wq[prime][part][k][N] (no N^{-1}: the column pass applies it).
-template <int M2>
-__global__ void __launch_bounds__(NTT_THREADS) k_mac3_rows(const u32* __restrict__ X, u32* __restrict__ G,
-                                                          const TDesc* td, const TState* ts, const KernelDesc* kd,
-                                                          const int* tlist, int K, NttGeom g, TwBlock tb, TwStep st,
-                                                          int lr, int gch, int toff) {
-  extern __shared__ u32 smem[];
-  const int t = tlist[blockIdx.z];
-  const TState& s = ts[t];
-  if (s.status) return;
-  const TDesc& d = td[t];
-  const KernelDesc& kk = kd[d.kd];
-  const int q = blockIdx.y;
-  const u32 p = prime_of(q);
-  constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2), TH = NTT_THREADS;
-  const int nr = 1 << lr, V = 2 * K, SL = 2 * K * K, logN = d.logN;
-  const u32 Nmask = (1u << logN) - 1;
-  uint2* tw = reinterpret_cast<uint2*>(smem);                // inverse block roots (N2 words)
-  u32* twmem = smem + N2;                                    // row twiddles
-  u32* code = twmem + ((rowtw_words(m2, nr) + 3) & ~3);      // the two walks, [component][position]
-  u32* col = code + 2 * MAX_MEMBERS + threadIdx.x;           // this thread's operand column: x, w, wq
-  u32* tile = smem + toff;                                   // gch * nr rows
-  load_block_tw(tw, tb.inv[q], m2);
-  const int i1_0 = blockIdx.x << lr;
-  RowTw rt;
-  build_rowtw(rt, twmem, nr, i1_0, g.m1, m2, Nmask, st.lo[1][q], st.hi[1][q], p);
-  const int nm0 = s.nmem[0], nm = nm0 + s.nmem[1];
-  for (int i = threadIdx.x; i < nm; i += TH) {
-    const int tg = i >= nm0, m = i - tg * nm0, c = s.mc[tg][m];
-    const int xo = ((((c + 1) >> 1) & 1) * K + s.ms[tg][m]) * TH;
-    const int wo = ((c & 1) * K + s.mt[tg][m]) * TH;
-    code[tg * MAX_MEMBERS + m] = (u32)xo | ((u32)wo << 13) | (c == 1 ? 1u << 31 : 0u);
-  }
-  __syncthreads();
-  const size_t base = (size_t)i1_0 << m2, wps = (size_t)V << logN;
-  const u32* Xb = X + d.X_off + q * d.xps + base;
-  const u32* Wb = kk.W + q * wps + base;
-  const u32* Qb = kk.Wq + q * wps + base;
-  u32* Gb = G + d.G_off + q * d.gps + base;
-  const int ng0 = s.ngroups[0], gtot = ng0 + s.ngroups[1];
-  for (int g0 = 0; g0 < gtot; g0 += gch) {
-    const int g1 = min(gtot, g0 + gch);
-    for (int idx = threadIdx.x; idx < (nr << m2); idx += TH) {
-      for (int v = 0; v < V; ++v) {
-        const int part = v >= K, k = v - part * K;
-        const size_t o = ((size_t)v << logN) + idx;
-        if (k < s.kx[part]) col[v * TH] = Xb[o];
-        if (k < kk.kw[part]) {
-          col[(V + v) * TH] = Wb[o];
-          col[(2 * V + v) * TH] = Qb[o];
-        }
-      }
-      const int r = idx >> m2, j2 = idx & (N2 - 1);
-      for (int gi = g0; gi < g1; ++gi) {
-        const int tg = gi >= ng0, gl = gi - tg * ng0;
-        const int m0 = s.groups[tg][gl].start, m1 = m0 + s.groups[tg][gl].count;
-        u32 acc = 0;
-        for (int m = m0; m < m1; ++m) {
-          const u32 cd = code[tg * MAX_MEMBERS + m];
-          const int wo = (cd >> 13) & 0x1FFF;
-          const u32 pr = shoup_mul(col[cd & 0x1FFF], col[V * TH + wo], col[2 * V * TH + wo], p);
-          acc = (cd >> 31) ? sub_mod(acc, pr, p) : add_mod(acc, pr, p);
-        }
-        tile[((gi - g0) * nr + r) * ldr + pad8(j2)] = acc;
-      }
-    }
-    __syncthreads();
-    block_ntt<M2, true, false>(tile, (g1 - g0) * nr, ldr, tw, p);
-    for (int idx = threadIdx.x; idx < (((g1 - g0) * nr) << m2); idx += TH) {
-      const int row = idx >> m2, j2 = idx & (N2 - 1), gi = g0 + row / nr, r = row - (row / nr) * nr;
-      const int tg = gi >= ng0, gl = gi - tg * ng0;
-      Gb[((size_t)(tg * SL + gl) << logN) + ((size_t)r << m2) + j2] = apply_rowtw(rt, tile[row * ldr + pad8(j2)], r,
-                                                                                  j2, m2, p);
-    }
-    __syncthreads();                                         // the tile is refilled by the next chunk
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Pipeline kernels.  blockIdx.z indexes the transform list.
 
@@ -682,16 +588,17 @@ struct FwdSel {
   int valid, prime;
 };
 
-__device__ __forceinline__ bool fwd_select(u32* X, const TDesc* td, const TState* ts, const int* tlist, int K,
+// vector vi = (part K + k) np + prime
+__device__ __forceinline__ bool fwd_select(u32* X, const TDesc* td, const TState* ts, const int* tlist, int K, int np,
                                            bool valid_full, int vi, FwdSel& o) {
   const int t = tlist[blockIdx.z];
   const TDesc& d = td[t];
   const TState& s = ts[t];
-  const int part = vi / (2 * K), k = (vi >> 1) % K;
+  const int pk = vi / np, part = pk / K, k = pk - part * K;
   if (s.status || k >= s.kx[part]) return false;
   o.vec = X + d.X_off + ((size_t)vi << d.logN);
   o.valid = valid_full ? d.N : d.n;
-  o.prime = vi & 1;
+  o.prime = vi - pk * np;
   return true;
 }
 
@@ -725,33 +632,33 @@ __device__ __forceinline__ bool walk_slice(const WalkArgs& w, const TDesc* td, c
 
 template <int M>
 __global__ void __launch_bounds__(NTT_THREADS) k_fwd_single(u32* X, const TDesc* td, const TState* ts,
-                                                            const int* tlist, int K, bool valid_full, int vi_lo,
-                                                            TwBlock tb, WalkArgs walk) {
+                                                            const int* tlist, int K, int np, bool valid_full,
+                                                            int vi_lo, TwBlock tb, WalkArgs walk) {
   extern __shared__ u32 smem[];
   if (walk_slice(walk, td, tlist, smem)) return;
   FwdSel o;
-  if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
+  if (!fwd_select(X, td, ts, tlist, K, np, valid_full, vi_lo + blockIdx.y, o)) return;
   fwd_single_body<M>(o.vec, o.valid, o.prime, tb.fwd[o.prime], smem);
 }
 
 template <int M1>
 __global__ void __launch_bounds__(COL_THREADS) k_fwd_cols(u32* X, const TDesc* td, const TState* ts,
-                                                          const int* tlist, int K, bool valid_full, int vi_lo,
-                                                          NttGeom g, TwBlock tb, TwStep st, WalkArgs walk) {
+                                                          const int* tlist, int K, int np, bool valid_full,
+                                                          int vi_lo, NttGeom g, TwBlock tb, TwStep st, WalkArgs walk) {
   extern __shared__ u32 smem[];
   if (walk_slice(walk, td, tlist, smem)) return;
   FwdSel o;
-  if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
+  if (!fwd_select(X, td, ts, tlist, K, np, valid_full, vi_lo + blockIdx.y, o)) return;
   fwd_cols_body<M1>(o.vec, o.valid, o.prime, g, col_tile(blockIdx.x, g.m2 - g.lc) << g.lc, tb.fwd[o.prime], smem);
 }
 
 template <int M2>
 __global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(u32* X, const TDesc* td, const TState* ts,
-                                                          const int* tlist, int K, bool valid_full, int vi_lo,
-                                                          NttGeom g, TwBlock tb, TwStep st) {
+                                                          const int* tlist, int K, int np, bool valid_full,
+                                                          int vi_lo, NttGeom g, TwBlock tb, TwStep st) {
   extern __shared__ u32 smem[];
   FwdSel o;
-  if (!fwd_select(X, td, ts, tlist, K, valid_full, vi_lo + blockIdx.y, o)) return;
+  if (!fwd_select(X, td, ts, tlist, K, np, valid_full, vi_lo + blockIdx.y, o)) return;
   fwd_rows_body<M2>(o.vec, o.prime, g, blockIdx.x << g.lrows, tb.fwd[o.prime], st.lo[0][o.prime], st.hi[0][o.prime], smem);
 }
 
@@ -776,6 +683,7 @@ struct MacArgs {
   int K, logN, prime;
   u32 p;
   int kw0, kw1;      // kernel slice counts of Re w*, Im w*
+  int np;            // moduli
 };
 
 __device__ __forceinline__ uint2 ld2(const u32* ptr) { return *reinterpret_cast<const uint2*>(ptr); }
@@ -917,15 +825,15 @@ __device__ __forceinline__ void walk_full(const V (&xa)[KT], const V (&wa)[KT], 
 // counts): the members (convolution, s, t) recorded by the schedule.
 __device__ void walk_mem(const MacArgs& a, const TState& s, int tg, int gbase, int g0, int g1, size_t e, u32* lds0,
                          int rstride) {
-  const size_t N = (size_t)1 << a.logN, sstride = 2 * N;
+  const size_t N = (size_t)1 << a.logN, sstride = a.np * N;
   int g = gbase;
   uint2 acc = make_uint2(0, 0);
   for (int w = 0; w < s.nmem[tg]; ++w) {
     const int c = s.mc[tg][w], ss = s.ms[tg][w], tt = s.mt[tg][w];
     const int pa = c_conv_pa[c], pb = c_conv_pb[c];
-    const u32* xb = a.X + (size_t)((pa * a.K) * 2 + a.prime) * N + e;
-    const u32* wb = a.W + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
-    const u32* qb = a.Wq + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
+    const u32* xb = a.X + (size_t)((pa * a.K) * a.np + a.prime) * N + e;
+    const u32* wb = a.W + (size_t)((pb * a.K) * a.np + a.prime) * N + e;
+    const u32* qb = a.Wq + (size_t)((pb * a.K) * a.np + a.prime) * N + e;
     if (c == 1) mac_sub(acc, ld2(xb + ss * sstride), ld2(wb + tt * sstride), ld2(qb + tt * sstride), a.p);
     else mac_acc(acc, ld2(xb + ss * sstride), ld2(wb + tt * sstride), ld2(qb + tt * sstride), a.p);
     if ((s.gend[tg][w >> 6] >> (w & 63)) & 1) {
@@ -947,11 +855,11 @@ __device__ __forceinline__ const u32* at_byte(const u32* base, u32 byte_off) {
   return reinterpret_cast<const u32*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 __device__ __forceinline__ void ldv(u32& v, const u32* ptr) { v = *ptr; }
-template <typename V>
+template <int NP, typename V>
 __device__ __forceinline__ void load_wregs(WRegs<V>& r, const u32* W, const u32* Wq, int K, int logN, int prime,
                                            int kw0, int kw1, u32 e) {
   // uniform row pointers plus a 32-bit byte offset per lane (e < N <= 2^24)
-  const size_t N = (size_t)1 << logN, sstride = 2 * N, part = (size_t)K * sstride;
+  const size_t N = (size_t)1 << logN, sstride = NP * N, part = (size_t)K * sstride;
   const u32 eb = e * 4u;
   const u32* wb = W + (size_t)prime * N;
   const u32* qb = Wq + (size_t)prime * N;
@@ -968,10 +876,10 @@ __device__ __forceinline__ void load_wregs(WRegs<V>& r, const u32* W, const u32*
   }
 }
 // Slice spectra of Re x' (xr) and Im x' (xi) at positions e, e+1.
-template <typename V>
+template <int NP, typename V>
 __device__ __forceinline__ void load_xregs(V (&xr)[KT], V (&xi)[KT], const u32* X, int K, int logN, int prime, int kx0,
                                            int kx1, u32 e) {
-  const size_t N = (size_t)1 << logN, sstride = 2 * N, part = (size_t)K * sstride;
+  const size_t N = (size_t)1 << logN, sstride = NP * N, part = (size_t)K * sstride;
   const u32 eb = e * 4u;
   const u32* xb = X + (size_t)prime * N;
 #pragma unroll
@@ -1022,7 +930,7 @@ __device__ __forceinline__ void mac_full(const V (&xr)[KT], const V (&xi)[KT], c
 // Output components [tg_lo, tg_hi] at positions e, e+1 (e even).
 __device__ void mac_pair(const MacArgs& a, const TState& s, bool merged, int tg_lo, int tg_hi, const int (&gofs)[2],
                          int g0, int g1, size_t e, u32* lds0, int rstride) {
-  const size_t N = (size_t)1 << a.logN, sstride = 2 * N;
+  const size_t N = (size_t)1 << a.logN, sstride = a.np * N;
   const int kx0 = s.kx[0], kx1 = s.kx[1];
   if (kx0 <= KT && kx1 <= KT && a.kw0 <= KT && a.kw1 <= KT) {
     uint2 w0[KT], q0[KT], w1[KT], q1[KT], xr[KT], xi[KT];
@@ -1062,11 +970,12 @@ __device__ void mac_single(const MacArgs& a, const TState& s, int tg_lo, int tg_
     for (int w = 0; w < s.nmem[tg]; ++w) {
       const int c = s.mc[tg][w], ss = s.ms[tg][w], tt = s.mt[tg][w];
       const int pa = c_conv_pa[c], pb = c_conv_pb[c];
-      const u32* xb = a.X + (size_t)((pa * a.K) * 2 + a.prime) * N + e;
-      const u32* wb = a.W + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
-      const u32* qb = a.Wq + (size_t)((pb * a.K) * 2 + a.prime) * N + e;
-      if (c == 1) mac_sub(acc, xb[ss * 2 * N], wb[tt * 2 * N], qb[tt * 2 * N], a.p);
-      else mac_acc(acc, xb[ss * 2 * N], wb[tt * 2 * N], qb[tt * 2 * N], a.p);
+      const u32* xb = a.X + (size_t)((pa * a.K) * a.np + a.prime) * N + e;
+      const u32* wb = a.W + (size_t)((pb * a.K) * a.np + a.prime) * N + e;
+      const u32* qb = a.Wq + (size_t)((pb * a.K) * a.np + a.prime) * N + e;
+      const size_t xo = (size_t)ss * a.np * N, wo = (size_t)tt * a.np * N;
+      if (c == 1) mac_sub(acc, xb[xo], wb[wo], qb[wo], a.p);
+      else mac_acc(acc, xb[xo], wb[wo], qb[wo], a.p);
       if ((s.gend[tg][w >> 6] >> (w & 63)) & 1) {
         if (g >= g0 && g < g1) lds0[(g - g0) * rstride] = acc;
         acc = 0;
@@ -1105,16 +1014,16 @@ __device__ __forceinline__ void decode_tile(int L, int pairs, int count, int& pa
 template <int M>
 __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z, const TDesc* td, const TState* ts,
                                                             const KernelDesc* kd, const int* tlist, int count, int K,
-                                                            int slot_lo, int slot_hi, TwBlock tb) {
+                                                            int np, int slot_lo, int slot_hi, TwBlock tb) {
   constexpr int logN = M;
   extern __shared__ u32 smem[];
   int pair, b;
-  decode_tile(blockIdx.x, 4, count, pair, b);
+  decode_tile(blockIdx.x, 2 * np, count, pair, b);
   const int t = tlist[b];
   const TDesc& d = td[t];
   const TState& s = ts[t];
   if (s.status) return;
-  const int tg = pair >> 1, prime = pair & 1;
+  const int tg = pair / np, prime = pair - tg * np;
   const int ng = s.ngroups[tg];
   if (ng == 0) return;
   const u32 p = prime_of(prime);
@@ -1124,7 +1033,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + N;
   load_block_tw(tw, tb.inv[prime], logN);
-  const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, logN, prime, p, kk.kw[0], kk.kw[1]};
+  const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, logN, prime, p, kk.kw[0], kk.kw[1], np};
   const int gofs[2] = {0, 0};
   for (int g0 = 0; g0 < ng; g0 += vmax) {
     const int g1 = min(ng, g0 + vmax);
@@ -1140,7 +1049,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
     for (int gi = g0; gi < g1; ++gi) {
       const int slot = tg * SL + gi;
       if (slot < slot_lo || slot >= slot_hi) continue;
-      u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.zs;
+      u32* zo = Z + d.Z_off + (size_t)(slot * np + prime) * d.zs;
       const u32* row = tile + (gi - g0) * ldr;
       for (int i = threadIdx.x; i < d.n; i += blockDim.x) zo[i] = row[pad8(i)];
     }
@@ -1155,8 +1064,8 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_single(const u32* X, u32* Z
 template <int PL = 8>
 __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u32* tile, const u32* rtw,
                                                  const int (&gofs)[2], int g0, int g1, int SL, int slot_lo,
-                                                 int slot_hi, int prime, int logN, size_t base, int m2, int nr,
-                                                 int ldr, u32 p) {
+                                                 int slot_hi, int np, int prime, int logN, size_t base, int m2,
+                                                 int nr, int ldr, u32 p) {
   const int quads = (nr << m2) >> 2, N2 = 1 << m2;
   const int items = (g1 - g0) * quads;
   const bool fixed = (blockDim.x % quads) == 0;
@@ -1186,7 +1095,7 @@ __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u
     v.y = shoup_mul(v.y, w.y, wq.y, p);
     v.z = shoup_mul(v.z, w.z, wq.z, p);
     v.w = shoup_mul(v.w, w.w, wq.w, p);
-    reinterpret_cast<uint4*>(G + d.G_off + ((size_t)(slot * 2 + prime) << logN) + base)[q] = v;
+    reinterpret_cast<uint4*>(G + d.G_off + ((size_t)(slot * np + prime) << logN) + base)[q] = v;
   }
 }
 
@@ -1202,7 +1111,7 @@ __device__ __forceinline__ void store_group_rows(u32* G, const TDesc& d, const u
 // one is transformed; more groups than one chunk holds recompute the
 // products from the registers per chunk.  (The batched schedule runs the
 // pipelined form below, which also does the forward row pass; this one
-// serves the per-group launches of the plain form.)
+// serves the per-group launches of the plain form, two moduli.)
 constexpr int INV_ROW_THREADS = 512;
 template <int M2>
 __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* X, u32* G, const TDesc* td,
@@ -1245,7 +1154,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
   while (bn < b_hi && ts[tlist[bn]].status) ++bn;
   if (bn < b_hi) {
     const int t = tlist[bn];
-    load_xregs(xr, xi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], pos);
+    load_xregs<2>(xr, xi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], pos);
   }
   while (bn < b_hi) {
     const int t = tlist[bn];
@@ -1253,7 +1162,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
     const TState& s = ts[t];
     const KernelDesc& kk = kd[d.kd];
     if (d.kd != wkd) {
-      load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], pos);
+      load_wregs<2>(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], pos);
       wkd = d.kd;
     }
     const int gofs[2] = {0, s.ngroups[0]};
@@ -1265,25 +1174,26 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
       mac_regs(xr, xi, wr, s, d.acc_mode == ACC_COMPLEX, kk.kw[0], kk.kw[1], gofs, g0, g1, lds_me, nr * ldr, p);
       if (g1 == gtot && b2 < b_hi) {                          // slices consumed: fetch the next transform's
         const int t2 = tlist[b2];
-        load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], pos);
+        load_xregs<2>(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], pos);
       }
       __syncthreads();
       block_ntt<M2, true, false, PL>(tile, (g1 - g0) * nr, ldr, tw, p);
-      store_group_rows<PL>(G, d, tile, rtw, gofs, g0, g1, SL, slot_lo, slot_hi, prime, g.logN, base, m2, nr, ldr, p);
+      store_group_rows<PL>(G, d, tile, rtw, gofs, g0, g1, SL, slot_lo, slot_hi, 2, prime, g.logN, base, m2, nr, ldr,
+                           p);
       __syncthreads();
     }
     if (gtot == 0 && b2 < b_hi) {                             // no groups (all-zero input): still advance
       const int t2 = tlist[b2];
-      load_xregs(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], pos);
+      load_xregs<2>(xr, xi, X + td[t2].X_off, K, g.logN, prime, ts[t2].kx[0], ts[t2].kx[1], pos);
     }
     bn = b2;
   }
 }
 
 // Persistent, pipelined form of the folded inverse row pass (the batched
-// schedule's row pass whenever fused_rows_ok holds).  The work units are
-// (row tile, prime, transform); workgroup i of the grid (sized to the
-// workgroups that fit the GPU at once) takes the contiguous units
+// schedule's row pass whenever fused_rows_ok holds; NP moduli).  The work
+// units are (row tile, prime, transform); workgroup i of the grid (sized to
+// the workgroups that fit the GPU at once) takes the contiguous units
 // [i U / grid, (i + 1) U / grid), U = tiles x primes x transforms, in the
 // order (tile, prime) major, transform minor, so a workgroup mostly stays on
 // one tile and prime and keeps the kernel-slice operands of its position in
@@ -1300,7 +1210,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_reg(const u32* 
 // spectra.  Nothing else touches another thread's position, so two barriers
 // per transform suffice.  The row twiddles w_N^{+-j2 k1} of the thread's
 // position are formed in registers once per (tile, prime).
-template <int M2>
+template <int M2, int NP>
 __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_pipe(const u32* X, u32* G, const TDesc* td,
                                                                    const TState* ts, const KernelDesc* kd,
                                                                    const int* tlist, int count, int K, NttGeom g,
@@ -1321,7 +1231,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_pipe(const u32*
   const int e_loc = threadIdx.x;
   const int r_loc = e_loc >> m2, j2 = e_loc & (N2 - 1);
   const int off_me = r_loc * ldr + padl<PL>(j2);
-  const long units = (long)(2 << (g.m1 - lrows)) * count;
+  const long units = (long)(NP << (g.m1 - lrows)) * count;
   const long u_lo = units * blockIdx.x / gridDim.x, u_hi = units * (blockIdx.x + 1) / gridDim.x;
 
   auto live = [&](int b) { return !ts[tlist[b]].status; };
@@ -1343,9 +1253,9 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_pipe(const u32*
     const long seg_end = min(u_hi, (long)(pair + 1) * count);
     const int b_hi = (int)(seg_end - (long)pair * count);
     u = seg_end;
-    const int prime = pair & 1;
+    const int rtile = pair / NP, prime = pair - rtile * NP;
     const u32 p = prime_of(prime);
-    const int i1_0 = (pair >> 1) << lrows;
+    const int i1_0 = rtile << lrows;
     const size_t base = (size_t)i1_0 << m2;
     const u32 pos = (u32)base + (u32)e_loc;
     // tables of this (tile, prime): block roots in LDS, row twiddles of this position
@@ -1383,7 +1293,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_pipe(const u32*
     };
     auto fetch = [&](int b) {                                 // column output of transform b into yr, yi
       const int t = tlist[b];
-      load_xregs(yr, yi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], pos);
+      load_xregs<NP>(yr, yi, X + td[t].X_off, K, g.logN, prime, ts[t].kx[0], ts[t].kx[1], pos);
     };
     // prologue: forward rows of the first live transform; the second one's
     // column output is fetched while they run
@@ -1406,7 +1316,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_pipe(const u32*
       const TState& s = ts[t];
       const KernelDesc& kk = kd[d.kd];
       if (d.kd != wkd) {
-        load_wregs(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], pos);
+        load_wregs<NP>(wr, kk.W, kk.Wq, K, g.logN, prime, kk.kw[0], kk.kw[1], pos);
         wkd = d.kd;
       }
       const int b2 = next_live(bn);                           // its column output is in yr, yi
@@ -1434,7 +1344,7 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_pipe(const u32*
         for (int gi = g0; gi < g1; ++gi) {                    // this position of every group row
           const int slot = gi < ng0 ? gi : SL + gi - ng0;
           const u32 v = shoup_mul(tileA[(gi - g0) * tstride + om], iwt.x, iwt.y, p);
-          G[d.G_off + ((size_t)(slot * 2 + prime) << g.logN) + pos] = v;
+          G[d.G_off + ((size_t)(slot * NP + prime) << g.logN) + pos] = v;
         }
         if (nB) get_b(nkx0, nkx1, om);
         if (last) break;
@@ -1449,14 +1359,14 @@ __global__ void __launch_bounds__(INV_ROW_THREADS, 6) k_inv_rows_pipe(const u32*
 template <int M2>
 __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, const TDesc* td, const TState* ts,
                                                           const KernelDesc* kd, const int* tlist, int count, int K,
-                                                          int slot_lo, int slot_hi, NttGeom g, TwBlock tb,
+                                                          int np, int slot_lo, int slot_hi, NttGeom g, TwBlock tb,
                                                           TwStep st, int tpw) {
   extern __shared__ u32 smem[];
   const int nruns = (count + tpw - 1) / tpw;
   int pair, run;
-  decode_tile(blockIdx.x, 2 << (g.m1 - g.lrows_inv), nruns, pair, run);
+  decode_tile(blockIdx.x, np << (g.m1 - g.lrows_inv), nruns, pair, run);
   const int b_lo = run * tpw, b_hi = min(count, b_lo + tpw);
-  const int prime = pair & 1;
+  const int rtile = pair / np, prime = pair - rtile * np;
   const u32 p = prime_of(prime);
   constexpr int m2 = M2, N2 = 1 << m2, ldr = row_ld(N2);
   const int nr = 1 << g.lrows_inv, SL = 2 * K * K;           // slots per output component
@@ -1466,7 +1376,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
   u32* rtw = smem + N2;                                       // w_N^{-j2 k1} per tile element, then companions
   u32* tile = smem + N2 + 2 * (nr << m2);
   load_block_tw(tw, tb.inv[prime], m2);
-  const int i1_0 = (pair >> 1) << g.lrows_inv;
+  const int i1_0 = rtile << g.lrows_inv;
   for (int e = threadIdx.x; e < (nr << m2); e += blockDim.x) {
     const uint2 r = step_root(((u32)(e & (N2 - 1)) * bitrev(i1_0 + (e >> m2), g.m1)) & Nmask, st.lo[1][prime],
                               st.hi[1][prime], p);
@@ -1483,7 +1393,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
     const KernelDesc& kk = kd[d.kd];
     const int gofs[2] = {0, s.ngroups[0]};
     const int gtot = s.ngroups[0] + s.ngroups[1];
-    const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, g.logN, prime, p, kk.kw[0], kk.kw[1]};
+    const MacArgs ma{X + d.X_off, kk.W, kk.Wq, K, g.logN, prime, p, kk.kw[0], kk.kw[1], np};
     for (int g0 = 0; g0 < gtot; g0 += gch) {
       const int g1 = min(gtot, g0 + gch);
       // tile vector (number - g0) * nr + r holds row r of that group
@@ -1493,24 +1403,25 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(const u32* X, u32* G, 
       }
       __syncthreads();
       block_ntt<M2, true, false>(tile, (g1 - g0) * nr, ldr, tw, p);
-      store_group_rows(G, d, tile, rtw, gofs, g0, g1, SL, slot_lo, slot_hi, prime, g.logN, base, m2, nr, ldr, p);
+      store_group_rows(G, d, tile, rtw, gofs, g0, g1, SL, slot_lo, slot_hi, np, prime, g.logN, base, m2, nr, ldr, p);
       __syncthreads();
     }
   }
 }
 
 // Two-pass inverse, second pass (columns).  The group vectors of a transform
-// are numbered j = 2 gi + prime over the Alg. 8 groups gi of all four
+// are numbered j = np gi + prime over the Alg. 8 groups gi of all four
 // convolutions; workgroup (x, y, z) takes column tile x of vectors
 // [y vpw, (y + 1) vpw) of transform z.  The tile of the next vector is
 // loaded into registers while the current one is transformed, and the first
 // n natural-order outputs go to the compact buffer.
 constexpr int COL_PF = 8;        // 16-byte registers per thread staging the next tile (tile <= 16K words)
 
-struct ColVecs {                 // group vectors of one transform (numbering j = 2 gi + prime)
+struct ColVecs {                 // group vectors of one transform (numbering j = np gi + prime)
   int ng0, SL, slot_lo, slot_hi, j_hi;   // ng0: groups of Re y'; SL: slots per output component
+  int np;
   __device__ __forceinline__ int slot_of(int j) const {
-    const int gi = j >> 1;
+    const int gi = j / np;
     return gi < ng0 ? gi : SL + gi - ng0;
   }
   // first vector >= j whose slot lies in [slot_lo, slot_hi), or j_hi
@@ -1568,7 +1479,7 @@ __device__ __forceinline__ void put_col_tile(ColStage& b, u32* tile, int tot4, i
 
 template <int M1>
 __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, const TDesc* td, const TState* ts,
-                                                          const int* tlist, int K, int slot_lo, int slot_hi,
+                                                          const int* tlist, int K, int np, int slot_lo, int slot_hi,
                                                           NttGeom g, TwBlock tb, int vpw) {
   extern __shared__ u32 smem[];
   const int t = tlist[blockIdx.z];
@@ -1580,32 +1491,32 @@ __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, 
   cv.SL = 2 * K * K;
   cv.slot_lo = slot_lo;
   cv.slot_hi = slot_hi;
+  cv.np = np;
   const int gtot = cv.ng0 + s.ngroups[1];
   const int j_lo = blockIdx.y * vpw;
-  cv.j_hi = min(2 * gtot, j_lo + vpw);
+  cv.j_hi = min(np * gtot, j_lo + vpw);
   if (j_lo >= cv.j_hi) return;
   constexpr int m1 = M1;
   const int m2 = g.m2, lc = g.lc, lq = lc - 2, n = d.n;
-  uint2* tw0 = reinterpret_cast<uint2*>(smem);             // roots of both primes, 2^(m1-1) entries each
-  uint2* tw1 = tw0 + (1 << (m1 - 1));
-  u32* tile = smem + (2 << m1);
-  load_block_tw(tw0, tb.inv[0], m1);
-  load_block_tw(tw1, tb.inv[1], m1);
+  uint2* tw0 = reinterpret_cast<uint2*>(smem);             // roots of every prime, 2^(m1-1) entries each
+  u32* tile = smem + (np << m1);
+  for (int q = 0; q < np; ++q) load_block_tw(tw0 + (q << (m1 - 1)), tb.inv[q], m1);
   const int j2_0 = col_tile(blockIdx.x, m2 - lc) << lc;
   const int tot4 = 1 << (m1 + lq);
   const u32* gbase = G + d.G_off;
   ColStage buf;
   int j = cv.next(j_lo);
-  if (j < cv.j_hi) fetch_col_tile(buf, gbase + ((size_t)(cv.slot_of(j) * 2 + (j & 1)) << g.logN), tot4, lq, m2, j2_0);
+  auto vec_of = [&](int jj) { return gbase + ((size_t)(cv.slot_of(jj) * np + jj % np) << g.logN); };
+  if (j < cv.j_hi) fetch_col_tile(buf, vec_of(j), tot4, lq, m2, j2_0);
   __syncthreads();                    // root tables
   while (j < cv.j_hi) {
-    const int prime = j & 1, slot = cv.slot_of(j);
+    const int prime = j % np, slot = cv.slot_of(j);
     put_col_tile(buf, tile, tot4, lq, lc);
     __syncthreads();
     const int jn = cv.next(j + 1);
-    if (jn < cv.j_hi) fetch_col_tile(buf, gbase + ((size_t)(cv.slot_of(jn) * 2 + (jn & 1)) << g.logN), tot4, lq, m2, j2_0);
-    block_ntt<M1, true, true>(tile, lc, 0, prime ? tw1 : tw0, prime_of(prime));
-    u32* zo = Z + d.Z_off + (size_t)(slot * 2 + prime) * d.zs;   // rows padded to a multiple of 4
+    if (jn < cv.j_hi) fetch_col_tile(buf, vec_of(jn), tot4, lq, m2, j2_0);
+    block_ntt<M1, true, true>(tile, lc, 0, tw0 + (prime << (m1 - 1)), prime_of(prime));
+    u32* zo = Z + d.Z_off + (size_t)(slot * np + prime) * d.zs;   // rows padded to a multiple of 4
     for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
       const int j1 = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
       const int gi = (j1 << m2) + j2_0 + c4;
@@ -1621,7 +1532,7 @@ __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, 
 // postmultiply (two-pass lengths with N1 <= 512, i.e. N <= 2^18; the tile
 // rows of longer lengths would be 16 bytes).  One workgroup of
 // REC_THREADS per (column tile of 2^(12 - M1) columns, transform): for every
-// Alg. 8 group the column vectors of both primes are transformed together,
+// group the column vectors of all NP primes are transformed together,
 // combined by Garner's formula and added, shifted by the group's exponent,
 // to exact per-output accumulators held in registers (REC_OUT outputs per
 // thread); the Re y' groups come first, then the Im y' groups, so one set of
@@ -1635,7 +1546,12 @@ constexpr int REC_THREADS = 1024, REC_OUT = 4;   // 4096-position tiles
 // values is a pad9 row; the stride is 8 mod 64 words so that the eight
 // columns read together at one tile position fall on different LDS banks.
 __host__ __device__ constexpr int rec_ldc(int m1) { return pad9(1 << m1) + ((8 - pad9(1 << m1)) & 63); }
-template <int M1>
+// LDS of the fused column pass: the inverse roots of every prime and two
+// buffers of one tile per prime.
+__host__ __device__ constexpr size_t rec_smem_words(int m1, int np) {
+  return ((size_t)np << m1) + 2 * (size_t)np * ((size_t)rec_ldc(m1) << (12 - m1));
+}
+template <int M1, int NP>
 __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32* Z, const IoPtrs* io, const TDesc* td,
                                                               const TState* ts, const KernelDesc* kd,
                                                               const int* tlist, int K, int m2, TwBlock tb, int dir,
@@ -1650,7 +1566,7 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
   // a transform whose exponent span needs the wide accumulator only gets
   // its column pass here: the residues go to the compact buffer Z for the
   // wide recombination
-  const bool wide = !s.status && (span_wide(s, 0) || span_wide(s, 1));
+  const bool wide = !s.status && (span_wide<NP>(s, 0) || span_wide<NP>(s, 1));
   const int n = d.n, N2 = 1 << m2;
   const int j2_0 = col_tile(blockIdx.x, m2 - LC) << LC;
   const double2* ch = kd[d.kd].chirp;
@@ -1663,23 +1579,22 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
     }
     return;
   }
-  uint2* tw0 = reinterpret_cast<uint2*>(smem);               // inverse roots, 2^(M1-1) per prime
-  uint2* tw1 = tw0 + (1 << (M1 - 1));
+  uint2* tw = reinterpret_cast<uint2*>(smem);                // inverse roots, 2^(M1-1) per prime
   // the tile of each prime holds its 2^LC columns as pad9 rows (column c at
-  // c LDC); two buffers of both primes' tiles: group v uses buffer v & 1, so
+  // c LDC); two buffers of all primes' tiles: group v uses buffer v & 1, so
   // the next group's values are written while other waves still read this
-  // one's.  Each wave owns CPW columns of one prime and runs their inverse
-  // NTTs on its own (wave-local rounds).
+  // one's.  Each wave owns CPW columns of one prime (CPW divides 2^LC) and
+  // runs their inverse NTTs on its own (wave-local rounds); with three
+  // primes the waves take a second turn for the columns beyond 32 CPW.
   // this thread's quad of the tile: row i, columns c4 .. c4 + 3
   const int qi = threadIdx.x >> LQ, qc = (threadIdx.x & ((1 << LQ) - 1)) << 2;
   constexpr int LDC = rec_ldc(M1), TT = LDC << LC;            // words per prime tile
-  u32* tiles = smem + (2 << M1);
-  load_block_tw(tw0, tb.inv[0], M1);
-  load_block_tw(tw1, tb.inv[1], M1);
-  constexpr int NWV = REC_THREADS / 64, CPW = (2 << LC) / NWV;   // columns per wave
+  u32* tiles = smem + (NP << M1);
+#pragma unroll
+  for (int q = 0; q < NP; ++q) load_block_tw(tw + (q << (M1 - 1)), tb.inv[q], M1);
+  constexpr int NWV = REC_THREADS / 64, CPW = (2 << LC) / NWV, NCOL = NP << LC;   // columns per wave, in all
   static_assert(CPW >= 1 && CPW * NWV == (2 << LC), "column split");
-  const int lane = threadIdx.x & 63, wcol = (int)(threadIdx.x >> 6) * CPW;
-  const int wprime = wcol >> LC, wc0 = wcol & ((1 << LC) - 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   auto put_tile = [&](u32* tile, const u32x4& q) {           // quad of row qi, columns qc .. qc + 3
     u32* b = tile + qc * LDC + pad9(qi);
     b[0] = q[0];
@@ -1688,43 +1603,54 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
     b[3 * LDC] = q[3];
   };
   auto at = [&](const u32* tile, int o) { return tile[(o & ((1 << LC) - 1)) * LDC + pad9(o >> LC)]; };
-  auto columns = [&](u32* tile0, u32* tile1) {
+  auto columns_at = [&](u32* buf, int wcol) {
     int ln = lane;
     asm volatile("" : "+v"(ln));
-    rounds_t<M1, 0, true, false, 9, true>((wprime ? tile1 : tile0) + wc0 * LDC, CPW, LDC, wprime ? tw1 : tw0,
-                                          wprime ? P1 : P0, ln, 64);
+    const int wprime = wcol >> LC, wc0 = wcol & ((1 << LC) - 1);
+    rounds_t<M1, 0, true, false, 9, true>(buf + wprime * TT + wc0 * LDC, CPW, LDC, tw + (wprime << (M1 - 1)),
+                                          prime_of(wprime), ln, 64);
   };
-  ColVecs cv;                                                 // group numbering (slot_of)
-  cv.ng0 = s.ngroups[0];
-  cv.SL = 2 * K * K;
-  const int V = cv.ng0 + s.ngroups[1];                        // groups; Re y' groups are [0, ng0)
+  auto columns = [&](u32* buf) {
+    if constexpr (NCOL == NWV * CPW) {
+      columns_at(buf, wave * CPW);
+    } else {
+      for (int wcol = wave * CPW; wcol < NCOL; wcol += NWV * CPW) columns_at(buf, wcol);
+    }
+  };
+  const int ng0 = s.ngroups[0], SL = 2 * K * K;
+  const int V = ng0 + s.ngroups[1];                           // groups; Re y' groups are [0, ng0)
+  auto slot_of = [&](int v) { return v < ng0 ? v : SL + v - ng0; };
   const u32* gb = G + d.G_off;
   const size_t goff = ((size_t)qi << m2) + j2_0 + qc;
-  u32x4 st0 = {0, 0, 0, 0}, st1 = {0, 0, 0, 0};
+  u32x4 st[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) st[q] = u32x4{0, 0, 0, 0};
   auto fetch = [&](int v) {
-    const u32* vec = gb + ((size_t)(cv.slot_of(2 * v) * 2) << d.logN);
-    st0 = *reinterpret_cast<const u32x4*>(vec + goff);
-    st1 = *reinterpret_cast<const u32x4*>(vec + ((size_t)1 << d.logN) + goff);
+    const u32* vec = gb + ((size_t)(slot_of(v) * NP) << d.logN) + goff;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) st[q] = *reinterpret_cast<const u32x4*>(vec + ((size_t)q << d.logN));
+  };
+  auto put_all = [&](u32* buf) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) put_tile(buf + q * TT, st[q]);
   };
   if (wide) {
     if (V > 0) fetch(0);
     for (int v = 0; v < V; ++v) {
-      u32* tile0 = tiles + (v & 1) * 2 * TT;
-      u32* tile1 = tile0 + TT;
-      put_tile(tile0, st0);
-      put_tile(tile1, st1);
+      u32* buf = tiles + (v & 1) * NP * TT;
+      put_all(buf);
       __syncthreads();                                        // tiles (and the root tables) complete
       if (v + 1 < V) fetch(v + 1);
-      columns(tile0, tile1);
+      columns(buf);
       __syncthreads();                                        // columns done
-      u32* z0 = Z + d.Z_off + (size_t)(cv.slot_of(2 * v) * 2) * d.zs;
+      u32* z0 = Z + d.Z_off + (size_t)(slot_of(v) * NP) * d.zs;
 #pragma unroll
       for (int k = 0; k < REC_OUT; ++k) {
         const int o = threadIdx.x + k * REC_THREADS;
         const int j = (o >> LC) * N2 + j2_0 + (o & ((1 << LC) - 1));
         if (j < n) {
-          z0[j] = at(tile0, o);
-          z0[d.zs + j] = at(tile1, o);
+#pragma unroll
+          for (int q = 0; q < NP; ++q) z0[q * d.zs + j] = at(buf + q * TT, o);
         }
       }
     }
@@ -1740,9 +1666,8 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
   }
   if (V > 0) fetch(0);
   for (int v = 0; v < V; ++v) {
-    u32* tile0 = tiles + (v & 1) * 2 * TT;
-    u32* tile1 = tile0 + TT;
-    if (v == cv.ng0 && v > 0) {                               // Re y' complete
+    u32* buf = tiles + (v & 1) * NP * TT;
+    if (v == ng0 && v > 0) {                                  // Re y' complete
 #pragma unroll
       for (int k = 0; k < REC_OUT; ++k) {
         u64 a64[W_FAST];
@@ -1753,22 +1678,24 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
         for (int l = 0; l < NL_FAST; ++l) acc[k][l] = 0;
       }
     }
-    put_tile(tile0, st0);
-    put_tile(tile1, st1);
+    put_all(buf);
     __syncthreads();                                          // tiles (and the root tables) complete
     if (v + 1 < V) fetch(v + 1);
-    columns(tile0, tile1);
+    columns(buf);
     __syncthreads();                                          // columns done
-    const int tg = v >= cv.ng0 ? 1 : 0;                       // the signs are applied in the NTT domain
-    const int sh = s.groups[tg][v - (tg ? cv.ng0 : 0)].e - s.emin[tg];
+    const int tg = v >= ng0 ? 1 : 0;                          // the signs are applied in the NTT domain
+    const int sh = s.groups[tg][v - (tg ? ng0 : 0)].e - s.emin[tg];
 #pragma unroll
     for (int k = 0; k < REC_OUT; ++k) {
       const int o = threadIdx.x + k * REC_THREADS;
-      limb_add(acc[k], garner(at(tile0, o), at(tile1, o)), sh);
+      u32 z[NP];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) z[q] = at(buf + q * TT, o);
+      limb_add_crt<NP>(acc[k], z, sh);
     }
   }
   double pi[REC_OUT];
-  const bool has_im = V > cv.ng0;
+  const bool has_im = V > ng0;
 #pragma unroll
   for (int k = 0; k < REC_OUT; ++k) {
     u64 a64[W_FAST];
@@ -1787,9 +1714,9 @@ __global__ void __launch_bounds__(REC_THREADS) k_inv_cols_rec(const u32* G, u32*
 }
 
 // Kernel slices: W <- W * N^{-1}, Wq <- Shoup companion.  Layout [part][t][prime][N].
-__global__ void k_kernel_finish(u32* W, u32* Wq, size_t total, int logN) {
+__global__ void k_kernel_finish(u32* W, u32* Wq, size_t total, int logN, int np) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-    const int prime = (int)((i >> logN) & 1);
+    const int prime = (int)((i >> logN) % np);
     const u32 p = prime_of(prime);
     const u32 ninv = p - ((p - 1) >> logN);
     const u32 v = shoup_mul(W[i], ninv, shoup_companion(ninv, p), p);
@@ -1834,7 +1761,9 @@ NttGeom ntt_geom(int logN, int lc_override, int lrows_override) {
 }
 
 static size_t smem_cols(const NttGeom& g) { return ((size_t)(1 << g.m1) + ((size_t)1 << (g.m1 + g.lc))) * 4; }
-static size_t smem_inv_cols(const NttGeom& g) { return ((size_t)(2 << g.m1) + ((size_t)1 << (g.m1 + g.lc))) * 4; }
+static size_t smem_inv_cols(const NttGeom& g, int np) {
+  return ((size_t)(np << g.m1) + ((size_t)1 << (g.m1 + g.lc))) * 4;
+}
 static size_t smem_rows(const NttGeom& g) {
   return ((size_t)(1 << g.m2) + ((size_t)row_ld(1 << g.m2) << g.lrows) + rowtw_words(g.m2, 1 << g.lrows)) * 4;
 }
@@ -1902,7 +1831,7 @@ static hipError_t big_lds(const void* fn) {
 }
 
 hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool inverse, const NttGeom& g,
-                                 const TwBlock& tb, const TwStep& ts, hipStream_t s, const VecSel& sel, int which) {
+                                 const TwBlock& tb, const TwStep& ts, hipStream_t s, int which) {
   if (count <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
   if (!g.two_pass()) {
@@ -1910,7 +1839,7 @@ hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool
           constexpr int M = decltype(mc)::value;
           if ((e = big_lds((const void*)k_std_single<M>)) != hipSuccess) return;
           hipLaunchKernelGGL(k_std_single<M>, dim3(1, 1, count), dim3(NTT_THREADS), smem_single(logN), s, data, prime,
-                             inverse, tb, sel);
+                             inverse, tb);
         }))
       return hipErrorInvalidValue;
     return e != hipSuccess ? e : hipGetLastError();
@@ -1920,20 +1849,20 @@ hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool
     constexpr int M1 = decltype(mc)::value;
     if (!inverse) {
       if ((e = big_lds((const void*)k_std_fwd_cols<M1>)) != hipSuccess) return;
-      hipLaunchKernelGGL(k_std_fwd_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, ts, sel);
+      hipLaunchKernelGGL(k_std_fwd_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, ts);
     } else {
       if ((e = big_lds((const void*)k_std_inv_cols<M1>)) != hipSuccess) return;
-      hipLaunchKernelGGL(k_std_inv_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, sel);
+      hipLaunchKernelGGL(k_std_inv_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb);
     }
   };
   auto rows = [&](auto mc) {
     constexpr int M2 = decltype(mc)::value;
     if (!inverse) {
       if ((e = big_lds((const void*)k_std_fwd_rows<M2>)) != hipSuccess) return;
-      hipLaunchKernelGGL(k_std_fwd_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts, sel);
+      hipLaunchKernelGGL(k_std_fwd_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
     } else {
       if ((e = big_lds((const void*)k_std_inv_rows<M2>)) != hipSuccess) return;
-      hipLaunchKernelGGL(k_std_inv_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts, sel);
+      hipLaunchKernelGGL(k_std_inv_rows<M2>, gr, dim3(NTT_THREADS), smem_rows(g), s, data, prime, g, tb, ts);
     }
   };
   const bool do_cols = which != 2, do_rows = which != 1;
@@ -1949,49 +1878,12 @@ hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool
   return e != hipSuccess ? e : hipGetLastError();
 }
 
-hipError_t launch_mac3_rows(const u32* X, u32* G, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                            const int* tlist, int count, int K, const NttGeom& g, const TwBlock& tb, const TwStep& st,
-                            hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  if (!g.two_pass()) return hipErrorInvalidValue;
-  // one row per workgroup: every group of the transform in one chunk (up
-  // to about 40 KiB of LDS), so the operands are staged once
-  const int lr = 0, nr = 1 << lr, N2 = 1 << g.m2, ldr = row_ld(N2);
-  const int toff = N2 + ((rowtw_words(g.m2, nr) + 3) & ~3) + 2 * MAX_MEMBERS + 3 * (2 * K) * NTT_THREADS;
-  int gch = (10240 - toff) / (nr * ldr);
-  gch = std::max(1, std::min(gch, 4 * K * K));
-  const size_t lds = 4 * ((size_t)toff + (size_t)gch * nr * ldr);
-  hipError_t e = hipSuccess;
-  if (!with_m<M2_LO, M2_HI>(g.m2, [&](auto mc) {
-        constexpr int M2 = decltype(mc)::value;
-        if ((e = big_lds((const void*)k_mac3_rows<M2>)) != hipSuccess) return;
-        hipLaunchKernelGGL(k_mac3_rows<M2>, dim3(1u << (g.m1 - lr), 3, count), dim3(NTT_THREADS), lds, s, X, G, td,
-                           ts, kd, tlist, K, g, tb, st, lr, gch, toff);
-      }))
-    return hipErrorInvalidValue;
-  return e != hipSuccess ? e : hipGetLastError();
-}
-
-hipError_t launch_inv_cols_standalone(u32* data, int prime, int count, const NttGeom& g, const TwBlock& tb,
-                                      hipStream_t s, const VecSel& sel) {
-  if (count <= 0) return hipSuccess;
-  if (!g.two_pass()) return hipErrorInvalidValue;
-  const dim3 gc(1u << (g.m2 - g.lc), 1, count);
-  hipError_t e = hipSuccess;
-  if (!with_m<M1_LO, M1_HI>(g.m1, [&](auto mc) {
-        constexpr int M1 = decltype(mc)::value;
-        if ((e = big_lds((const void*)k_std_inv_cols<M1>)) != hipSuccess) return;
-        hipLaunchKernelGGL(k_std_inv_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, sel);
-      }))
-    return hipErrorInvalidValue;
-  return e != hipSuccess ? e : hipGetLastError();
-}
-
-hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, bool valid_full,
-                            int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb, const TwStep& st, int which,
-                            hipStream_t s, TState* walk_ts, const KernelDesc* kd, int L) {
+hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, int np,
+                            bool valid_full, int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb,
+                            const TwStep& st, int which, hipStream_t s, TState* walk_ts, const KernelDesc* kd, int L) {
   const int nv = vi_hi - vi_lo;
   if (count <= 0 || nv <= 0) return hipSuccess;
+  if (np != 2 && np != 3) return hipErrorInvalidValue;
   WalkArgs walk;
   if (walk_ts && which != 2) {
     walk.ts = walk_ts;
@@ -2007,7 +1899,7 @@ hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int
           if ((e = big_lds((const void*)k_fwd_single<M>)) != hipSuccess) return;
           // the walk slice stages 4 KMAX exponents in LDS
           const size_t lds = std::max(smem_single(g.logN), sizeof(int) * 4 * KMAX);
-          hipLaunchKernelGGL(k_fwd_single<M>, dim3(1, ny, count), dim3(NTT_THREADS), lds, s, X, td, ts, tlist, K,
+          hipLaunchKernelGGL(k_fwd_single<M>, dim3(1, ny, count), dim3(NTT_THREADS), lds, s, X, td, ts, tlist, K, np,
                              valid_full, vi_lo, tb, walk);
         }))
       return hipErrorInvalidValue;
@@ -2018,7 +1910,7 @@ hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int
         if ((e = big_lds((const void*)k_fwd_cols<M1>)) != hipSuccess) return;
         const size_t lds = std::max(smem_cols(g), sizeof(int) * 4 * KMAX);
         hipLaunchKernelGGL(k_fwd_cols<M1>, dim3(1u << (g.m2 - g.lc), ny, count), dim3(COL_THREADS), lds, s, X, td, ts,
-                           tlist, K, valid_full, vi_lo, g, tb, st, walk);
+                           tlist, K, np, valid_full, vi_lo, g, tb, st, walk);
       }))
     return hipErrorInvalidValue;
   if (e != hipSuccess) return e;
@@ -2026,16 +1918,16 @@ hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int
         constexpr int M2 = decltype(mc)::value;
         if ((e = big_lds((const void*)k_fwd_rows<M2>)) != hipSuccess) return;
         hipLaunchKernelGGL(k_fwd_rows<M2>, dim3(1u << (g.m1 - g.lrows), nv, count), dim3(NTT_THREADS), smem_rows(g), s,
-                           X, td, ts, tlist, K, valid_full, vi_lo, g, tb, st);
+                           X, td, ts, tlist, K, np, valid_full, vi_lo, g, tb, st);
       }))
     return hipErrorInvalidValue;
   return e != hipSuccess ? e : hipGetLastError();
 }
 
-hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K,
+hipError_t launch_fwd_pipeline(u32* X, const TDesc* td, const TState* ts, const int* tlist, int count, int K, int np,
                                bool valid_full, int vi_lo, int vi_hi, const NttGeom& g, const TwBlock& tb,
                                const TwStep& st, hipStream_t s) {
-  return launch_fwd_stage(X, td, ts, tlist, count, K, valid_full, vi_lo, vi_hi, g, tb, st, 0, s);
+  return launch_fwd_stage(X, td, ts, tlist, count, K, np, valid_full, vi_lo, vi_hi, g, tb, st, 0, s);
 }
 
 bool fused_rows_ok(const NttGeom& g, int K) {
@@ -2045,10 +1937,11 @@ bool fused_rows_ok(const NttGeom& g, int K) {
 }
 
 hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                            const int* tlist, int count, int K, int slot_lo, int slot_hi, const NttGeom& g,
+                            const int* tlist, int count, int K, int np, int slot_lo, int slot_hi, const NttGeom& g,
                             const TwBlock& tb, const TwStep& st, int which, hipStream_t s,
                             bool fused_fwd) {
   if (fused_fwd && !fused_rows_ok(g, K)) return hipErrorInvalidValue;   // also keeps the forward rows inside the tile
+  if (np != 2 && np != 3) return hipErrorInvalidValue;
   if (count <= 0 || slot_hi <= slot_lo) return hipSuccess;
   hipError_t e = hipSuccess;
   if (!g.two_pass()) {
@@ -2056,8 +1949,8 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
     if (!with_m<0, LOG2_BLOCK_MAX>(g.logN, [&](auto mc) {
           constexpr int M = decltype(mc)::value;
           if ((e = big_lds((const void*)k_inv_single<M>)) != hipSuccess) return;
-          hipLaunchKernelGGL(k_inv_single<M>, dim3(4 * count), dim3(NTT_THREADS), smem_inv_single(g.logN), s, X, Z, td,
-                             ts, kd, tlist, count, K, slot_lo, slot_hi, tb);
+          hipLaunchKernelGGL(k_inv_single<M>, dim3(2 * np * count), dim3(NTT_THREADS), smem_inv_single(g.logN), s, X,
+                             Z, td, ts, kd, tlist, count, K, np, slot_lo, slot_hi, tb);
         }))
       return hipErrorInvalidValue;
     return e != hipSuccess ? e : hipGetLastError();
@@ -2065,12 +1958,13 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
   if (which != 2) {
     // runs of up to four transforms per workgroup while the grid keeps
     // at least about four workgroups per CU slot (3 per CU on 256 CUs)
-    const long pairs = 2l << (g.m1 - g.lrows_inv);
+    const long pairs = (long)np << (g.m1 - g.lrows_inv);
     int tpw = 1;
     while (tpw < 4 && 2 * tpw <= count && pairs * ((count + 2 * tpw - 1) / (2 * tpw)) >= 3072) tpw *= 2;
     const long runs = (count + tpw - 1) / tpw;
     // register form: slices fit the registers and the row tile has one
-    // position per thread
+    // position per thread (without the folded forward rows: the plain
+    // form's per-group launches, two moduli)
     const bool reg = K <= KT && (1 << (g.m2 + g.lrows_inv)) == INV_ROW_THREADS;
     if (!with_m<M2_LO, M2_HI>(g.m2, [&](auto mc) {
           constexpr int M2 = decltype(mc)::value;
@@ -2081,7 +1975,7 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
                 e = hipErrorInvalidValue;
                 return;
               }
-              auto* kfn = &k_inv_rows_pipe<M2>;
+              auto* kfn = np == 3 ? &k_inv_rows_pipe<M2, 3> : &k_inv_rows_pipe<M2, 2>;
               if ((e = big_lds((const void*)kfn)) != hipSuccess) return;
               const size_t sm = smem_inv_pipe(g);
               const long units = pairs * count;
@@ -2094,7 +1988,7 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
                                  td, ts, kd, tlist, count, K, g, tb, st);
               return;
             }
-            if (reg) {
+            if (reg && np == 2) {
               auto* kfn = &k_inv_rows_reg<M2>;
               if ((e = big_lds((const void*)kfn)) != hipSuccess) return;
               hipLaunchKernelGGL(kfn, dim3((unsigned)(pairs * runs)), dim3(INV_ROW_THREADS), smem_inv_rows(g), s, X,
@@ -2105,7 +1999,7 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
           {
             if ((e = big_lds((const void*)k_inv_rows<M2>)) != hipSuccess) return;
             hipLaunchKernelGGL(k_inv_rows<M2>, dim3((unsigned)(pairs * runs)), dim3(NTT_THREADS), smem_inv_rows(g), s,
-                               X, G, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, tpw);
+                               X, G, td, ts, kd, tlist, count, K, np, slot_lo, slot_hi, g, tb, st, tpw);
           }
         }))
       return hipErrorInvalidValue;
@@ -2114,13 +2008,13 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
   if (which != 1) {
     // the staged next tile must fit COL_PF 16-byte registers per thread
     if (g.m1 + g.lc > 14) return hipErrorInvalidValue;
-    const int vecs = 8 * K * K, vpw = 4;    // group vectors (at most 4 K^2 groups, two primes)
+    const int vecs = 4 * K * K * np, vpw = 4;    // group vectors (at most 4 K^2 groups, np primes)
     const dim3 grid(1u << (g.m2 - g.lc), (vecs + vpw - 1) / vpw, count);
     if (!with_m<M1_LO, M1_HI>(g.m1, [&](auto mc) {
           constexpr int M1 = decltype(mc)::value;
           if ((e = big_lds((const void*)k_inv_cols<M1>)) != hipSuccess) return;
-          hipLaunchKernelGGL(k_inv_cols<M1>, grid, dim3(COL_THREADS), smem_inv_cols(g), s, G, Z, td, ts, tlist, K,
-                             slot_lo, slot_hi, g, tb, vpw);
+          hipLaunchKernelGGL(k_inv_cols<M1>, grid, dim3(COL_THREADS), smem_inv_cols(g, np), s, G, Z, td, ts, tlist, K,
+                             np, slot_lo, slot_hi, g, tb, vpw);
         }))
       return hipErrorInvalidValue;
   }
@@ -2132,32 +2026,33 @@ bool fused_cols_ok(const NttGeom& g) {
 }
 
 hipError_t launch_inv_cols_rec(const u32* G, u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts,
-                               const KernelDesc* kd, const int* tlist, int count, int K, const NttGeom& g,
+                               const KernelDesc* kd, const int* tlist, int count, int K, int np, const NttGeom& g,
                                const TwBlock& tb, int dir, int io32, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (!fused_cols_ok(g)) return hipErrorInvalidValue;
+  if (!fused_cols_ok(g) || (np != 2 && np != 3)) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
   with_m<7, 9>(g.m1, [&](auto mc) {
     constexpr int M1 = decltype(mc)::value;
     constexpr int LC = 12 - M1;
-    const size_t smem = ((size_t)(2 << M1) + 4 * ((size_t)rec_ldc(M1) << LC)) * 4;
-    if ((e = big_lds((const void*)k_inv_cols_rec<M1>)) != hipSuccess) return;
-    hipLaunchKernelGGL(k_inv_cols_rec<M1>, dim3(1u << (g.m2 - LC), 1, count), dim3(REC_THREADS), smem, s, G, Z, io,
-                       td, ts, kd, tlist, K, g.m2, tb, dir, io32);
+    auto* kfn = np == 3 ? &k_inv_cols_rec<M1, 3> : &k_inv_cols_rec<M1, 2>;
+    const size_t smem = rec_smem_words(M1, np) * 4;
+    if ((e = big_lds((const void*)kfn)) != hipSuccess) return;
+    hipLaunchKernelGGL(kfn, dim3(1u << (g.m2 - LC), 1, count), dim3(REC_THREADS), smem, s, G, Z, io, td, ts, kd, tlist,
+                       K, g.m2, tb, dir, io32);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_inv_pipeline(const u32* X, u32* G, u32* Z, const TDesc* td, const TState* ts,
-                               const KernelDesc* kd, const int* tlist, int count, int K, int slot_lo, int slot_hi,
-                               const NttGeom& g, const TwBlock& tb, const TwStep& st, hipStream_t s) {
-  return launch_inv_stage(X, G, Z, td, ts, kd, tlist, count, K, slot_lo, slot_hi, g, tb, st, 0, s);
+                               const KernelDesc* kd, const int* tlist, int count, int K, int np, int slot_lo,
+                               int slot_hi, const NttGeom& g, const TwBlock& tb, const TwStep& st, hipStream_t s) {
+  return launch_inv_stage(X, G, Z, td, ts, kd, tlist, count, K, np, slot_lo, slot_hi, g, tb, st, 0, s);
 }
 
-hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int logN, hipStream_t s) {
-  const size_t total = (size_t)(2 * K * 2) << logN;
+hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int np, int logN, hipStream_t s) {
+  const size_t total = (size_t)(2 * K * np) << logN;
   const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
-  hipLaunchKernelGGL(k_kernel_finish, dim3(blocks), dim3(256), 0, s, W, Wq, total, logN);
+  hipLaunchKernelGGL(k_kernel_finish, dim3(blocks), dim3(256), 0, s, W, Wq, total, logN, np);
   return hipGetLastError();
 }
 

@@ -132,8 +132,6 @@ struct LengthClass {
   std::vector<int> tids;
   int* d_tlist = nullptr;
   int nmax = 0;
-  // three moduli: the class's slice and group buffers, prime by prime
-  i64 x3_base = 0, x3_ps = 0, g3_base = 0, g3_ps = 0;
 };
 
 // A captured batched schedule for one direction.  Its first node writes the
@@ -348,7 +346,7 @@ static int autotune_geom(fft_ozaki_plan_s* p, int logN, int transforms, NttGeom*
   for (int c = 2; c <= 6; ++c) {
     if (!lc_ok(c)) continue;
     const float ms = time_shape(ntt_geom(logN, c, def.lrows), [&](const NttGeom& g) {
-      return launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr, VecSel{}, 1);
+      return launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr, 1);
     });
     FO_LOG("autotune N=2^%d (%d vectors): column tile 2^%d: %.4f ms", logN, vecs, c, ms);
     if (ms < best_c) {
@@ -359,8 +357,8 @@ static int autotune_geom(fft_ozaki_plan_s* p, int logN, int transforms, NttGeom*
   for (int r = 0; r <= 4; ++r) {
     if (!lr_ok(r)) continue;
     const float ms = time_shape(ntt_geom(logN, pick_c, r), [&](const NttGeom& g) {
-      const hipError_t a = launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr, VecSel{}, 2);
-      const hipError_t b = launch_ntt_standalone(buf, logN, 0, vecs, true, g, p->tb, st, nullptr, VecSel{}, 2);
+      const hipError_t a = launch_ntt_standalone(buf, logN, 0, vecs, false, g, p->tb, st, nullptr, 2);
+      const hipError_t b = launch_ntt_standalone(buf, logN, 0, vecs, true, g, p->tb, st, nullptr, 2);
       return a != hipSuccess ? a : b;
     });
     FO_LOG("autotune N=2^%d (%d vectors): row tile 2^%d: %.4f ms", logN, vecs, r, ms);
@@ -425,7 +423,6 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   h.logN = kh.logN;
   h.alpha = kh.alpha;
   h.kd = 0;
-  h.xps = (i64)(2 * K) * (i64)N;         // three moduli: W laid out [prime][part][k][N]
   KernelDesc hk{};
   hk.n = (int)n;
   hk.N = (int)N;
@@ -454,18 +451,11 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
     kh.kw[part] = hs.kx[part];
     for (int k = 0; k < KMAX; ++k) kh.Ew[part][k] = k < hs.kx[part] ? hs.E[part][k] : 0;
   }
-  // forward NTTs of the kernel slices (all N positions populated)
+  // forward NTTs of the kernel slices (all N positions populated), then
+  // N^{-1} folded in and the Shoup companions
   NttGeom g = ntt_geom(kh.logN);
-  if (np == 3) {
-    // prime by prime; the standalone inverse applies N^{-1} itself
-    for (int q = 0; q < 3; ++q)
-      HIPCHK(launch_ntt_standalone(kh.W + (size_t)q * h.xps, kh.logN, q, 2 * K, false, g, p->tb,
-                                   step_for(p, kh.logN), nullptr));
-    HIPCHK(launch_companions3(kh.W, kh.Wq, K, kh.logN, nullptr));
-  } else {
-    HIPCHK(launch_fwd_pipeline(kh.W, td, ts, tl, 1, K, true, 0, 4 * K, g, p->tb, step_for(p, kh.logN), nullptr));
-    HIPCHK(launch_kernel_finish(kh.W, kh.Wq, K, kh.logN, nullptr));
-  }
+  HIPCHK(launch_fwd_pipeline(kh.W, td, ts, tl, 1, K, np, true, 0, 2 * np * K, g, p->tb, step_for(p, kh.logN), nullptr));
+  HIPCHK(launch_kernel_finish(kh.W, kh.Wq, K, np, kh.logN, nullptr));
   HIPCHK(hipDeviceSynchronize());
   (void)idx;
   return FFT_OZAKI_OK;
@@ -542,35 +532,13 @@ static int build_plan(fft_ozaki_plan_s* p) {
     d.G_off = go;
     d.Z_off = zo;
     io += n;
-    if (p->primes == 2) {
-      xo += (i64)(4 * K) << d.logN;
-      if (ntt_geom(d.logN).two_pass()) go += (8 * SL) << d.logN;
-      zo += 8 * SL * (i64)d.zs;
-    }
+    xo += (i64)(2 * p->primes * K) << d.logN;                    // [part][k][prime][N]
+    if (ntt_geom(d.logN).two_pass()) go += (4 * SL * p->primes) << d.logN;   // [slot][prime][N], 4 K^2 slots
+    zo += 4 * SL * p->primes * (i64)d.zs;                        // [slot][prime][zs]
     p->td.push_back(d);
     LengthClass& lc = p->classes[cidx[d.logN]];
     lc.tids.push_back(t);
     lc.nmax = std::max<int>(lc.nmax, (int)n);
-  }
-  if (p->primes == 3) {
-    // per class, prime by prime: slice spectra [prime][transform][part][k][N]
-    // and group sums [prime][transform][slot][N] (4 K^2 slots)
-    for (auto& lc : p->classes) {
-      const i64 N = (i64)1 << lc.logN, T = (i64)lc.tids.size();
-      lc.x3_base = xo;
-      lc.x3_ps = T * 2 * K * N;
-      lc.g3_base = go;
-      lc.g3_ps = T * 4 * SL * N;
-      for (i64 i = 0; i < T; ++i) {
-        TDesc& d = p->td[lc.tids[i]];
-        d.X_off = lc.x3_base + i * 2 * K * N;
-        d.xps = lc.x3_ps;
-        d.G_off = lc.g3_base + i * 4 * SL * N;
-        d.gps = lc.g3_ps;
-      }
-      xo += 3 * lc.x3_ps;
-      go += 3 * lc.g3_ps;
-    }
   }
   p->total = io;
   for (auto& lc : p->classes)
@@ -628,66 +596,10 @@ static int build_plan(fft_ozaki_plan_s* p) {
 // 1 when the plan's transforms read and write complex64 (binary32 target).
 static inline int io32_of(const fft_ozaki_plan_s* p) { return p->precision == FFT_OZAKI_PREC_FP32 ? 1 : 0; }
 
-// The batched launch sequence (also what gets captured into the graph).
+// The batched launch sequence (also what gets captured into the graph), for
+// two or three moduli alike.
 static int enqueue_batched(fft_ozaki_plan_s* p, int dir, hipStream_t s) {
-  const int K = p->K, count = (int)p->td.size();
-  HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
-  for (auto& lc : p->classes)
-    HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
-                         io32_of(p), s));
-  HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
-  for (int r = 0; r < K; ++r) {
-    for (auto& lc : p->classes)
-      HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s));
-    HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
-  }
-  for (auto& lc : p->classes) {
-    // forward NTTs; where the forward row pass is folded into the inverse
-    // row pass, only the column pass here.  The accumulation schedule of the
-    // class's transforms is computed inside the same launch.
-    const int which = fused_rows_ok(lc.geom, K) ? 1 : 0;
-    HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K, lc.geom,
-                            p->tb, step_for(p, lc.logN), which, s, p->d_ts, p->d_kd, p->L));
-  }
-  for (auto& lc : p->classes) {
-    const int cnt = (int)lc.tids.size();
-    if (fused_cols_ok(lc.geom)) {
-      // rows (with the forward rows where possible); fused columns + CRT +
-      // recombination (for transforms that need the wide accumulator: the
-      // columns to the compact buffer, then the wide recombination)
-      HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
-                              p->tb, step_for(p, lc.logN), 1, s, fused_rows_ok(lc.geom, K)));
-      HIPCHK(launch_inv_cols_rec(p->G, p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb, dir,
-                                 io32_of(p), s));
-      HIPCHK(launch_recombine_wide(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s));
-    } else {
-      HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K, lc.geom,
-                              p->tb, step_for(p, lc.logN), 0, s, fused_rows_ok(lc.geom, K)));
-      HIPCHK(launch_recombine(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s));
-    }
-  }
-  return FFT_OZAKI_OK;
-}
-
-// Standalone NTTs of `count` vectors at data, in launches of at most 65535
-// vectors (the grid's z extent); sel numbers the vectors from 0 across them.
-static int ntt_chunked(u32* data, int logN, int prime, i64 count, bool inverse, const NttGeom& g, const TwBlock& tb,
-                       const TwStep& st, hipStream_t s, VecSel sel) {
-  for (i64 v0 = 0; v0 < count; v0 += 65535) {
-    const int c = (int)std::min<i64>(65535, count - v0);
-    sel.v0 = (int)v0;
-    HIPCHK(launch_ntt_standalone(data + ((size_t)v0 << logN), logN, prime, c, inverse, g, tb, st, s, sel));
-  }
-  return FFT_OZAKI_OK;
-}
-
-// The launch sequence of a three-modulus plan (captured like the two-modulus
-// one): premultiply and split as there, then per length class and prime the
-// forward NTTs of the live slice vectors, the NTT-domain multiply-accumulate,
-// the inverse NTTs of the live group vectors, and Garner (d = 3) with the
-// exact recombination and postmultiply.
-static int enqueue_batched3(fft_ozaki_plan_s* p, int dir, hipStream_t s) {
-  const int K = p->K, count = (int)p->td.size();
+  const int K = p->K, np = p->primes, count = (int)p->td.size();
   HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
   for (auto& lc : p->classes)
     HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
@@ -696,45 +608,35 @@ static int enqueue_batched3(fft_ozaki_plan_s* p, int dir, hipStream_t s) {
   for (int r = 0; r < K; ++r) {
     for (auto& lc : p->classes)
       HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s,
-                                  3));
+                                  np));
     HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
   }
-  HIPCHK(launch_groups(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, p->L, s));
   for (auto& lc : p->classes) {
-    const i64 T = (i64)lc.tids.size();
-    const TwStep& st = step_for(p, lc.logN);
-    VecSel xs;
-    xs.ts = p->d_ts;
-    xs.tlist = lc.d_tlist;
-    xs.per = 2 * K;
-    xs.K = K;
-    xs.kind = 1;
-    VecSel gs = xs;
-    gs.per = 4 * K * K;
-    gs.kind = 2;
-    int rc;
-    for (int q = 0; q < 3; ++q)
-      if ((rc = ntt_chunked(p->X + lc.x3_base + q * lc.x3_ps, lc.logN, q, T * 2 * K, false, lc.geom, p->tb, st, s, xs)))
-        return rc;
-    if (lc.geom.two_pass()) {
-      // multiply-accumulate in the inverse row pass, then the column pass
-      HIPCHK(launch_mac3_rows(p->X, p->G, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, K, lc.geom, p->tb, st, s));
-      for (int q = 0; q < 3; ++q)
-        for (i64 v0 = 0; v0 < T * 4 * K * K; v0 += 65535) {
-          VecSel gsc = gs;
-          gsc.v0 = (int)v0;
-          HIPCHK(launch_inv_cols_standalone(p->G + lc.g3_base + q * lc.g3_ps + ((size_t)v0 << lc.logN), q,
-                                            (int)std::min<i64>(65535, T * 4 * K * K - v0), lc.geom, p->tb, s, gsc));
-        }
+    // forward NTTs; where the forward row pass is folded into the inverse
+    // row pass, only the column pass here.  The accumulation schedule of the
+    // class's transforms is computed inside the same launch.
+    const int which = fused_rows_ok(lc.geom, K) ? 1 : 0;
+    HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, np, false, 0, 2 * np * K,
+                            lc.geom, p->tb, step_for(p, lc.logN), which, s, p->d_ts, p->d_kd, p->L));
+  }
+  for (auto& lc : p->classes) {
+    const int cnt = (int)lc.tids.size();
+    if (fused_cols_ok(lc.geom)) {
+      // rows (with the forward rows where possible); fused columns + CRT +
+      // recombination (for transforms that need the wide accumulator: the
+      // columns to the compact buffer, then the wide recombination)
+      HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, np, 0, 4 * K * K,
+                              lc.geom, p->tb, step_for(p, lc.logN), 1, s, fused_rows_ok(lc.geom, K)));
+      HIPCHK(launch_inv_cols_rec(p->G, p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, np, lc.geom, p->tb,
+                                 dir, io32_of(p), s));
+      HIPCHK(launch_recombine_wide(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir,
+                                   io32_of(p), s, np));
     } else {
-      HIPCHK(launch_mac3(p->X, p->G, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, K, lc.logN, s));
-      for (int q = 0; q < 3; ++q)
-        if ((rc = ntt_chunked(p->G + lc.g3_base + q * lc.g3_ps, lc.logN, q, T * 4 * K * K, true, lc.geom, p->tb, st,
-                              s, gs)))
-          return rc;
+      HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, np, 0, 4 * K * K,
+                              lc.geom, p->tb, step_for(p, lc.logN), 0, s, fused_rows_ok(lc.geom, K)));
+      HIPCHK(launch_recombine(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s,
+                              np));
     }
-    HIPCHK(launch_recombine3(p->G, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)T, lc.nmax, K, dir, io32_of(p),
-                             s));
   }
   return FFT_OZAKI_OK;
 }
@@ -760,7 +662,7 @@ static hipError_t set_io_node(fft_ozaki_plan_s* p, GraphEntry& g, const void* in
 
 static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
   for (auto& lc : p->classes)
-    if (p->primes == 2 && fused_rows_ok(lc.geom, p->K)) p->x_rows_pending = true;
+    if (fused_rows_ok(lc.geom, p->K)) p->x_rows_pending = true;
   for (size_t i = 0; i < p->graphs.size(); ++i) {
     GraphEntry& g = p->graphs[i];
     if (g.dir != dir) continue;
@@ -788,7 +690,7 @@ static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, 
   HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
   hipError_t le = launch_set_io(p->d_io, in, out, p->cap);
   int rc = le != hipSuccess ? fail(FFT_OZAKI_ERR_HIP, std::string("launch_set_io: ") + hipGetErrorString(le))
-                            : (p->primes == 3 ? enqueue_batched3(p, dir, p->cap) : enqueue_batched(p, dir, p->cap));
+                            : enqueue_batched(p, dir, p->cap);
   hipError_t ce = hipStreamEndCapture(p->cap, &graph);
   if (rc) {
     if (ce == hipSuccess) (void)hipGraphDestroy(graph);
@@ -820,6 +722,7 @@ static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, 
 
 static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
   const int K = p->K, SL = 2 * K * K;   // slots per output component
+  constexpr int np = 2;                 // the plain form serves two-modulus plans
   HIPCHK(launch_set_io(p->d_io, in, out, s));
   for (int t = 0; t < (int)p->td.size(); ++t) {
     const TDesc& d = p->td[t];
@@ -836,7 +739,7 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
     HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, io32_of(p), s));
     HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, tl, 1, K, s));
     for (int r = 0; r < K; ++r) {
-      HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, tl, 1, d.n, K, false, s));
+      HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, tl, 1, d.n, K, false, s, np));
       HIPCHK(launch_split_check(p->d_td, p->d_ts, tl, 1, K, s));
       int act[2];
       HIPCHK(hipMemcpyAsync(act, &p->d_ts[t].active, sizeof act, hipMemcpyDeviceToHost, s));
@@ -852,20 +755,20 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
       stage.reset(new Range("forward NTTs"));
       for (int part = 0; part < 2; ++part)
         for (int k = 0; k < hs.kx[part]; ++k)
-          for (int prime = 0; prime < 2; ++prime) {
-            const int vi = (part * K + k) * 2 + prime;
-            HIPCHK(launch_fwd_pipeline(p->X, p->d_td, p->d_ts, tl, 1, K, false, vi, vi + 1, g, p->tb, st, s));
+          for (int prime = 0; prime < np; ++prime) {
+            const int vi = (part * K + k) * np + prime;
+            HIPCHK(launch_fwd_pipeline(p->X, p->d_td, p->d_ts, tl, 1, K, np, false, vi, vi + 1, g, p->tb, st, s));
           }
       stage.reset(new Range("NTT-domain multiply-accumulate + inverse NTTs"));
       for (int tg = 0; tg < 2; ++tg)
         for (int gi = 0; gi < hs.ngroups[tg]; ++gi) {
           const int slot = tg * SL + gi;
-          HIPCHK(launch_inv_pipeline(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, tl, 1, K, slot, slot + 1, g, p->tb,
-                                     st, s));
+          HIPCHK(launch_inv_pipeline(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, tl, 1, K, np, slot, slot + 1, g,
+                                     p->tb, st, s));
         }
     }
     stage.reset(new Range("CRT + recombination + postmultiply"));
-    HIPCHK(launch_recombine(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, tl, 1, d.n, K, dir, io32_of(p), s));
+    HIPCHK(launch_recombine(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, tl, 1, d.n, K, dir, io32_of(p), s, np));
   }
   HIPCHK(hipStreamSynchronize(s));
   return FFT_OZAKI_OK;
@@ -877,7 +780,7 @@ static const char* const kStageNames[9] = {"", "stage 1: premultiply + split", "
                                             "stage 5: forward row pass", "stage 6: row pass (fused MAC)",
                                             "stage 7: column pass (fused CRT)", "stage 8: recombination"};
 static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
-  const int K = p->K, count = (int)p->td.size();
+  const int K = p->K, np = p->primes, count = (int)p->td.size();
   Range range(stage >= 1 && stage <= 8 ? kStageNames[stage] : "stage");
   // the plan's descriptor still holds the last execution's in / out
   const int dir = p->last_dir;
@@ -890,7 +793,8 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
       HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
       for (int r = 0; r < K; ++r) {
         for (auto& lc : p->classes)
-          HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s));
+          HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false,
+                                      s, np));
         HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
       }
       return FFT_OZAKI_OK;
@@ -906,23 +810,23 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
         const bool rows_folded = fused_rows_ok(g, K);   // the forward rows run inside stage 6
         if (stage == 5 && rows_folded) continue;
         const int which = stage == 3 ? (rows_folded ? 1 : 0) : stage - 3;
-        HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K, g, p->tb,
-                                step_for(p, lc.logN), which, s));
+        HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, np, false, 0, 2 * np * K, g,
+                                p->tb, step_for(p, lc.logN), which, s));
       }
       return FFT_OZAKI_OK;
     case 6:
       for (auto& lc : p->classes)
-        HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), K, 0,
+        HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, (int)lc.tids.size(), K, np, 0,
                                 4 * K * K, lc.geom, p->tb, step_for(p, lc.logN), 1, s, fused_rows_ok(lc.geom, K)));
       return FFT_OZAKI_OK;
     case 7:   // column pass (fused with CRT and recombination where the length allows)
       for (auto& lc : p->classes) {
         const int cnt = (int)lc.tids.size();
         if (fused_cols_ok(lc.geom))
-          HIPCHK(launch_inv_cols_rec(p->G, p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, lc.geom, p->tb,
-                                     dir, io32_of(p), s));
+          HIPCHK(launch_inv_cols_rec(p->G, p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, np, lc.geom,
+                                     p->tb, dir, io32_of(p), s));
         else
-          HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, 0, 4 * K * K,
+          HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, np, 0, 4 * K * K,
                                   lc.geom, p->tb, step_for(p, lc.logN), 2, s));
       }
       return FFT_OZAKI_OK;
@@ -931,10 +835,10 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
         const int cnt = (int)lc.tids.size();
         if (fused_cols_ok(lc.geom)) {
           HIPCHK(launch_recombine_wide(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir,
-                                       io32_of(p), s));
+                                       io32_of(p), s, np));
         } else {
           HIPCHK(launch_recombine(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p),
-                                  s));
+                                  s, np));
         }
       }
       return FFT_OZAKI_OK;
@@ -1188,16 +1092,14 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
   if (index < 0 || index >= (int64_t)plan->td.size()) return fail(FFT_OZAKI_ERR_INVALID, "index out of range");
   const TDesc& d = plan->td[index];
   const KernelHost& kh = plan->kernels[d.kd];
-  const int K = plan->K;
+  const int K = plan->K, np = plan->primes;
   const void* src = nullptr;
   size_t sz = 0;
-  if (plan->primes == 3 && stage >= 2 && stage <= 4)
-    return fail(FFT_OZAKI_ERR_UNSUPPORTED, "stages 2-4 are laid out for two moduli");
   switch (stage) {
     case 1: src = plan->xp + d.xp_off; sz = sizeof(double2) * (size_t)d.n; break;
-    case 2: src = plan->X + d.X_off; sz = 4 * ((size_t)(4 * K) << d.logN); break;
-    case 3: src = plan->Z + d.Z_off; sz = 4 * (size_t)(8 * K * K) * (size_t)d.zs; break;
-    case 4: src = kh.W; sz = 4 * ((size_t)(4 * K) << d.logN); break;
+    case 2: src = plan->X + d.X_off; sz = 4 * ((size_t)(2 * np * K) << d.logN); break;
+    case 3: src = plan->Z + d.Z_off; sz = 4 * (size_t)(4 * K * K * np) * (size_t)d.zs; break;
+    case 4: src = kh.W; sz = 4 * ((size_t)(2 * np * K) << d.logN); break;
     case 5: src = kh.chirp; sz = sizeof(double2) * (size_t)d.n; break;
     default: return fail(FFT_OZAKI_ERR_INVALID, "unknown stage");
   }
@@ -1213,8 +1115,8 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
     // complete the stored slice spectra with it (once per execution)
     for (auto& lc : plan->classes) {
       if (!fused_rows_ok(lc.geom, K)) continue;
-      HIPCHK(launch_fwd_stage(plan->X, plan->d_td, plan->d_ts, lc.d_tlist, (int)lc.tids.size(), K, false, 0, 4 * K,
-                              lc.geom, plan->tb, step_for(plan, lc.logN), 2, nullptr));
+      HIPCHK(launch_fwd_stage(plan->X, plan->d_td, plan->d_ts, lc.d_tlist, (int)lc.tids.size(), K, np, false, 0,
+                              2 * np * K, lc.geom, plan->tb, step_for(plan, lc.logN), 2, nullptr));
     }
     HIPCHK(hipDeviceSynchronize());
     plan->x_rows_pending = false;
@@ -1225,7 +1127,7 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
     for (auto& lc : plan->classes) {
       if (lc.logN != d.logN || !fused_cols_ok(lc.geom)) continue;
       HIPCHK(launch_inv_stage(plan->X, plan->G, plan->Z, plan->d_td, plan->d_ts, plan->d_kd, lc.d_tlist,
-                              (int)lc.tids.size(), K, 0, 4 * K * K, lc.geom, plan->tb, step_for(plan, lc.logN), 2,
+                              (int)lc.tids.size(), K, np, 0, 4 * K * K, lc.geom, plan->tb, step_for(plan, lc.logN), 2,
                               nullptr));
       HIPCHK(hipDeviceSynchronize());
     }
@@ -1239,7 +1141,6 @@ int fft_ozaki_profile_stage(fft_ozaki_plan_t plan, int stage, int reps, void* st
   g_err.clear();
   if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
   if (plan->mode != FFT_OZAKI_MODE_BATCHED) return fail(FFT_OZAKI_ERR_INVALID, "stage profiling needs the batched mode");
-  if (plan->primes != 2) return fail(FFT_OZAKI_ERR_UNSUPPORTED, "stage profiling covers two-modulus plans");
   if (!plan->last_in) return fail(FFT_OZAKI_ERR_INVALID, "execute the plan once before profiling");
   if (reps < 1) return fail(FFT_OZAKI_ERR_INVALID, "reps must be >= 1");
   for (int r = 0; r < reps; ++r) {

@@ -1,8 +1,9 @@
 // Garner CRT, exact recombination to binary64 and chirp postmultiply.
 //
 // For each output index k < n and each group g of the accumulation schedule
-// the two inverse-NTT residues are combined by Garner's formula (Sec. 3.3)
-//     z = z0 + ((z1 - z0) p0^{-1} mod p1) p0,  mapped to [-(P-1)/2, (P-1)/2],
+// the inverse-NTT residues are combined by Garner's formula (Sec. 3.3)
+//     z = z0 + ((z1 - z0) p0^{-1} mod p1) p0,  mapped to [-(P-1)/2, (P-1)/2]
+// (with a third modulus p2 the mixed-radix form adds p0 p1 h2, P = p0 p1 p2),
 // which is the exact signed integer value of the group's sum because at most
 // acc_limit products of magnitude <= n 4^alpha enter it and
 // acc_limit n 4^alpha <= (P-1)/2 (Sec. 4.2 / 4.4; the ImIm products enter Re y'
@@ -19,6 +20,8 @@ namespace fo {
 
 // Both outputs j, j + 1 of one component (j even; the compact rows are
 // padded to a multiple of four, so j + 1 is always a readable position).
+// Compact buffer: row (slot NP + prime) of zs words.
+template <int NP>
 __device__ void recombine_fast2(const u32* Zb, const TState& s, int tg, int SL, int zs, int j, double& r0,
                                 double& r1) {
   u32 a[NL_FAST], b[NL_FAST];
@@ -27,11 +30,16 @@ __device__ void recombine_fast2(const u32* Zb, const TState& s, int tg, int SL, 
   const int emin = s.emin[tg];
   for (int g = 0; g < s.ngroups[tg]; ++g) {
     const int slot = tg * SL + g;
-    const uint2 v0 = *reinterpret_cast<const uint2*>(Zb + (size_t)(slot * 2) * zs + j);
-    const uint2 v1 = *reinterpret_cast<const uint2*>(Zb + (size_t)(slot * 2 + 1) * zs + j);
+    u32 z0[NP], z1[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const uint2 v = *reinterpret_cast<const uint2*>(Zb + (size_t)(slot * NP + q) * zs + j);
+      z0[q] = v.x;
+      z1[q] = v.y;
+    }
     const int sh = s.groups[tg][g].e - emin;
-    limb_add(a, garner(v0.x, v1.x), sh);
-    limb_add(b, garner(v0.y, v1.y), sh);
+    limb_add_crt<NP>(a, z0, sh);
+    limb_add_crt<NP>(b, z1, sh);
   }
   u64 a64[W_FAST], b64[W_FAST];
 #pragma unroll
@@ -43,7 +51,7 @@ __device__ void recombine_fast2(const u32* Zb, const TState& s, int tg, int SL, 
   r1 = acc_round<W_FAST>(b64, emin);
 }
 
-template <int W>
+template <int NP, int W>
 __device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, int zs, int j) {
   u64 acc[W];
 #pragma unroll
@@ -51,9 +59,10 @@ __device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, 
   const int emin = s.emin[tg];
   for (int g = 0; g < s.ngroups[tg]; ++g) {
     const int slot = tg * SL + g;
-    const u32 z0 = Zb[(size_t)(slot * 2) * zs + j];
-    const u32 z1 = Zb[(size_t)(slot * 2 + 1) * zs + j];
-    acc_add<W>(acc, garner(z0, z1), s.groups[tg][g].e - emin);
+    u32 z[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) z[q] = Zb[(size_t)(slot * NP + q) * zs + j];
+    acc_add_crt<NP, W>(acc, z, s.groups[tg][g].e - emin);
   }
   return acc_round<W>(acc, emin);
 }
@@ -61,14 +70,14 @@ __device__ double recombine_one(const u32* Zb, const TState& s, int tg, int SL, 
 // WIDE = false: transforms whose exponent spans fit the fast accumulator (and
 // those with a status, which get NaN), two outputs per thread;
 // WIDE = true: the others, one output per thread.
-template <bool WIDE>
+template <bool WIDE, int NP>
 __global__ void k_recombine(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
                             const int* tlist, int K, int dir, int io32) {
   const int t = tlist[blockIdx.z];
   void* out = io->out;
   const TDesc& d = td[t];
   const TState& s = ts[t];
-  const bool wide0 = span_wide(s, 0), wide1 = span_wide(s, 1);
+  const bool wide0 = span_wide<NP>(s, 0), wide1 = span_wide<NP>(s, 1);
   if (WIDE != (!s.status && (wide0 || wide1))) return;
   const double2* ch = kd[d.kd].chirp;
   const int SL = 2 * K * K;                                   // slots per output component
@@ -80,8 +89,8 @@ __global__ void k_recombine(const u32* Z, const IoPtrs* io, const TDesc* td, con
         o0 = o1 = make_double2(__builtin_nan(""), __builtin_nan(""));
       } else {
         double pr0, pr1, pi0, pi1;
-        recombine_fast2(Zb, s, 0, SL, d.zs, j, pr0, pr1);
-        recombine_fast2(Zb, s, 1, SL, d.zs, j, pi0, pi1);
+        recombine_fast2<NP>(Zb, s, 0, SL, d.zs, j, pr0, pr1);
+        recombine_fast2<NP>(Zb, s, 1, SL, d.zs, j, pi0, pi1);
         o0 = finish(pr0, pi0, ch[j], dir, d.n);
         o1 = j + 1 < d.n ? finish(pr1, pi1, ch[j + 1], dir, d.n) : o0;
       }
@@ -91,34 +100,50 @@ __global__ void k_recombine(const u32* Z, const IoPtrs* io, const TDesc* td, con
     return;
   }
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
-    const double pr = wide0 ? recombine_one<W_WIDE>(Zb, s, 0, SL, d.zs, j) : recombine_one<W_FAST>(Zb, s, 0, SL, d.zs, j);
-    const double pi = wide1 ? recombine_one<W_WIDE>(Zb, s, 1, SL, d.zs, j) : recombine_one<W_FAST>(Zb, s, 1, SL, d.zs, j);
+    const double pr = wide0 ? recombine_one<NP, W_WIDE>(Zb, s, 0, SL, d.zs, j)
+                            : recombine_one<NP, W_FAST>(Zb, s, 0, SL, d.zs, j);
+    const double pi = wide1 ? recombine_one<NP, W_WIDE>(Zb, s, 1, SL, d.zs, j)
+                            : recombine_one<NP, W_FAST>(Zb, s, 1, SL, d.zs, j);
     put_out(out, d.io_off + j, finish(pr, pi, ch[j], dir, d.n), io32);
   }
 }
 
-hipError_t launch_recombine(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                            const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
+static int recombine_blocks(int nmax) {
   int b = (nmax + 255) / 256;
   if (b > 2048) b = 2048;
-  if (b < 1) b = 1;
-  const int b2 = (b + 1) / 2;      // two outputs per thread
-  hipLaunchKernelGGL(k_recombine<false>, dim3(b2, 1, count), dim3(256), 0, s, Z, io, td, ts, kd, tlist, K, dir, io32);
-  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, io, td, ts, kd, tlist, K, dir, io32);
+  return b < 1 ? 1 : b;
+}
+
+template <bool WIDE, int NP>
+static void launch_rec(int blocks, int count, hipStream_t s, const u32* Z, const IoPtrs* io, const TDesc* td,
+                       const TState* ts, const KernelDesc* kd, const int* tlist, int K, int dir, int io32) {
+  hipLaunchKernelGGL((k_recombine<WIDE, NP>), dim3(blocks, 1, count), dim3(256), 0, s, Z, io, td, ts, kd, tlist, K,
+                     dir, io32);
+}
+
+hipError_t launch_recombine(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
+                            const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s, int np) {
+  if (count <= 0) return hipSuccess;
+  if (np != 2 && np != 3) return hipErrorInvalidValue;
+  const int b = recombine_blocks(nmax), b2 = (b + 1) / 2;      // two outputs per thread in the fast kernel
+  if (np == 3) {
+    launch_rec<false, 3>(b2, count, s, Z, io, td, ts, kd, tlist, K, dir, io32);
+    launch_rec<true, 3>(b, count, s, Z, io, td, ts, kd, tlist, K, dir, io32);
+  } else {
+    launch_rec<false, 2>(b2, count, s, Z, io, td, ts, kd, tlist, K, dir, io32);
+    launch_rec<true, 2>(b, count, s, Z, io, td, ts, kd, tlist, K, dir, io32);
+  }
   return hipGetLastError();
 }
 
-}  // namespace fo
-
-namespace fo {
 hipError_t launch_recombine_wide(const u32* Z, const IoPtrs* io, const TDesc* td, const TState* ts, const KernelDesc* kd,
-                                 const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s) {
+                                 const int* tlist, int count, int nmax, int K, int dir, int io32, hipStream_t s,
+                                 int np) {
   if (count <= 0) return hipSuccess;
-  int b = (nmax + 255) / 256;
-  if (b > 2048) b = 2048;
-  if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_recombine<true>, dim3(b, 1, count), dim3(256), 0, s, Z, io, td, ts, kd, tlist, K, dir, io32);
+  if (np != 2 && np != 3) return hipErrorInvalidValue;
+  const int b = recombine_blocks(nmax);
+  if (np == 3) launch_rec<true, 3>(b, count, s, Z, io, td, ts, kd, tlist, K, dir, io32);
+  else launch_rec<true, 2>(b, count, s, Z, io, td, ts, kd, tlist, K, dir, io32);
   return hipGetLastError();
 }
 

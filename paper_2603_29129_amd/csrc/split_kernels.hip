@@ -326,12 +326,20 @@ hipError_t launch_split_plan(const TDesc* td, TState* ts, const KernelDesc* kd, 
   return hipGetLastError();
 }
 
+// Residue of u < 2^64 modulo p by Barrett's reduction with m = floor(2^64 / p):
+// q = floor(u m / 2^64) undershoots floor(u / p) by at most one, so
+// u - q p lies in [0, 2p).
+__device__ __forceinline__ u32 mod_barrett(u64 u, u32 p, u64 m) {
+  const u64 r = u - __umul64hi(u, m) * (u64)p;
+  return (u32)(r >= p ? r - p : r);
+}
+constexpr u64 BARRETT_P0 = ~0ull / P0, BARRETT_P1 = ~0ull / P1, BARRETT_P2 = ~0ull / P2;
+
 // blockIdx.y = part.  Slices k >= start are written, times 2^xsh[part], as
-// residues mod p0, p1 into X[(part*K + k)*2 + prime][.] (NP = 2), or mod p0,
-// p1, p2 into X[prime * xps + (part*K + k) N] (NP = 3); input slices go to
-// positions j < n (the
-// NTT treats the rest as zero), kernel slices are placed by ZeroPad+-
-// (positions j and N - j), or at j alone when N = n (cyclic embedding).
+// residues mod p0 .. p(NP-1) into X[((part*K + k)*NP + prime) N + j]; input
+// slices go to positions j < n (the NTT treats the rest as zero), kernel
+// slices are placed by ZeroPad+- (positions j and N - j), or at j alone when
+// N = n (cyclic embedding).
 template <int NP>
 __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts, const int* tlist, int K,
                                 bool kernel_mode) {
@@ -361,45 +369,35 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
       const double x = (r + sigma) - sigma;
       r = r - x;
       if (k >= start) {
-        if constexpr (NP == 2) {
         // x is a multiple of 2^(E - alpha) with |x| <= 2^E, so scaling x itself is
         // exact; the factor 2^(alpha - E + sh) alone can exceed the binary64 range
         // (E - alpha down to -1022, sh up to 2)
-        const int a = (int)ldexp(x, alpha - E + sh);   // |a| <= 2^(alpha + sh) <= 2^30 < p0, p1
-        const u32 r0 = a < 0 ? (u32)(a + (int)P0) : (u32)a;
-        const u32 r1 = a < 0 ? (u32)(a + (int)P1) : (u32)a;
-        u32* v0 = Xb + (((size_t)((part * K + k) * 2)) << d.logN);
-        u32* v1 = v0 + N;
-        v0[j] = r0;
-        v1[j] = r1;
-        if (kernel_mode && j > 0 && N != (size_t)d.n) {   // ZeroPad+- (no wrap when N = n: cyclic)
-          v0[N - j] = r0;
-          v1[N - j] = r1;
-        }
+        u32 res[NP];
+        if constexpr (NP == 2) {
+          const int a = (int)ldexp(x, alpha - E + sh);   // |a| <= 2^(alpha + sh) <= 2^30 < p0, p1
+          res[0] = a < 0 ? (u32)(a + (int)P0) : (u32)a;
+          res[1] = a < 0 ? (u32)(a + (int)P1) : (u32)a;
         } else {
-        // three moduli: |a| <= 2^alpha with alpha up to 45, kept in 64 bits
-        const long long a = (long long)ldexp(x, alpha - E + sh);   // exact, as above
-        const u32 r[3] = {(u32)(((a % (long long)P0) + P0) % P0), (u32)(((a % (long long)P1) + P1) % P1),
-                          (u32)(((a % (long long)P2) + P2) % P2)};
-        u32* v0 = Xb + (((size_t)(part * K + k)) << d.logN);
-        for (int q = 0; q < 3; ++q) {
-          u32* vq = v0 + q * d.xps;
-          vq[j] = r[q];
-          if (kernel_mode && j > 0 && N != (size_t)d.n) vq[N - j] = r[q];
+          // three moduli: |a| <= 2^alpha with alpha up to 46, reduced as |a|
+          // and negated
+          const long long a = (long long)ldexp(x, alpha - E + sh);
+          const u64 u = (u64)(a < 0 ? -a : a);
+          const u32 m0 = mod_barrett(u, P0, BARRETT_P0), m1 = mod_barrett(u, P1, BARRETT_P1),
+                    m2 = mod_barrett(u, P2, BARRETT_P2);
+          res[0] = a < 0 && m0 ? P0 - m0 : m0;
+          res[1] = a < 0 && m1 ? P1 - m1 : m1;
+          res[2] = a < 0 && m2 ? P2 - m2 : m2;
         }
+        u32* v0 = Xb + (((size_t)((part * K + k) * NP)) << d.logN);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          v0[q * N + j] = res[q];
+          if (kernel_mode && j > 0 && N != (size_t)d.n) v0[q * N + N - j] = res[q];   // ZeroPad+- (cyclic: no wrap)
         }
         const u64 rb = abs_bits(r);
         if (rb > mloc[k]) mloc[k] = rb;
       }
     }
-  }
-  if constexpr (NP == 3) {
-    // the standalone NTTs of the three-modulus path read whole vectors and
-    // transform them in place: clear the zero padding n <= j < N each time
-    if (!kernel_mode)
-      for (size_t j = (size_t)d.n + blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (size_t)gridDim.x * blockDim.x)
-        for (int k = start; k < kend; ++k)
-          for (int q = 0; q < 3; ++q) Xb[((size_t)(part * K + k) << d.logN) + q * d.xps + j] = 0u;
   }
   for (int k = start; k < kend && k + 1 < K; ++k) {
     const u64 m = block_max_u64(mloc[k]);
