@@ -510,7 +510,7 @@ def main():
     print(f"# single transform: {ms1:.3f} ms", file=sys.stderr, flush=True)
 
     # three CRT moduli (d = 3): K = 2 slices of alpha = 36 bits, same input
-    # and output type; the standalone NTTs run per length class and prime
+    # and output type, the same kernels with three primes per group
     plan3 = oz.Plan(n, B, mode="batched", primes=3)
     out3 = torch.empty_like(xd)
     for _ in range(args.warmup):
@@ -523,6 +523,8 @@ def main():
                     "value": round(flops / (ms3 * 1e-3) / 1e9, 2), "rel_l2_error": rel3, "max_rel_error": maxrel3,
                     "ntt_counts": {"forward_runtime": i3["forward_runtime"], "inverse": i3["inverse"],
                                    "forward_offline": i3["forward_offline"]}}
+    three_moduli["stages_ms"] = {st: round(time_events(torch, lambda k, st=st: plan3.profile_stage(st, k),
+                                                       args.stage_reps), 4) for st in (1, 2, 4, 5, 6, 7, 8)}
     plan3.close()
     # the same with L = 12: alpha = 35, a CRT bound of 14 products, 3 groups per component
     plan3b = oz.Plan(n, B, mode="batched", primes=3, L=12)

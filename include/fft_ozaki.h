@@ -127,8 +127,9 @@ enum {
  * split width then follows Sec. 4.2 with the product p0 p1 p2 (alpha = 36 at
  * n = 2^18, L = 3), so K = 2 slices of about 36 bits reach the binary64
  * accuracy that K = 3 needs with two moduli.  Three moduli: batched mode
- * only (FFT_OZAKI_ERR_UNSUPPORTED otherwise); group values reach 93 bits;
- * debug stages 2-4 and fft_ozaki_profile_stage are not available. */
+ * only (FFT_OZAKI_ERR_UNSUPPORTED otherwise); group values reach 93 bits and
+ * are rebuilt by Garner's mixed-radix form over the three moduli; the
+ * buffers hold the three primes' residues where two-modulus plans hold two. */
 typedef struct {
   int K;
   int L;
@@ -203,16 +204,17 @@ typedef struct {
 int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_transform_info* info);
 
 /* Test hook: copy an intermediate buffer of transform `index` of the last
- * execution to host memory (synchronises the device).  Stages:
+ * execution to host memory (synchronises the device).  P = the plan's CRT
+ * moduli (2 or 3).  Stages:
  *   1  x' = x (.) w                          double2[n]
- *   2  forward NTTs of the x' slices         uint32[2][K][2][N]  (part, slice, prime; NTT-domain order;
+ *   2  forward NTTs of the x' slices         uint32[2][K][P][N]  (part, slice, prime; NTT-domain order;
  *                                            part p's slices times 2^xsh[p], see fft_ozaki_transform_info)
- *   3  inverse NTT outputs per group         uint32[4*K*K][2][n4] (slot = component*2*K*K + group,
+ *   3  inverse NTT outputs per group         uint32[4*K*K][P][n4] (slot = component*2*K*K + group,
  *                                            component 0 = Re y', 1 = Im y'; prime;
  *                                            n4 = n rounded up to a multiple of 4, first n valid; where
  *                                            the batched form fuses the column pass with the CRT these
  *                                            are rebuilt from the stored row-pass output by the call)
- *   4  kernel NTTs times N^{-1}              uint32[2][K][2][N]
+ *   4  kernel NTTs times N^{-1}              uint32[2][K][P][N]
  *   5  chirp (cos, sin)                      double2[n]
  * `bytes` must be at least the stage size (FFT_OZAKI_ERR_INVALID otherwise);
  * the size is returned through *needed when not NULL. */

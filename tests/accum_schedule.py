@@ -102,11 +102,11 @@ def component_schedule(EX, EW, L: int, mode: str, limit: int, weights: bool = Fa
 
 
 def group_residues(tr, kp, group):
-    """Inverse-NTT residues (first n, both primes) of one group's signed,
-    weighted sum (members (c, s, t) or (c, s, t, shift))."""
+    """Inverse-NTT residues (first n, every prime of the kernel plan) of one
+    group's signed, weighted sum (members (c, s, t) or (c, s, t, shift))."""
     n, N = tr["n"], tr["N"]
     res = []
-    for ip, p in enumerate(nt.PRIMES):
+    for ip, p in enumerate(kp.primes):
         pu = np.uint64(p)
         acc = np.zeros(N, dtype=np.uint64)
         for m in group:

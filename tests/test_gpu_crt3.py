@@ -13,8 +13,8 @@ import workloads as wl
 from oracle import bluestein as bl
 from oracle import ntt as nt
 from oracle import ozaki as oz_or
-from tests.accum_schedule import acc_limit, component_schedule
-from tests.gpu_helpers import max_ulp
+from tests.accum_schedule import acc_limit, component_schedule, group_residues, part_shift
+from tests.gpu_helpers import max_ulp, ntt_domain_index
 
 pytestmark = pytest.mark.gpu
 ULP_TOL = 2
@@ -193,10 +193,10 @@ def test_autograd_three_moduli(torch_mod):
 
 
 def test_many_transforms_chunked_launches(torch_mod):
-    """5000 transforms of n = 16 with three moduli and K = 2: the inverse
-    NTTs cover 5000 x 16 = 80000 group vectors per prime, more than one
-    launch's 65535, so the selector numbers vectors across two launches.
-    Sampled transforms (both launches) bit-exact against the oracle."""
+    """5000 transforms of n = 16 with three moduli and K = 2 in one length
+    class: 80000 group vectors per prime, 30000 single-workgroup inverse
+    launches' worth of (transform, prime, component) work items in one grid.
+    Sampled transforms across the batch bit-exact against the oracle."""
     import paper_2603_29129_amd as oz
     torch = torch_mod
     n, B = 16, 5000
@@ -250,3 +250,52 @@ def test_k8_two_pass_three_moduli(torch_mod):
         tr = bl.forward_trace(x[b], 8, 3, kp)
         check_info(plan, b, tr, kp)
         assert max_ulp(y[b], tr["y"]) <= ULP_TOL, b
+
+
+@pytest.mark.parametrize("n,cyclic", [(100, False), (4096, True), (5000, False), (1 << 14, True)])
+def test_stages_three_moduli(torch_mod, n, cyclic):
+    """Intermediates of the three-modulus path bit for bit against the
+    oracle's (slice spectra [part][k][prime][N] times 2^xsh, kernel spectra
+    times N^-1, every group's inverse-NTT residues mod p0, p1, p2), for a
+    single-workgroup length, a padded length and two-pass lengths (the
+    pipelined row pass and the fused column pass)."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    K, L = 2, 3
+    x = wl.paper_phi(n, 1.0, seed=n + 3, batch=2)
+    plan = oz.Plan(n, 2, K=K, L=L, primes=3, cyclic=cyclic)
+    y = plan.forward(_gpu(torch, x)).cpu().numpy()
+    kp = kplan3(n, K, L, cyclic)
+    primes = kp.primes
+    assert len(primes) == 3
+    for b in range(2):
+        tr = bl.forward_trace(x[b], K, L, kp)
+        info = check_info(plan, b, tr, kp)
+        assert max_ulp(y[b], tr["y"]) <= ULP_TOL
+        N = tr["N"]
+        logN = N.bit_length() - 1
+        perm = ntt_domain_index(logN, info["ntt_log2N1"])
+        EX = [[E for _, E in tr["slices"][v]] for v in range(2)]
+        EW = [kp.exps(v) for v in range(2)]
+        limit = acc_limit(n, tr["alpha"], primes=3)
+        xsh = part_shift(EX, EW, limit, tr["alpha"])
+        assert info["xsh"] == xsh
+        X = plan.debug_dump(2, b).reshape(2, K, 3, N)
+        for part in range(2):
+            for k in range(len(tr["slices"][part])):
+                for ip, p in enumerate(primes):
+                    want = (tr["X"][part][k][ip] * np.uint64(1 << xsh[part])) % np.uint64(p)
+                    assert np.array_equal(X[part, k, ip].astype(np.uint64), want[perm]), (b, part, k, ip)
+        W = plan.debug_dump(4, b).reshape(2, K, 3, N)
+        for part in range(2):
+            for t in range(len(kp.slices[part])):
+                for ip, p in enumerate(primes):
+                    want = (kp.ntts[part][t][ip] * np.uint64(pow(N, -1, p))) % np.uint64(p)
+                    assert np.array_equal(W[part, t, ip].astype(np.uint64), want[perm]), (b, part, t, ip)
+        sched = component_schedule(EX, EW, L, "complex", limit, weights=True, alpha=tr["alpha"])
+        Z = plan.debug_dump(3, b).reshape(4 * K * K, 3, (n + 3) // 4 * 4)[:, :, :n]
+        for tg in range(2):
+            for g, grp in enumerate(sched[tg]):
+                want = group_residues(tr, kp, grp)
+                for ip in range(3):
+                    assert np.array_equal(Z[tg * 2 * K * K + g, ip].astype(np.uint64), want[ip]), (b, tg, g, ip)
