@@ -108,7 +108,14 @@ hipError_t launch_kernel_finish(u32* W, u32* Wq, int K, int np, int logN, hipStr
 
 // --- split / chirp / groups / recombination --------------------------------
 hipError_t launch_chirp(double2* chirp, int n, int* flag, hipStream_t s);
-hipError_t launch_reset(TState* ts, const int* tlist, int count, hipStream_t s);
+// Zeroes the per-execution state of the listed transforms; with io set it
+// also writes the execution's array pointers there.  reset_io_kernel is that
+// kernel: its node in a captured graph is the one whose pointer arguments
+// change per execution (grid: count workgroups of RESET_THREADS).
+constexpr int RESET_THREADS = 256;
+hipError_t launch_reset_io(TState* ts, const int* tlist, int count, IoPtrs* io, const void* in, void* out,
+                           hipStream_t s);
+const void* reset_io_kernel();
 // in / out of the transforms: complex128, or complex64 when io32 (binary32
 // target precision: inputs widened exactly, outputs rounded once).
 hipError_t launch_premul(const IoPtrs* io, double2* xp, const TDesc* td, const KernelDesc* kd,
@@ -132,8 +139,7 @@ hipError_t launch_recombine_wide(const u32* Z, const IoPtrs* io, const TDesc* td
                                  const KernelDesc* kd, const int* tlist, int count, int nmax, int K,
                                  int dir, int io32, hipStream_t s, int np);
 // Writes the execution's array pointers to the plan's descriptor (one
-// thread); set_io_kernel is that kernel, to find its node in a graph.
+// thread; the plain form's per-call write).
 hipError_t launch_set_io(IoPtrs* io, const void* in, void* out, hipStream_t s);
-const void* set_io_kernel();
 
 }  // namespace fo

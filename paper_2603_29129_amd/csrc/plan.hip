@@ -434,7 +434,7 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   HIPCHK(hipMemcpy(kd, &hk, sizeof hk, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(tl, &zero, sizeof zero, hipMemcpyHostToDevice));
   HIPCHK(launch_chirp(kh.chirp, (int)n, flag, nullptr));
-  HIPCHK(launch_reset(ts, tl, 1, nullptr));
+  HIPCHK(launch_reset_io(ts, tl, 1, nullptr, nullptr, nullptr, nullptr));
   HIPCHK(launch_premul(nullptr, xp, td, kd, ts, tl, 1, (int)n, 0, true, 0, nullptr));
   HIPCHK(launch_split_plan(td, ts, kd, tl, 1, K, nullptr));
   for (int r = 0; r < K; ++r) {
@@ -598,9 +598,9 @@ static inline int io32_of(const fft_ozaki_plan_s* p) { return p->precision == FF
 
 // The batched launch sequence (also what gets captured into the graph), for
 // two or three moduli alike.
-static int enqueue_batched(fft_ozaki_plan_s* p, int dir, hipStream_t s) {
+static int enqueue_batched(fft_ozaki_plan_s* p, int dir, hipStream_t s, const void* in, void* out) {
   const int K = p->K, np = p->primes, count = (int)p->td.size();
-  HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
+  HIPCHK(launch_reset_io(p->d_ts, p->d_tall, count, p->d_io, in, out, s));
   for (auto& lc : p->classes)
     HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
                          io32_of(p), s));
@@ -643,12 +643,14 @@ static int enqueue_batched(fft_ozaki_plan_s* p, int dir, hipStream_t s) {
 
 // Arguments of the descriptor-writing node for (in, out).
 static hipError_t set_io_node(fft_ozaki_plan_s* p, GraphEntry& g, const void* in, void* out) {
+  TState* ts = p->d_ts;
+  const int* tl = p->d_tall;
   IoPtrs* io = p->d_io;
-  void* args[3] = {&io, &in, &out};
+  void* args[5] = {&ts, &tl, &io, &in, &out};
   hipKernelNodeParams kp{};
-  kp.func = const_cast<void*>(set_io_kernel());
-  kp.gridDim = dim3(1);
-  kp.blockDim = dim3(1);
+  kp.func = const_cast<void*>(reset_io_kernel());
+  kp.gridDim = dim3((unsigned)p->td.size());
+  kp.blockDim = dim3(RESET_THREADS);
   kp.sharedMemBytes = 0;
   kp.kernelParams = args;
   kp.extra = nullptr;
@@ -688,16 +690,14 @@ static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, 
   (void)hipEventDestroy(ev);
   hipGraph_t graph;
   HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-  hipError_t le = launch_set_io(p->d_io, in, out, p->cap);
-  int rc = le != hipSuccess ? fail(FFT_OZAKI_ERR_HIP, std::string("launch_set_io: ") + hipGetErrorString(le))
-                            : enqueue_batched(p, dir, p->cap);
+  int rc = enqueue_batched(p, dir, p->cap, in, out);
   hipError_t ce = hipStreamEndCapture(p->cap, &graph);
   if (rc) {
     if (ce == hipSuccess) (void)hipGraphDestroy(graph);
     return rc;
   }
   if (ce != hipSuccess) return fail(FFT_OZAKI_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
-  // the descriptor-writing node: the graph's only launch of that kernel
+  // the descriptor-writing node: the graph's only launch of the reset kernel
   GraphEntry g{dir, graph, nullptr, nullptr, in, out};
   size_t nn = 0;
   HIPCHK(hipGraphGetNodes(graph, nullptr, &nn));
@@ -707,7 +707,7 @@ static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, 
     hipGraphNodeType ty;
     if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
     hipKernelNodeParams kp{};
-    if (hipGraphKernelNodeGetParams(nd, &kp) == hipSuccess && kp.func == set_io_kernel()) g.io_node = nd;
+    if (hipGraphKernelNodeGetParams(nd, &kp) == hipSuccess && kp.func == reset_io_kernel()) g.io_node = nd;
   }
   if (!g.io_node) {
     (void)hipGraphDestroy(graph);
@@ -735,7 +735,7 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
     const TwStep& st = step_for(p, d.logN);
     Range rt("transform");
     std::unique_ptr<Range> stage(new Range("premultiply + split"));
-    HIPCHK(launch_reset(p->d_ts, tl, 1, s));
+    HIPCHK(launch_reset_io(p->d_ts, tl, 1, nullptr, nullptr, nullptr, s));
     HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, io32_of(p), s));
     HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, tl, 1, K, s));
     for (int r = 0; r < K; ++r) {
@@ -786,7 +786,7 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
   const int dir = p->last_dir;
   switch (stage) {
     case 1:   // split: premultiply, maxima and the K extraction/check passes
-      HIPCHK(launch_reset(p->d_ts, p->d_tall, count, s));
+      HIPCHK(launch_reset_io(p->d_ts, p->d_tall, count, nullptr, nullptr, nullptr, s));
       for (auto& lc : p->classes)
         HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
                          io32_of(p), s));
@@ -1256,8 +1256,7 @@ int fft_ozaki_execute_static(int64_t n, int64_t batch, const void* in, void* out
     }
     sl.plan = p;
   }
-  HIPCHK(launch_set_io(p->d_io, in, out, s));
-  return enqueue_batched(p, direction, s);
+  return enqueue_batched(p, direction, s, in, out);
 }
 
 }  // extern "C"

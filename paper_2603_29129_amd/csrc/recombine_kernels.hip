@@ -157,5 +157,4 @@ hipError_t launch_set_io(IoPtrs* io, const void* in, void* out, hipStream_t s) {
   hipLaunchKernelGGL(k_set_io, dim3(1), dim3(1), 0, s, io, in, out);
   return hipGetLastError();
 }
-const void* set_io_kernel() { return reinterpret_cast<const void*>(&k_set_io); }
 }  // namespace fo

@@ -151,19 +151,27 @@ hipError_t launch_chirp(double2* chirp, int n, int* flag, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-execution state reset.
+// Per-execution state reset; with io set the first workgroup also writes the
+// execution's array pointers (a kernel, so that the write is an ordinary
+// stream operation, also inside captured graphs).
 
-__global__ void k_reset(TState* ts, const int* tlist) {
+__global__ void k_reset_io(TState* ts, const int* tlist, IoPtrs* io, const void* in, void* out) {
   const int t = tlist[blockIdx.x];
   u32* w = reinterpret_cast<u32*>(ts + t);
   for (int i = threadIdx.x; i < (int)(sizeof(TState) / 4); i += blockDim.x) w[i] = 0u;
+  if (io && blockIdx.x == 0 && threadIdx.x == 0) {
+    io->in = in;
+    io->out = out;
+  }
 }
 
-hipError_t launch_reset(TState* ts, const int* tlist, int count, hipStream_t s) {
+hipError_t launch_reset_io(TState* ts, const int* tlist, int count, IoPtrs* io, const void* in, void* out,
+                           hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reset, dim3(count), dim3(256), 0, s, ts, tlist);
+  hipLaunchKernelGGL(k_reset_io, dim3(count), dim3(RESET_THREADS), 0, s, ts, tlist, io, in, out);
   return hipGetLastError();
 }
+const void* reset_io_kernel() { return reinterpret_cast<const void*>(&k_reset_io); }
 
 // ---------------------------------------------------------------------------
 // Premultiply x' = x (.) w (Sec. 3.2 Step 1) and mu_0 = max |x'| per part.
