@@ -206,7 +206,9 @@ int fft_ozaki_query_transform(fft_ozaki_plan_t plan, int64_t index, fft_ozaki_tr
 /* Test hook: copy an intermediate buffer of transform `index` of the last
  * execution to host memory (synchronises the device).  P = the plan's CRT
  * moduli (2 or 3).  Stages:
- *   1  x' = x (.) w                          double2[n]
+ *   1  x' = x (.) w                          double2[n]  (not kept by the execution: rebuilt from its
+ *                                            input, which must still hold the same values;
+ *                                            FFT_OZAKI_ERR_UNSUPPORTED after an in-place execution)
  *   2  forward NTTs of the x' slices         uint32[2][K][P][N]  (part, slice, prime; NTT-domain order;
  *                                            part p's slices times 2^xsh[p], see fft_ozaki_transform_info)
  *   3  inverse NTT outputs per group         uint32[4*K*K][P][n4] (slot = component*2*K*K + group,

@@ -118,14 +118,18 @@ hipError_t launch_reset_io(TState* ts, const int* tlist, int count, IoPtrs* io, 
 const void* reset_io_kernel();
 // in / out of the transforms: complex128, or complex64 when io32 (binary32
 // target precision: inputs widened exactly, outputs rounded once).
+// x' = x (.) w is recomputed from the input by every pass that needs it:
+// launch_premul with xp == nullptr takes the per-part maxima (the
+// execution), otherwise it writes x' to xp (at each transform's xp_off)
+// and takes no maxima (the debug copy).
 hipError_t launch_premul(const IoPtrs* io, double2* xp, const TDesc* td, const KernelDesc* kd,
                          TState* ts, const int* tlist, int count, int nmax, int dir, bool kernel_mode,
                          int io32, hipStream_t s);
 hipError_t launch_split_plan(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist, int count, int K,
                              hipStream_t s);
-hipError_t launch_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts,
-                                const int* tlist, int count, int nmax, int K, bool kernel_mode,
-                                hipStream_t s, int np);
+hipError_t launch_split_extract(const IoPtrs* io, const KernelDesc* kd, u32* X, const TDesc* td, TState* ts,
+                                const int* tlist, int count, int nmax, int K, int dir, bool kernel_mode, int io32,
+                                int np, hipStream_t s);
 hipError_t launch_split_check(const TDesc* td, TState* ts, const int* tlist, int count, int K,
                               hipStream_t s);
 hipError_t launch_groups(const TDesc* td, TState* ts, const KernelDesc* kd, const int* tlist,

@@ -168,7 +168,7 @@ struct fft_ozaki_plan_s {
   fo::KernelDesc* d_kd = nullptr;
   fo::TState* d_ts = nullptr;
   int* d_tall = nullptr;
-  double2* xp = nullptr;
+  double2* xp = nullptr;            // x' of the transforms, filled only by the debug copy (stage 1)
   fo::u32* X = nullptr;
   fo::u32* G = nullptr;
   fo::u32* Z = nullptr;
@@ -388,7 +388,6 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   // temporaries of the kernel split (freed at the end; carved and left in
   // place with an arena)
   int* flag = nullptr;
-  double2* xp = nullptr;
   TState* ts = nullptr;
   TDesc* td = nullptr;
   KernelDesc* kd = nullptr;
@@ -412,7 +411,7 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
       for (void* a : v) (void)hipFree(a);
     }
   } free_temps{temps};
-  if ((rc = tmalloc((void**)&flag, sizeof(int))) || (rc = tmalloc((void**)&xp, sizeof(double2) * n)) ||
+  if ((rc = tmalloc((void**)&flag, sizeof(int))) ||
       (rc = tmalloc((void**)&ts, sizeof(TState))) || (rc = tmalloc((void**)&td, sizeof(TDesc))) ||
       (rc = tmalloc((void**)&kd, sizeof(KernelDesc))) || (rc = tmalloc((void**)&tl, sizeof(int))))
     return rc;
@@ -435,10 +434,10 @@ static int prepare_kernel(fft_ozaki_plan_s* p, KernelHost& kh, int idx) {
   HIPCHK(hipMemcpy(tl, &zero, sizeof zero, hipMemcpyHostToDevice));
   HIPCHK(launch_chirp(kh.chirp, (int)n, flag, nullptr));
   HIPCHK(launch_reset_io(ts, tl, 1, nullptr, nullptr, nullptr, nullptr));
-  HIPCHK(launch_premul(nullptr, xp, td, kd, ts, tl, 1, (int)n, 0, true, 0, nullptr));
+  HIPCHK(launch_premul(nullptr, nullptr, td, kd, ts, tl, 1, (int)n, 0, true, 0, nullptr));
   HIPCHK(launch_split_plan(td, ts, kd, tl, 1, K, nullptr));
   for (int r = 0; r < K; ++r) {
-    HIPCHK(launch_split_extract(xp, kh.W, td, ts, tl, 1, (int)n, K, true, nullptr, np));
+    HIPCHK(launch_split_extract(nullptr, kd, kh.W, td, ts, tl, 1, (int)n, K, 0, true, 0, np, nullptr));
     HIPCHK(launch_split_check(td, ts, tl, 1, K, nullptr));
   }
   TState hs;
@@ -544,7 +543,6 @@ static int build_plan(fft_ozaki_plan_s* p) {
   for (auto& lc : p->classes)
     if (lc.tids.size() > 65535) return fail(FFT_OZAKI_ERR_INVALID, "more than 65535 transforms share one convolution length");
   int rc;
-  if ((rc = dmalloc(p, (void**)&p->xp, sizeof(double2) * (size_t)io))) return rc;
   if ((rc = dmalloc(p, (void**)&p->X, 4 * (size_t)xo))) return rc;
   if ((rc = dmalloc(p, (void**)&p->G, 4 * (size_t)go))) return rc;
   if ((rc = dmalloc(p, (void**)&p->Z, 4 * (size_t)zo))) return rc;
@@ -602,13 +600,13 @@ static int enqueue_batched(fft_ozaki_plan_s* p, int dir, hipStream_t s, const vo
   const int K = p->K, np = p->primes, count = (int)p->td.size();
   HIPCHK(launch_reset_io(p->d_ts, p->d_tall, count, p->d_io, in, out, s));
   for (auto& lc : p->classes)
-    HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
-                         io32_of(p), s));
+    HIPCHK(launch_premul(p->d_io, nullptr, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir,
+                         false, io32_of(p), s));
   HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
   for (int r = 0; r < K; ++r) {
     for (auto& lc : p->classes)
-      HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false, s,
-                                  np));
+      HIPCHK(launch_split_extract(p->d_io, p->d_kd, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K,
+                                  dir, false, io32_of(p), np, s));
     HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
   }
   for (auto& lc : p->classes) {
@@ -736,10 +734,11 @@ static int run_plain(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hi
     Range rt("transform");
     std::unique_ptr<Range> stage(new Range("premultiply + split"));
     HIPCHK(launch_reset_io(p->d_ts, tl, 1, nullptr, nullptr, nullptr, s));
-    HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, io32_of(p), s));
+    HIPCHK(launch_premul(p->d_io, nullptr, p->d_td, p->d_kd, p->d_ts, tl, 1, d.n, dir, false, io32_of(p), s));
     HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, tl, 1, K, s));
     for (int r = 0; r < K; ++r) {
-      HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, tl, 1, d.n, K, false, s, np));
+      HIPCHK(launch_split_extract(p->d_io, p->d_kd, p->X, p->d_td, p->d_ts, tl, 1, d.n, K, dir, false, io32_of(p), np,
+                                  s));
       HIPCHK(launch_split_check(p->d_td, p->d_ts, tl, 1, K, s));
       int act[2];
       HIPCHK(hipMemcpyAsync(act, &p->d_ts[t].active, sizeof act, hipMemcpyDeviceToHost, s));
@@ -788,13 +787,13 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
     case 1:   // split: premultiply, maxima and the K extraction/check passes
       HIPCHK(launch_reset_io(p->d_ts, p->d_tall, count, nullptr, nullptr, nullptr, s));
       for (auto& lc : p->classes)
-        HIPCHK(launch_premul(p->d_io, p->xp, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir, false,
-                         io32_of(p), s));
+        HIPCHK(launch_premul(p->d_io, nullptr, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir,
+                             false, io32_of(p), s));
       HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
       for (int r = 0; r < K; ++r) {
         for (auto& lc : p->classes)
-          HIPCHK(launch_split_extract(p->xp, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K, false,
-                                      s, np));
+          HIPCHK(launch_split_extract(p->d_io, p->d_kd, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(),
+                                      lc.nmax, K, dir, false, io32_of(p), np, s));
         HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
       }
       return FFT_OZAKI_OK;
@@ -884,13 +883,11 @@ static size_t static_bytes(i64 n, i64 batch) {
   add(4 * (size_t)(2 * np * K) * N);                       // W
   add(4 * (size_t)(2 * np * K) * N);                       // Wq
   add(sizeof(int));                                        // split temporaries
-  add(sizeof(double2) * (size_t)n);
   add(sizeof(TState));
   add(sizeof(TDesc));
   add(sizeof(KernelDesc));
   add(sizeof(int));
   const size_t SL = (size_t)K * K, zs = (size_t)((n + 3) & ~(i64)3);
-  add(sizeof(double2) * (size_t)n * B);                    // x'
   add(4 * ((size_t)(4 * K) << logN) * B);                  // slice spectra
   add(two ? 4 * ((8 * SL) << logN) * B : 0);               // group rows
   add(4 * 8 * SL * zs * B);                                // compact outputs
@@ -899,6 +896,7 @@ static size_t static_bytes(i64 n, i64 batch) {
   add(sizeof(int) * B);
   add(sizeof(KernelDesc));
   add(sizeof(int) * B);                                    // the class's transform list
+  add(sizeof(IoPtrs));                                     // execution descriptor
   return b;
 }
 
@@ -1096,7 +1094,7 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
   const void* src = nullptr;
   size_t sz = 0;
   switch (stage) {
-    case 1: src = plan->xp + d.xp_off; sz = sizeof(double2) * (size_t)d.n; break;
+    case 1: sz = sizeof(double2) * (size_t)d.n; break;   // recomputed below
     case 2: src = plan->X + d.X_off; sz = 4 * ((size_t)(2 * np * K) << d.logN); break;
     case 3: src = plan->Z + d.Z_off; sz = 4 * (size_t)(4 * K * K * np) * (size_t)d.zs; break;
     case 4: src = kh.W; sz = 4 * ((size_t)(2 * np * K) << d.logN); break;
@@ -1110,6 +1108,24 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
   HIPCHK(hipGetDevice(&cur));
   HIPCHK(hipSetDevice(plan->device));
   HIPCHK(hipDeviceSynchronize());
+  if (stage == 1) {
+    // x' is not kept by the execution: recompute it from the last
+    // execution's input, which must still hold the same values
+    if (!plan->last_in) return fail(FFT_OZAKI_ERR_INVALID, "no execution to copy x' from");
+    if (plan->last_in == plan->last_out)
+      return fail(FFT_OZAKI_ERR_UNSUPPORTED, "x' is rebuilt from the input, which the in-place execution overwrote");
+    if (!plan->xp) {     // a test hook's buffer: not part of the execution's workspace
+      const hipError_t e = hipMalloc((void**)&plan->xp, sizeof(double2) * (size_t)plan->total);
+      if (e != hipSuccess) return fail(FFT_OZAKI_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      plan->allocs.push_back(plan->xp);
+    }
+    int nmax = 0;
+    for (const TDesc& e : plan->td) nmax = std::max(nmax, e.n);
+    HIPCHK(launch_premul(plan->d_io, plan->xp, plan->d_td, plan->d_kd, plan->d_ts, plan->d_tall, (int)plan->td.size(),
+                         nmax, plan->last_dir, false, io32_of(plan), nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    src = plan->xp + d.xp_off;
+  }
   if (stage == 2 && plan->mode == FFT_OZAKI_MODE_BATCHED && plan->x_rows_pending) {
     // the batched form folds the forward row pass into the inverse row pass;
     // complete the stored slice spectra with it (once per execution)

@@ -202,6 +202,28 @@ __device__ __forceinline__ u64 block_max_u64(u64 v) {
   return m;
 }
 
+// x'(j) of transform d: the input element times the chirp, or the kernel
+// w* = (c, s) itself (kernel_mode).  The premultiply and every extraction
+// pass compute it here, with the same binary64 operations, instead of
+// keeping x' in memory.
+__device__ __forceinline__ double2 xprime(const void* in, const TDesc& d, const double2* ch, int j, int dir,
+                                          bool kernel_mode, int io32) {
+  const double2 w = ch[j];
+  if (kernel_mode) return w;
+  double2 x;
+  if (io32) {                       // binary32 input: widened exactly
+    const float2 f = reinterpret_cast<const float2*>(in)[d.io_off + j];
+    x = make_double2((double)f.x, (double)f.y);
+  } else {
+    x = reinterpret_cast<const double2*>(in)[d.io_off + j];
+  }
+  const double xr = x.x, xi = dir ? -x.y : x.y;
+  return make_double2(xr * w.x + xi * w.y,      // RN(RN(xr c) + RN(xi s))
+                      xi * w.x - xr * w.y);     // RN(RN(xi c) - RN(xr s))
+}
+
+// xp == nullptr: the maxima only (the execution); otherwise x' written to
+// xp and no maxima (the debug copy).
 __global__ void k_premul(const IoPtrs* io, double2* xp, const TDesc* td, const KernelDesc* kd, TState* ts,
                          const int* tlist, int dir, bool kernel_mode, int io32) {
   const int t = tlist[blockIdx.z];
@@ -211,28 +233,16 @@ __global__ void k_premul(const IoPtrs* io, double2* xp, const TDesc* td, const K
   u64 m0 = 0, m1 = 0;
 #pragma unroll 4
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
-    double re, im;
-    const double2 w = ch[j];
-    if (kernel_mode) {
-      re = w.x;
-      im = w.y;
-    } else {
-      double2 x;
-      if (io32) {                     // binary32 input: widened exactly
-        const float2 f = reinterpret_cast<const float2*>(in)[d.io_off + j];
-        x = make_double2((double)f.x, (double)f.y);
-      } else {
-        x = reinterpret_cast<const double2*>(in)[d.io_off + j];
-      }
-      const double xr = x.x, xi = dir ? -x.y : x.y;
-      re = xr * w.x + xi * w.y;       // RN(RN(xr c) + RN(xi s))
-      im = xi * w.x - xr * w.y;       // RN(RN(xi c) - RN(xr s))
+    const double2 v = xprime(in, d, ch, j, dir, kernel_mode, io32);
+    if (xp) {
+      xp[d.xp_off + j] = v;
+      continue;
     }
-    xp[d.xp_off + j] = make_double2(re, im);
-    const u64 a = abs_bits(re), b = abs_bits(im);
+    const u64 a = abs_bits(v.x), b = abs_bits(v.y);
     m0 = a > m0 ? a : m0;
     m1 = b > m1 ? b : m1;
   }
+  if (xp) return;
   m0 = block_max_u64(m0);
   m1 = block_max_u64(m1);
   if (threadIdx.x == 0) {
@@ -349,13 +359,15 @@ constexpr u64 BARRETT_P0 = ~0ull / P0, BARRETT_P1 = ~0ull / P1, BARRETT_P2 = ~0u
 // slices are placed by ZeroPad+- (positions j and N - j), or at j alone when
 // N = n (cyclic embedding).
 template <int NP>
-__global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts, const int* tlist, int K,
-                                bool kernel_mode) {
+__global__ void k_split_extract(const IoPtrs* io, const KernelDesc* kd, u32* X, const TDesc* td, TState* ts,
+                                const int* tlist, int K, int dir, bool kernel_mode, int io32) {
   const int t = tlist[blockIdx.z];
   const int part = blockIdx.y;
   TState& s = ts[t];
   if (!s.active[part]) return;
   const TDesc& d = td[t];
+  const void* in = kernel_mode ? nullptr : io->in;
+  const double2* ch = kd[d.kd].chirp;
   const int alpha = d.alpha, start = s.start[part], sh = s.xsh[part];
   int Ek[KMAX];
   int kend = K;
@@ -369,7 +381,7 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
   const size_t N = (size_t)1 << d.logN;
 #pragma unroll 4
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
-    const double2 v = xp[d.xp_off + j];
+    const double2 v = xprime(in, d, ch, j, dir, kernel_mode, io32);
     double r = part ? v.y : v.x;
     for (int k = 0; k < kend; ++k) {
       const int E = Ek[k];
@@ -413,15 +425,16 @@ __global__ void k_split_extract(const double2* xp, u32* X, const TDesc* td, TSta
   }
 }
 
-hipError_t launch_split_extract(const double2* xp, u32* X, const TDesc* td, TState* ts, const int* tlist, int count,
-                                int nmax, int K, bool kernel_mode, hipStream_t s, int np) {
+hipError_t launch_split_extract(const IoPtrs* io, const KernelDesc* kd, u32* X, const TDesc* td, TState* ts,
+                                const int* tlist, int count, int nmax, int K, int dir, bool kernel_mode, int io32,
+                                int np, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (np == 3)
-    hipLaunchKernelGGL(k_split_extract<3>, dim3(chunks_for(nmax), 2, count), dim3(256), 0, s, xp, X, td, ts, tlist, K,
-                       kernel_mode);
+    hipLaunchKernelGGL(k_split_extract<3>, dim3(chunks_for(nmax), 2, count), dim3(256), 0, s, io, kd, X, td, ts, tlist,
+                       K, dir, kernel_mode, io32);
   else
-    hipLaunchKernelGGL(k_split_extract<2>, dim3(chunks_for(nmax), 2, count), dim3(256), 0, s, xp, X, td, ts, tlist, K,
-                       kernel_mode);
+    hipLaunchKernelGGL(k_split_extract<2>, dim3(chunks_for(nmax), 2, count), dim3(256), 0, s, io, kd, X, td, ts, tlist,
+                       K, dir, kernel_mode, io32);
   return hipGetLastError();
 }
 

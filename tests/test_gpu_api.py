@@ -19,8 +19,10 @@ def torch_mod():
 @pytest.mark.parametrize("mode", ["batched", "plain"])
 @pytest.mark.parametrize("n", [1000, 1 << 14])
 def test_in_place_equals_out_of_place(torch_mod, mode, n):
-    """in == out is allowed: each input is consumed by the premultiply before
-    any output is written."""
+    """in == out is allowed: each input is consumed by the split (the
+    premultiply and the extraction passes, which recompute x' from it)
+    before any output is written.  The debug copy of x' rebuilds it from the
+    input and so is refused after an in-place execution."""
     import paper_2603_29129_amd as oz
     torch = torch_mod
     x = torch.from_numpy(wl.uniform(n, batch=3, seed=8)).cuda()
@@ -29,6 +31,8 @@ def test_in_place_equals_out_of_place(torch_mod, mode, n):
     buf = x.clone()
     plan.forward(buf, out=buf)
     assert torch.equal(buf.view(torch.float64), ref.view(torch.float64))
+    with pytest.raises(oz.FftOzakiError, match="in-place"):
+        plan.debug_dump(1, 0)
     back = buf.clone()
     plan.inverse(back, out=back)
     assert torch.equal(back.view(torch.float64), plan.inverse(ref).view(torch.float64))
