@@ -68,22 +68,19 @@ def folded_rows(info, K):
     return logN > 12 and K <= 3 and m2 + li == 9
 
 
-def stage_kernels(info, K):
+def stage_kernels(info, K, primes=2):
     """Kernel launched by each pass stage (one launch per stage for a uniform
-    batch), by the name rocprofv3 reports (None: the stage launches nothing)."""
+    batch) of a batched plan, by the name rocprofv3 reports (None: the stage
+    launches nothing)."""
     logN, m1 = info["N"].bit_length() - 1, info["ntt_log2N1"]
     m2 = logN - m1
-    li = min(max(9 - m2, 0), m1)
-    if K <= 3 and m2 + li == 9:
-        # the folded row pass runs as the persistent pipelined kernel
-        rows = f"k_inv_rows_pipe<{m2}>" if folded_rows(info, K) else f"k_inv_rows_reg<{m2}, false>"
-    else:
-        rows = f"k_inv_rows<{m2}>"
+    # the folded row pass runs as the persistent pipelined kernel
+    rows = f"k_inv_rows_pipe<{m2}, {primes}>" if folded_rows(info, K) else f"k_inv_rows<{m2}>"
     out = {4: f"k_fwd_cols<{m1}>", 5: None if folded_rows(info, K) else f"k_fwd_rows<{m2}>", 6: rows}
     if fused_columns(info):
-        out.update({7: f"k_inv_cols_rec<{m1}>", 8: "k_recombine<true>"})
+        out.update({7: f"k_inv_cols_rec<{m1}, {primes}>", 8: f"k_recombine<true, {primes}>"})
     else:
-        out.update({7: f"k_inv_cols<{m1}>", 8: "k_recombine<false>"})
+        out.update({7: f"k_inv_cols<{m1}>", 8: f"k_recombine<false, {primes}>"})
     return out
 
 
