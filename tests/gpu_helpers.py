@@ -44,3 +44,43 @@ def ntt_domain_index(logN, log2N1):
     i1 = pos >> m2
     i2 = pos & ((1 << m2) - 1)
     return bitrev(i1, m1) + (bitrev(i2, m2) << m1)
+
+
+# The oracle over a pool of processes (one transform per task), for parity
+# checks at sizes where one process would take minutes.  Spawned workers
+# (the parent holds a GPU context); the kernel plan is sent once per worker.
+_POOL_PLAN = None
+
+
+def _pool_init(plan):
+    global _POOL_PLAN
+    _POOL_PLAN = plan
+
+
+def _pool_fft(args):
+    from oracle import bluestein as bl
+    x, K, L = args
+    return bl.fft(x, K, L, _POOL_PLAN)
+
+
+def oracle_ffts(xs, K, L, plan, procs=8):
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(procs, len(xs)), initializer=_pool_init, initargs=(plan,)) as pool:
+        return pool.map_async(_pool_fft, [(x, K, L) for x in xs], chunksize=1).get(timeout=600)
+
+
+def _own_plan_fft(args):
+    from oracle import bluestein as bl
+    x, K, L = args
+    n = len(x)
+    return bl.fft(x, K, L, bl.KernelPlan(n, K, L, cyclic=bl.is_pow2(n)))
+
+
+def oracle_ffts_own_plans(xs, K, L, procs=16):
+    """The oracle for vectors of different lengths, each worker building the
+    kernel plan of the length it is given."""
+    import multiprocessing as mp
+    import os
+    procs = max(1, min(procs, len(xs), os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(procs) as pool:
+        return pool.map_async(_own_plan_fft, [(x, K, L) for x in xs], chunksize=1).get(timeout=900)

@@ -13,7 +13,7 @@ import pytest
 import workloads as wl
 from oracle import bluestein as bl
 from oracle import reference as ref
-from tests.gpu_helpers import max_ulp
+from tests.gpu_helpers import max_ulp, oracle_ffts, oracle_ffts_own_plans
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +51,20 @@ def test_wide_256k_batch8(torch_mod, wide_plan):
     assert ref.rel_l2_error(yb[0], ref.dft_longdouble(x[0])) < 1e-15
 
 
+def test_wide_256k_every_transform_vs_oracle(torch_mod, wide_plan):
+    """Every transform of the headline workload (8 x n = 2^18, |x|
+    log-uniform in [2^-30, 2^30], seed 0) against the oracle, 0 ulp; the
+    oracle runs one transform per process."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    n, B = 1 << 18, 8
+    x = wl.wide_256k(seed=0, batch=B, n=n)
+    y = oz.Plan(n, B).forward(_gpu(torch, x)).cpu().numpy()
+    want = oracle_ffts(list(x), 3, 3, wide_plan)
+    for b in range(B):
+        assert max_ulp(y[b], want[b]) == 0, b
+
+
 def test_wide_256k_single_K6_L1(torch_mod):
     """Single transform at n = 2^18 with K = 6, L = 1 (uncapped for this
     distribution's dynamic range)."""
@@ -68,9 +82,10 @@ def test_wide_256k_single_K6_L1(torch_mod):
 
 def test_mixed_256_one_launch(torch_mod):
     """256 transforms of lengths log-uniform in [2^10, 2^16] (a third prime)
-    in one batched execution: sampled transforms against the oracle, every
-    transform equal to the same transform computed by a plan of its own
-    (for a subset), and the graph replay stable."""
+    in one batched execution: every eighth transform and one per convolution
+    length class against the oracle (over a pool of processes), a subset
+    equal to the same transform computed by a plan of its own, and the graph
+    replay stable."""
     import paper_2603_29129_amd as oz
     torch = torch_mod
     ns, xs = wl.mixed_256(0)
@@ -80,14 +95,14 @@ def test_mixed_256_one_launch(torch_mod):
     y2 = plan.forward(flat).cpu().numpy()
     assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
     offs = np.concatenate([[0], np.cumsum(ns)])
-    # one sample per convolution-length class, smallest n first
+    # every eighth transform and one per convolution-length class
     by_N = {}
     for i, n in enumerate(ns):
         by_N.setdefault(bl.conv_length(n), i)
-    for i in sorted(by_N.values()):
-        n = ns[i]
-        want = bl.fft(xs[i], 3, 3, bl.KernelPlan(n, 3, 3))
-        assert max_ulp(y1[offs[i]:offs[i + 1]], want) == 0, (i, n)
+    sample = sorted(set(range(0, 256, 8)) | set(by_N.values()))
+    wants = oracle_ffts_own_plans([xs[i] for i in sample], 3, 3)
+    for i, want in zip(sample, wants):
+        assert max_ulp(y1[offs[i]:offs[i + 1]], want) == 0, (i, ns[i])
     for i in range(0, 256, 37):
         single = oz.Plan(ns[i], 1).forward(_gpu(torch, xs[i][None, :])).cpu().numpy()[0]
         assert np.array_equal(single.view(np.uint64), y1[offs[i]:offs[i + 1]].view(np.uint64)), i
