@@ -67,6 +67,11 @@ __host__ __device__ constexpr int row_ld(int M) { return pad8(M) + (M >= 512 ? 0
 __host__ __device__ constexpr int pad9(int i) { return i + (i >> 3); }
 template <int PL>
 __host__ __device__ constexpr int padl(int i) { return PL == 9 ? pad9(i) : pad8(i); }
+// Column stride of the column passes' wave-local tiles: each column of
+// N1 = 2^m1 values is a pad9 row; the stride is 8 mod 64 words so that the
+// columns written or read together at one tile position fall on different
+// LDS banks.
+__host__ __device__ constexpr int rec_ldc(int m1) { return pad9(1 << m1) + ((8 - pad9(1 << m1)) & 63); }
 template <int PL>
 __host__ __device__ constexpr int row_ldl(int M) { return PL == 9 ? pad9(M) : row_ld(M); }
 
@@ -426,6 +431,11 @@ __device__ void load_cols(u32* tile, const u32* __restrict__ vec, int m1, int m2
 
 // Forward column pass on vector `vec` (elements >= valid read as zero),
 // written back in place; the twiddle w_N^{j2 k1} is applied by the row pass.
+// With at least 8 columns per tile (one per wave of the COL_THREADS
+// workgroup) the columns are stored as pad9 rows, each wave transforms
+// whole columns with wave-local rounds (no workgroup barrier between the
+// rounds), and the tile is transposed on the way in and out; narrower
+// tiles keep the column layout and workgroup-wide rounds.
 template <int M1>
 __device__ __forceinline__ void fwd_cols_body(u32* vec, int valid, int prime, const NttGeom g, int j2_0, const uint2* twb,
                                               u32* smem) {
@@ -435,6 +445,48 @@ __device__ __forceinline__ void fwd_cols_body(u32* vec, int valid, int prime, co
   uint2* tw = reinterpret_cast<uint2*>(smem);
   u32* tile = smem + (1 << m1);
   load_block_tw(tw, twb, m1);
+  if (lc >= 3 && (1 << lc) >= (int)(blockDim.x >> 6)) {
+    constexpr int LDC = rec_ldc(M1);
+    const int tot4 = 1 << (m1 + lq);
+    for (int q0 = threadIdx.x; q0 < tot4; q0 += blockDim.x * UNR) {
+      uint4 v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * blockDim.x;
+        if (q < tot4) {
+          const int gi = ((q >> lq) << m2) + j2_0 + ((q & ((1 << lq) - 1)) << 2);
+          v[u] = gi < valid ? *reinterpret_cast<const uint4*>(vec + gi) : make_uint4(0, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * blockDim.x;
+        if (q < tot4) {
+          const int i = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+          const uint4 w = zero_from(v[u], (i << m2) + j2_0 + c4, valid);
+          u32* b = tile + c4 * LDC + pad9(i);                // row i of columns c4 .. c4 + 3
+          b[0] = w.x;
+          b[LDC] = w.y;
+          b[2 * LDC] = w.z;
+          b[3 * LDC] = w.w;
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const int cpw = (1 << lc) / (int)(blockDim.x >> 6);   // columns per wave
+      int ln = threadIdx.x & 63;
+      asm volatile("" : "+v"(ln));
+      rounds_t<M1, 0, false, false, 9, true>(tile + (int)(threadIdx.x >> 6) * cpw * LDC, cpw, LDC, tw, p, ln, 64);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < tot4; q += blockDim.x) {
+      const int i = q >> lq, c4 = (q & ((1 << lq) - 1)) << 2;
+      const u32* b = tile + c4 * LDC + pad9(i);
+      *reinterpret_cast<uint4*>(vec + (i << m2) + j2_0 + c4) = make_uint4(b[0], b[LDC], b[2 * LDC], b[3 * LDC]);
+    }
+    return;
+  }
   load_cols(tile, vec, m1, m2, lc, j2_0, valid);
   __syncthreads();
   block_ntt<M1, false, true>(tile, lc, 0, tw, p);
@@ -1542,10 +1594,6 @@ __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, 
 // recombination.
 
 constexpr int REC_THREADS = 1024, REC_OUT = 4;   // 4096-position tiles
-// Column stride of the fused column pass's tiles: each column of N1 = 2^m1
-// values is a pad9 row; the stride is 8 mod 64 words so that the eight
-// columns read together at one tile position fall on different LDS banks.
-__host__ __device__ constexpr int rec_ldc(int m1) { return pad9(1 << m1) + ((8 - pad9(1 << m1)) & 63); }
 // LDS of the fused column pass: the inverse roots of every prime and two
 // buffers of one tile per prime.
 __host__ __device__ constexpr size_t rec_smem_words(int m1, int np) {
@@ -1761,6 +1809,13 @@ NttGeom ntt_geom(int logN, int lc_override, int lrows_override) {
 }
 
 static size_t smem_cols(const NttGeom& g) { return ((size_t)(1 << g.m1) + ((size_t)1 << (g.m1 + g.lc))) * 4; }
+// The forward column pass: column layout, or the wave-local padded-row tile
+// when there are at least as many columns as waves.
+static size_t smem_fwd_cols(const NttGeom& g) {
+  if (g.lc >= 3 && (1 << g.lc) >= COL_THREADS / 64)
+    return ((size_t)(1 << g.m1) + ((size_t)rec_ldc(g.m1) << g.lc)) * 4;
+  return smem_cols(g);
+}
 static size_t smem_inv_cols(const NttGeom& g, int np) {
   return ((size_t)(np << g.m1) + ((size_t)1 << (g.m1 + g.lc))) * 4;
 }
@@ -1849,7 +1904,7 @@ hipError_t launch_ntt_standalone(u32* data, int logN, int prime, int count, bool
     constexpr int M1 = decltype(mc)::value;
     if (!inverse) {
       if ((e = big_lds((const void*)k_std_fwd_cols<M1>)) != hipSuccess) return;
-      hipLaunchKernelGGL(k_std_fwd_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb, ts);
+      hipLaunchKernelGGL(k_std_fwd_cols<M1>, gc, dim3(COL_THREADS), smem_fwd_cols(g), s, data, prime, g, tb, ts);
     } else {
       if ((e = big_lds((const void*)k_std_inv_cols<M1>)) != hipSuccess) return;
       hipLaunchKernelGGL(k_std_inv_cols<M1>, gc, dim3(COL_THREADS), smem_cols(g), s, data, prime, g, tb);
@@ -1908,7 +1963,7 @@ hipError_t launch_fwd_stage(u32* X, const TDesc* td, const TState* ts, const int
   if (which != 2 && !with_m<M1_LO, M1_HI>(g.m1, [&](auto mc) {
         constexpr int M1 = decltype(mc)::value;
         if ((e = big_lds((const void*)k_fwd_cols<M1>)) != hipSuccess) return;
-        const size_t lds = std::max(smem_cols(g), sizeof(int) * 4 * KMAX);
+        const size_t lds = std::max(smem_fwd_cols(g), sizeof(int) * 4 * KMAX);
         hipLaunchKernelGGL(k_fwd_cols<M1>, dim3(1u << (g.m2 - g.lc), ny, count), dim3(COL_THREADS), lds, s, X, td, ts,
                            tlist, K, np, valid_full, vi_lo, g, tb, st, walk);
       }))
