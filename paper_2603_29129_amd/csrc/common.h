@@ -183,7 +183,7 @@ struct TDesc {
   int kd;                  // index into the KernelDesc array
   int zs;                  // row stride of the compact outputs: n rounded up to a multiple of 4
   i64 io_off;              // element offset of this transform in in/out
-  i64 xp_off;              // element offset in the x' buffer (double2)
+  i64 xp_off;              // element offset in the debug copy of x' (double2)
   i64 X_off;               // u32 offset of the slice/NTT buffer [part][k][prime][N]
   i64 G_off;               // u32 offset of the group buffer [slot][prime][N]
   i64 Z_off;               // u32 offset of the compact outputs [slot][prime][zs]

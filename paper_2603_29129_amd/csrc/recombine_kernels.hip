@@ -10,7 +10,8 @@
 // with a minus sign, already applied in the NTT domain).  Each component of
 // y' is then the exact sum of z 2^e over its groups,
 // accumulated in a two's-complement fixed-point integer (4 x 64 bits when the
-// exponents of the transform span <= 185 bits, 50 x 64 bits otherwise) and
+// exponents of the transform span <= 185 bits, 152 with three moduli; 50 x 64
+// bits otherwise) and
 // rounded once to binary64, round to nearest even, subnormals and overflow
 // included.  The chirp postmultiply y = y' (.) w (Sec. 3.2 Step 3) uses the
 // same unfused product rule as the premultiply.
