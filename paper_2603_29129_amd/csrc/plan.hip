@@ -668,9 +668,11 @@ static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, 
     if (g.dir != dir) continue;
     if ((g.in != in || g.out != out) && set_io_node(p, g, in, out) != hipSuccess) {
       // the node could not be updated: capture this direction again below
+      // (the graph may still run from an earlier call on another stream:
+      // wait for the device before destroying it)
       (void)hipGetLastError();
       FO_LOG("graph argument update failed; capturing again");
-      (void)hipStreamSynchronize(s);
+      (void)hipDeviceSynchronize();
       (void)hipGraphExecDestroy(g.exec);
       (void)hipGraphDestroy(g.graph);
       p->graphs.erase(p->graphs.begin() + (long)i);
