@@ -15,7 +15,8 @@ constexpr int COL_THREADS = 512;     // column passes: 2 x 64 KiB tiles per CU, 
 // over log2 N1 resp. log2 N2 bits); for the block case N1 = N, N2 = 1.
 struct NttGeom {
   int logN, m1, m2;      // N1 = 2^m1, N2 = 2^m2
-  int lc;                // log2 of the columns per workgroup (column pass)
+  int lc;                // log2 of the columns per workgroup (forward column pass, standalone passes)
+  int lc_inv;            // log2 of the columns per workgroup (unfused inverse column pass)
   int lrows;             // log2 of the rows per workgroup (forward row pass)
   int lrows_inv;         // log2 of the rows per workgroup (inverse row pass, all groups in LDS)
   bool two_pass() const { return m2 > 0; }

@@ -1549,7 +1549,7 @@ __global__ void __launch_bounds__(COL_THREADS) k_inv_cols(const u32* G, u32* Z, 
   cv.j_hi = min(np * gtot, j_lo + vpw);
   if (j_lo >= cv.j_hi) return;
   constexpr int m1 = M1;
-  const int m2 = g.m2, lc = g.lc, lq = lc - 2, n = d.n;
+  const int m2 = g.m2, lc = g.lc_inv, lq = lc - 2, n = d.n;
   uint2* tw0 = reinterpret_cast<uint2*>(smem);             // roots of every prime, 2^(m1-1) entries each
   u32* tile = smem + (np << m1);
   for (int q = 0; q < np; ++q) load_block_tw(tw0 + (q << (m1 - 1)), tb.inv[q], m1);
@@ -1783,16 +1783,22 @@ NttGeom ntt_geom(int logN, int lc_override, int lrows_override) {
     g.m1 = logN;
     g.m2 = 0;
     g.lc = 0;
+    g.lc_inv = 0;
     g.lrows = 0;
     return g;
   }
   g.m2 = logN / 2;
   g.m1 = logN - g.m2;
   // column tile: C * N1 words <= 16K words (64 KiB), 4 <= C <= 16 columns
-  // (16 columns measured faster than 32 for N1 = 512: more workgroups)
+  // (16 columns measured faster than 32 for N1 = 512: more workgroups); from
+  // N1 = 1024 on the forward pass takes 8 columns (16 padded columns of 1024
+  // allow two workgroups per CU; 8 columns measured faster there), the
+  // unfused inverse pass keeps 16 (8 measured slower)
   int lc = 4;
   while (lc > 2 && (g.m1 + lc) > 14) --lc;
   if (lc > g.m2) lc = g.m2;
+  g.lc_inv = lc;
+  if (g.m1 >= 10 && lc > 3) lc = 3;
   // row tile: 4096 words per workgroup
   int lr = LOG2_BLOCK_MAX - g.m2;
   if (lr < 0) lr = 0;
@@ -1817,7 +1823,7 @@ static size_t smem_fwd_cols(const NttGeom& g) {
   return smem_cols(g);
 }
 static size_t smem_inv_cols(const NttGeom& g, int np) {
-  return ((size_t)(np << g.m1) + ((size_t)1 << (g.m1 + g.lc))) * 4;
+  return ((size_t)(np << g.m1) + ((size_t)1 << (g.m1 + g.lc_inv))) * 4;
 }
 static size_t smem_rows(const NttGeom& g) {
   return ((size_t)(1 << g.m2) + ((size_t)row_ld(1 << g.m2) << g.lrows) + rowtw_words(g.m2, 1 << g.lrows)) * 4;
@@ -2062,9 +2068,9 @@ hipError_t launch_inv_stage(const u32* X, u32* G, u32* Z, const TDesc* td, const
   }
   if (which != 1) {
     // the staged next tile must fit COL_PF 16-byte registers per thread
-    if (g.m1 + g.lc > 14) return hipErrorInvalidValue;
+    if (g.m1 + g.lc_inv > 14) return hipErrorInvalidValue;
     const int vecs = 4 * K * K * np, vpw = 4;    // group vectors (at most 4 K^2 groups, np primes)
-    const dim3 grid(1u << (g.m2 - g.lc), (vecs + vpw - 1) / vpw, count);
+    const dim3 grid(1u << (g.m2 - g.lc_inv), (vecs + vpw - 1) / vpw, count);
     if (!with_m<M1_LO, M1_HI>(g.m1, [&](auto mc) {
           constexpr int M1 = decltype(mc)::value;
           if ((e = big_lds((const void*)k_inv_cols<M1>)) != hipSuccess) return;
