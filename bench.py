@@ -250,7 +250,7 @@ def cpu_baseline(xs, n, budget_s, max_procs=16):
             "host": host}
 
 
-def events_ms(torch, fn, reps, warmup=3):
+def events_ms(torch, fn, reps, warmup=20):
     """Device time per call of fn() between HIP events on torch's current
     stream (the stream the library launches on), after warmup calls."""
     for _ in range(warmup):
@@ -389,8 +389,10 @@ def config_per_conv(np, torch, oz, xd, out_ref, reps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    # about 0.1 s of timed steps after 50 ms of warmup: with 20 steps the
+    # timed window (10 ms) still held the GPU's clock ramp (5-7% slower)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=1 << 18)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--plain-steps", type=int, default=3)
@@ -402,7 +404,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other configurations (n = 2^10, 64 x 2^14, 64 x 10007, 256 mixed lengths, "
                          "32 x 2^16 forward + backward)")
-    ap.add_argument("--config-reps", type=int, default=20)
+    ap.add_argument("--config-reps", type=int, default=100)
     ap.add_argument("--only-config", default=None,
                     choices=["plain_1k", "batch_16k", "batch_prime", "mixed_256", "grad_64k"],
                     help="run only this configuration and print its figures (for profiling)")
