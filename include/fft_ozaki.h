@@ -239,6 +239,30 @@ int fft_ozaki_debug_dump(fft_ozaki_plan_t plan, int stage, int64_t index, void* 
  * afterwards are not those of the last execution.  Batched plans only. */
 int fft_ozaki_profile_stage(fft_ozaki_plan_t plan, int stage, int reps, void* stream);
 
+/* Measurement hook: with enable != 0 every later batched execution of the
+ * plan launches its kernels on `stream` itself, in the order of the captured
+ * graph, with a HIP event recorded at each stage boundary (HIP records no
+ * timestamps from inside a graph replay), so the device time of each stage
+ * is taken where it runs, between its neighbours in the schedule and with
+ * their data in the caches; enable = 0 returns to graph replays.  Batched
+ * plans only; FFT_OZAKI_ERR_INVALID otherwise. */
+int fft_ozaki_stage_timing(fft_ozaki_plan_t plan, int enable);
+
+/* Device times in ms of the stages of the plan's last execution, which must
+ * have run with stage timing on (FFT_OZAKI_ERR_INVALID otherwise); waits for
+ * it to finish.  ms[0]: premultiply and split (from the state reset through
+ * the last check); then for each length class c (the transforms of one
+ * convolution length N; classes in the order in which their N first occurs
+ * among the plan's transforms): ms[1 + 4c] forward NTTs
+ * (with the folded row pass: the forward column pass), ms[2 + 4c] inverse
+ * row pass (with the NTT-domain multiply-accumulate and the folded forward
+ * rows; for N <= 4096 the whole inverse NTT), ms[3 + 4c] inverse column pass
+ * (fused with the CRT, recombination and postmultiply where N1 <= 512),
+ * ms[4 + 4c] the recombination launch (the wide-accumulator fallback where
+ * fused).  *count (if not NULL) receives 1 + 4 x (length classes); an array
+ * shorter than that (capacity) is FFT_OZAKI_ERR_INVALID. */
+int fft_ozaki_stage_times(fft_ozaki_plan_t plan, float* ms, int capacity, int* count);
+
 /* Release the plan and its device memory. */
 int fft_ozaki_destroy(fft_ozaki_plan_t plan);
 

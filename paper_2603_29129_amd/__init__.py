@@ -90,6 +90,8 @@ def lib():
                     "fft_ozaki_debug_dump": ([vp, ci, i64, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ci),
                     "fft_ozaki_destroy": ([vp], ci),
                     "fft_ozaki_profile_stage": ([vp, ci, ci, vp], ci),
+                    "fft_ozaki_stage_timing": ([vp, ci], ci),
+                    "fft_ozaki_stage_times": ([vp, ctypes.POINTER(ctypes.c_float), ci, ctypes.POINTER(ci)], ci),
                     "fft_ozaki_error_string": ([ci], ctypes.c_char_p),
                     "fft_ozaki_last_error_message": ([], ctypes.c_char_p),
                     "fft_ozaki_ntt": ([ci, ci, i64, vp, ci, vp], ci),
@@ -202,6 +204,25 @@ class Plan:
         import torch
         s = stream if stream is not None else _stream_handle(torch, torch.cuda.current_device())
         _check(lib().fft_ozaki_profile_stage(self._h, int(stage), int(reps), ctypes.c_void_p(s)))
+
+    def stage_timing(self, enable: bool = True):
+        """Launch later batched executions on the stream in the graph's order
+        with a HIP event at each stage boundary (see fft_ozaki_stage_timing);
+        False returns to graph replays."""
+        _check(lib().fft_ozaki_stage_timing(self._h, int(bool(enable))))
+
+    def stage_times(self) -> dict:
+        """Device ms of the stages of the last execution (see
+        fft_ozaki_stage_times): {"split": t, "classes": [{"forward", "rows",
+        "cols", "recombine"} per length class]}."""
+        n = ctypes.c_int(0)
+        lib().fft_ozaki_stage_times(self._h, None, 0, ctypes.byref(n))
+        buf = (ctypes.c_float * n.value)()
+        _check(lib().fft_ozaki_stage_times(self._h, buf, n.value, ctypes.byref(n)))
+        v = list(buf)
+        keys = ("forward", "rows", "cols", "recombine")
+        return {"split": v[0],
+                "classes": [dict(zip(keys, v[1 + 4 * c: 5 + 4 * c])) for c in range((n.value - 1) // 4)]}
 
     def info(self) -> dict:
         i = _Info()

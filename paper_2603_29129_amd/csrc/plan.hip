@@ -177,6 +177,12 @@ struct fft_ozaki_plan_s {
   fo::i64 bytes = 0;
   hipStream_t cap = nullptr;
   std::vector<fo::GraphEntry> graphs;
+  // stage timing: HIP events at the stage boundaries of the batched
+  // sequence, 2 + 4 (length classes); such executions launch the sequence
+  // on the caller's stream instead of replaying the graph
+  bool stage_timing = false;
+  std::vector<hipEvent_t> tev;
+  bool timed_last = false;          // the last execution recorded them
   const void* last_in = nullptr;
   void* last_out = nullptr;
   int last_dir = -1;
@@ -229,6 +235,7 @@ static void destroy_plan(fft_ozaki_plan_s* p) {
     (void)hipGraphExecDestroy(g.exec);
     (void)hipGraphDestroy(g.graph);
   }
+  for (hipEvent_t e : p->tev) (void)hipEventDestroy(e);
   if (p->cap) (void)hipStreamDestroy(p->cap);
   for (void* a : p->allocs) (void)hipFree(a);
   (void)hipSetDevice(cur);
@@ -596,8 +603,18 @@ static inline int io32_of(const fft_ozaki_plan_s* p) { return p->precision == FF
 
 // The batched launch sequence (also what gets captured into the graph), for
 // two or three moduli alike.
+// Stage boundary i of the batched sequence (stage timing only): 0 start,
+// 1 after the split, 2 + c after class c's forward NTTs, 2 + C + 3c (+1, +2)
+// after its inverse row pass (column pass, recombination).
+// Stage-timed executions are not captured (see fft_ozaki_stage_timing).
+static hipError_t mark(fft_ozaki_plan_s* p, size_t i, hipStream_t s) {
+  return p->stage_timing ? hipEventRecord(p->tev[i], s) : hipSuccess;
+}
+
 static int enqueue_batched(fft_ozaki_plan_s* p, int dir, hipStream_t s, const void* in, void* out) {
   const int K = p->K, np = p->primes, count = (int)p->td.size();
+  const size_t C = p->classes.size();
+  HIPCHK(mark(p, 0, s));
   HIPCHK(launch_reset_io(p->d_ts, p->d_tall, count, p->d_io, in, out, s));
   for (auto& lc : p->classes)
     HIPCHK(launch_premul(p->d_io, nullptr, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir,
@@ -609,32 +626,42 @@ static int enqueue_batched(fft_ozaki_plan_s* p, int dir, hipStream_t s, const vo
                                   dir, false, io32_of(p), np, s));
     HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
   }
-  for (auto& lc : p->classes) {
+  HIPCHK(mark(p, 1, s));
+  for (size_t c = 0; c < C; ++c) {
     // forward NTTs; where the forward row pass is folded into the inverse
     // row pass, only the column pass here.  The accumulation schedule of the
     // class's transforms is computed inside the same launch.
+    auto& lc = p->classes[c];
     const int which = fused_rows_ok(lc.geom, K) ? 1 : 0;
     HIPCHK(launch_fwd_stage(p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), K, np, false, 0, 2 * np * K,
                             lc.geom, p->tb, step_for(p, lc.logN), which, s, p->d_ts, p->d_kd, p->L));
+    HIPCHK(mark(p, 2 + c, s));
   }
-  for (auto& lc : p->classes) {
+  for (size_t c = 0; c < C; ++c) {
+    auto& lc = p->classes[c];
     const int cnt = (int)lc.tids.size();
+    const size_t b = 2 + C + 3 * c;
+    // rows (with the forward rows where possible)
+    HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, np, 0, 4 * K * K, lc.geom,
+                            p->tb, step_for(p, lc.logN), 1, s, fused_rows_ok(lc.geom, K)));
+    HIPCHK(mark(p, b, s));
     if (fused_cols_ok(lc.geom)) {
-      // rows (with the forward rows where possible); fused columns + CRT +
-      // recombination (for transforms that need the wide accumulator: the
-      // columns to the compact buffer, then the wide recombination)
-      HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, np, 0, 4 * K * K,
-                              lc.geom, p->tb, step_for(p, lc.logN), 1, s, fused_rows_ok(lc.geom, K)));
+      // fused columns + CRT + recombination (for transforms that need the
+      // wide accumulator: the columns to the compact buffer, then the wide
+      // recombination)
       HIPCHK(launch_inv_cols_rec(p->G, p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, np, lc.geom, p->tb,
                                  dir, io32_of(p), s));
+      HIPCHK(mark(p, b + 1, s));
       HIPCHK(launch_recombine_wide(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir,
                                    io32_of(p), s, np));
     } else {
       HIPCHK(launch_inv_stage(p->X, p->G, p->Z, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, K, np, 0, 4 * K * K,
-                              lc.geom, p->tb, step_for(p, lc.logN), 0, s, fused_rows_ok(lc.geom, K)));
+                              lc.geom, p->tb, step_for(p, lc.logN), 2, s, fused_rows_ok(lc.geom, K)));
+      HIPCHK(mark(p, b + 1, s));
       HIPCHK(launch_recombine(p->Z, p->d_io, p->d_td, p->d_ts, p->d_kd, lc.d_tlist, cnt, lc.nmax, K, dir, io32_of(p), s,
                               np));
     }
+    HIPCHK(mark(p, b + 2, s));
   }
   return FFT_OZAKI_OK;
 }
@@ -663,6 +690,9 @@ static hipError_t set_io_node(fft_ozaki_plan_s* p, GraphEntry& g, const void* in
 static int run_batched(fft_ozaki_plan_s* p, const void* in, void* out, int dir, hipStream_t s) {
   for (auto& lc : p->classes)
     if (fused_rows_ok(lc.geom, p->K)) p->x_rows_pending = true;
+  // stage timing: the same launches in the same order, with the boundary
+  // events, directly on the caller's stream
+  if (p->stage_timing) return enqueue_batched(p, dir, s, in, out);
   for (size_t i = 0; i < p->graphs.size(); ++i) {
     GraphEntry& g = p->graphs[i];
     if (g.dir != dir) continue;
@@ -1011,6 +1041,7 @@ int fft_ozaki_execute(fft_ozaki_plan_t plan, const void* in, void* out, int dire
   Range range(plan->mode == FFT_OZAKI_MODE_PLAIN ? "fft_ozaki_execute (plain)" : "fft_ozaki_execute (batched)");
   int rc = plan->mode == FFT_OZAKI_MODE_PLAIN ? run_plain(plan, in, out, direction, s)
                                               : run_batched(plan, in, out, direction, s);
+  plan->timed_last = rc == FFT_OZAKI_OK && plan->stage_timing && plan->mode == FFT_OZAKI_MODE_BATCHED;
   if (cur != plan->device) (void)hipSetDevice(cur);
   return rc;
 }
@@ -1165,6 +1196,52 @@ int fft_ozaki_profile_stage(fft_ozaki_plan_t plan, int stage, int reps, void* st
     int rc = enqueue_stage(plan, stage, (hipStream_t)stream);
     if (rc) return rc;
   }
+  return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_stage_timing(fft_ozaki_plan_t plan, int enable) {
+  g_err.clear();
+  if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
+  if (plan->mode != FFT_OZAKI_MODE_BATCHED) return fail(FFT_OZAKI_ERR_INVALID, "stage timing needs the batched mode");
+  const bool on = enable != 0;
+  if (on == plan->stage_timing) return FFT_OZAKI_OK;
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != plan->device) HIPCHK(hipSetDevice(plan->device));
+  const size_t need = 2 + 4 * plan->classes.size();
+  while (on && plan->tev.size() < need) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    plan->tev.push_back(e);
+  }
+  plan->stage_timing = on;
+  plan->timed_last = false;
+  if (cur != plan->device) (void)hipSetDevice(cur);
+  return FFT_OZAKI_OK;
+}
+
+int fft_ozaki_stage_times(fft_ozaki_plan_t plan, float* ms, int capacity, int* count) {
+  g_err.clear();
+  if (!plan) return fail(FFT_OZAKI_ERR_INVALID, "plan is NULL");
+  const int C = (int)plan->classes.size(), n = 1 + 4 * C;
+  if (count) *count = n;
+  if (!ms || capacity < n) return fail(FFT_OZAKI_ERR_INVALID, "times array too small (" + std::to_string(n) + " needed)");
+  if (!plan->timed_last) return fail(FFT_OZAKI_ERR_INVALID, "the last execution recorded no stage times");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != plan->device) HIPCHK(hipSetDevice(plan->device));
+  const std::vector<hipEvent_t>& e = plan->tev;
+  HIPCHK(hipEventSynchronize(e[1 + 4 * (size_t)C]));
+  auto span = [&](size_t a, size_t b, float* out) { return hipEventElapsedTime(out, e[a], e[b]); };
+  HIPCHK(span(0, 1, &ms[0]));
+  for (int c = 0; c < C; ++c) {
+    const size_t f = 2 + c, r = 2 + C + 3 * (size_t)c;
+    HIPCHK(span(c == 0 ? 1 : f - 1, f, &ms[1 + 4 * c]));                    // forward NTTs
+    HIPCHK(span(c == 0 ? 1 + (size_t)C : r - 1, r, &ms[1 + 4 * c + 1]));   // inverse row pass
+    HIPCHK(span(r, r + 1, &ms[1 + 4 * c + 2]));                           // inverse column pass
+    HIPCHK(span(r + 1, r + 2, &ms[1 + 4 * c + 3]));                       // recombination
+  }
+  if (cur != plan->device) (void)hipSetDevice(cur);
   return FFT_OZAKI_OK;
 }
 

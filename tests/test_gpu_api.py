@@ -187,3 +187,46 @@ def test_rotating_buffers_reuse_the_graph(torch_mod):
             plan.execute(xs[i], d, out=outs[i])
             want = ref.execute(xs[i], d)
             assert torch.equal(outs[i].view(torch.float64), want.view(torch.float64)), (rnd, i)
+
+
+def test_stage_timing_in_the_graph(torch_mod):
+    """Stage timing (the batched launches on the stream with HIP events at
+    the stage boundaries): the outputs keep the graph replay's bits, every
+    stage of every length class gets a nonnegative device time, and the times
+    add up to no more than the execution's own device time; switched off,
+    the plan replays its graph again.  Three length classes: a fused
+    two-pass length (N = 2^14), a single-block length (N = 2^11 for
+    n = 1000) and an unfused two-pass length (N = 2^20: N1 = 1024)."""
+    import paper_2603_29129_amd as oz
+    torch = torch_mod
+    lengths = [1 << 14, 1000, (1 << 19) - 1, 1 << 14]
+    x = torch.from_numpy(np.concatenate([wl.uniform(n, batch=1, seed=60 + i).ravel()
+                                         for i, n in enumerate(lengths)])).cuda()
+    plan = oz.Plan(lengths=lengths)
+    ref = plan.forward(x)
+    with pytest.raises(oz.FftOzakiError, match="no stage times"):
+        plan.stage_times()
+    plan.stage_timing(True)
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for rep in range(3):
+        a.record(s)
+        y = plan.forward(x)
+        b.record(s)
+        torch.cuda.synchronize()
+        assert torch.equal(y.view(torch.float64), ref.view(torch.float64)), rep
+        t = plan.stage_times()
+        assert len(t["classes"]) == 3
+        vals = [t["split"]] + [v for c in t["classes"] for v in c.values()]
+        assert all(v >= 0 for v in vals), t
+        assert t["split"] > 0 and all(c["forward"] > 0 and c["rows"] > 0 for c in t["classes"]), t
+        assert sum(vals) <= a.elapsed_time(b) * 1.05 + 0.01, (t, a.elapsed_time(b))
+    # the single-block class has no separate column pass
+    assert t["classes"][1]["cols"] < 0.01, t
+    plan.stage_timing(False)
+    y = plan.forward(x)
+    assert torch.equal(y.view(torch.float64), ref.view(torch.float64))
+    with pytest.raises(oz.FftOzakiError, match="no stage times"):
+        plan.stage_times()
+    with pytest.raises(oz.FftOzakiError):
+        oz.Plan(1000, 1, mode="plain").stage_timing(True)
