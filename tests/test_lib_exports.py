@@ -70,6 +70,9 @@ def test_host_only_calls():
     assert d.accumulation == oz.ACCUM_COMPLEX and d.primes == 2
     assert L.fft_ozaki_execute(None, None, None, 0, None) == -1
     assert L.fft_ozaki_destroy(None) == -1
+    assert L.fft_ozaki_stage_timing(None, 1) == -1
+    n = ctypes.c_int(-7)
+    assert L.fft_ozaki_stage_times(None, None, 0, ctypes.byref(n)) == -1 and n.value == -7
     m = ctypes.c_int()
     assert L.fft_ozaki_ntt_layout(19, ctypes.byref(m)) == 0 and m.value == 10
     assert L.fft_ozaki_ntt_layout(12, ctypes.byref(m)) == 0 and m.value == 12
