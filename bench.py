@@ -107,14 +107,17 @@ def algorithmic_ops(infos):
 
 
 def source_digest():
-    """SHA-256 of the kernel sources: every .h and every .hip file under csrc
-    except the host-only plan layer (plan.hip holds no device code)."""
+    """SHA-256 of the kernel sources and their compile flags: every .h and
+    every .hip file under csrc except the host-only plan layer (plan.hip
+    holds no device code), and the flags build_lib compiles them with."""
     import hashlib
+    from paper_2603_29129_amd import build_lib
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
         if f.endswith((".hip", ".h")) and f != "plan.hip":
             with open(os.path.join(CSRC, f), "rb") as fh:
                 h.update(f.encode() + b"\0" + fh.read())
+            h.update(" ".join(build_lib.FLAGS + build_lib.SOURCE_FLAGS.get(f, [])).encode() + b"\0")
     return h.hexdigest()
 
 
