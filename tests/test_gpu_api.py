@@ -189,20 +189,22 @@ def test_rotating_buffers_reuse_the_graph(torch_mod):
             assert torch.equal(outs[i].view(torch.float64), want.view(torch.float64)), (rnd, i)
 
 
-def test_stage_timing_in_the_graph(torch_mod):
+@pytest.mark.parametrize("primes", [2, 3])
+def test_stage_timing_in_the_graph(torch_mod, primes):
     """Stage timing (the batched launches on the stream with HIP events at
     the stage boundaries): the outputs keep the graph replay's bits, every
     stage of every length class gets a nonnegative device time, and the times
     add up to no more than the execution's own device time; switched off,
     the plan replays its graph again.  Three length classes: a fused
     two-pass length (N = 2^14), a single-block length (N = 2^11 for
-    n = 1000) and an unfused two-pass length (N = 2^20: N1 = 1024)."""
+    n = 1000) and an unfused two-pass length (N = 2^20: N1 = 1024); two and
+    three moduli."""
     import paper_2603_29129_amd as oz
     torch = torch_mod
     lengths = [1 << 14, 1000, (1 << 19) - 1, 1 << 14]
     x = torch.from_numpy(np.concatenate([wl.uniform(n, batch=1, seed=60 + i).ravel()
                                          for i, n in enumerate(lengths)])).cuda()
-    plan = oz.Plan(lengths=lengths)
+    plan = oz.Plan(lengths=lengths, primes=primes)
     ref = plan.forward(x)
     with pytest.raises(oz.FftOzakiError, match="no stage times"):
         plan.stage_times()
