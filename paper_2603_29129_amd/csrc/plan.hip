@@ -616,14 +616,16 @@ static int enqueue_batched(fft_ozaki_plan_s* p, int dir, hipStream_t s, const vo
   const size_t C = p->classes.size();
   HIPCHK(mark(p, 0, s));
   HIPCHK(launch_reset_io(p->d_ts, p->d_tall, count, p->d_io, in, out, s));
-  for (auto& lc : p->classes)
-    HIPCHK(launch_premul(p->d_io, nullptr, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir,
-                         false, io32_of(p), s));
+  // the premultiply and the extraction passes: one launch each over all
+  // transforms (each workgroup stops at its transform's length), so the
+  // length classes' work overlaps
+  int nmax = 0;
+  for (auto& lc : p->classes) nmax = std::max(nmax, lc.nmax);
+  HIPCHK(launch_premul(p->d_io, nullptr, p->d_td, p->d_kd, p->d_ts, p->d_tall, count, nmax, dir, false, io32_of(p), s));
   HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
   for (int r = 0; r < K; ++r) {
-    for (auto& lc : p->classes)
-      HIPCHK(launch_split_extract(p->d_io, p->d_kd, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, K,
-                                  dir, false, io32_of(p), np, s));
+    HIPCHK(launch_split_extract(p->d_io, p->d_kd, p->X, p->d_td, p->d_ts, p->d_tall, count, nmax, K, dir, false,
+                                io32_of(p), np, s));
     HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
   }
   HIPCHK(mark(p, 1, s));
@@ -817,18 +819,20 @@ static int enqueue_stage(fft_ozaki_plan_s* p, int stage, hipStream_t s) {
   const int dir = p->last_dir;
   switch (stage) {
     case 1:   // split: premultiply, maxima and the K extraction/check passes
+    {
       HIPCHK(launch_reset_io(p->d_ts, p->d_tall, count, nullptr, nullptr, nullptr, s));
-      for (auto& lc : p->classes)
-        HIPCHK(launch_premul(p->d_io, nullptr, p->d_td, p->d_kd, p->d_ts, lc.d_tlist, (int)lc.tids.size(), lc.nmax, dir,
-                             false, io32_of(p), s));
+      int nmax = 0;
+      for (auto& lc : p->classes) nmax = std::max(nmax, lc.nmax);
+      HIPCHK(launch_premul(p->d_io, nullptr, p->d_td, p->d_kd, p->d_ts, p->d_tall, count, nmax, dir, false,
+                           io32_of(p), s));
       HIPCHK(launch_split_plan(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, s));
       for (int r = 0; r < K; ++r) {
-        for (auto& lc : p->classes)
-          HIPCHK(launch_split_extract(p->d_io, p->d_kd, p->X, p->d_td, p->d_ts, lc.d_tlist, (int)lc.tids.size(),
-                                      lc.nmax, K, dir, false, io32_of(p), np, s));
+        HIPCHK(launch_split_extract(p->d_io, p->d_kd, p->X, p->d_td, p->d_ts, p->d_tall, count, nmax, K, dir, false,
+                                    io32_of(p), np, s));
         HIPCHK(launch_split_check(p->d_td, p->d_ts, p->d_tall, count, K, s));
       }
       return FFT_OZAKI_OK;
+    }
     case 2:
       HIPCHK(launch_groups(p->d_td, p->d_ts, p->d_kd, p->d_tall, count, K, p->L, s));
       return FFT_OZAKI_OK;
